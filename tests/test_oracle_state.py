@@ -1,0 +1,297 @@
+"""Pins of the oracle's binary32 state path (no GPU).
+
+Covers the steps of Alg. 1 other than fitness: initialisation, explosion sparks
+and their random mapping, multi-guiding sparks, selection with the dynamic
+amplitude, the loser-out tournament and the best-so-far.  Pins: hand-worked
+golden tables, brute-force ranking, exact special cases (all-tie, k = 1,
+unit amplitude), statistics of the draws, and invariants of the whole run.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2501_03944_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _f(v):
+    return np.float32(math.inf) if v == "inf" else np.float32(v)
+
+
+# ----------------------------------------------------------------- init & explosion
+def test_init_positions_uniform_in_box():
+    cfg = O.make_config(lb=-3.0, ub=7.0)
+    x = np.concatenate([O.init_row(cfg, 4000, row, 0) for row in range(5)])
+    assert x.min() >= -3.0 and x.max() <= 7.0
+    assert abs(x.mean() - 2.0) < 0.1
+    assert abs(x.var() - 100.0 / 12.0) < 0.25
+    # rows and streams are distinct
+    assert not np.array_equal(O.init_row(cfg, 64, 0, 0), O.init_row(cfg, 64, 1, 0))
+    assert not np.array_equal(O.init_row(cfg, 64, 0, 0), O.init_row(cfg, 64, 0, 0, "reinit"))
+
+
+def test_explosion_unit_amplitude_lands_on_2pow23_grid():
+    # x = 0, A = 1: s = 2u - 1 exactly, so s * 2^23 is an integer in [-2^23, 2^23)
+    cfg = O.make_config()
+    s = O.explosion_row(cfg, np.zeros(5000, np.float32), 1.0, row=3, t=1)
+    k = s.astype(np.float64) * 2.0 ** 23
+    assert np.all(k == np.round(k))
+    assert k.min() >= -2 ** 23 and k.max() < 2 ** 23
+
+
+def test_explosion_statistics_interior():
+    # an interior firework with small amplitude never needs mapping:
+    # (s - x) / A is uniform on [-1, 1): mean 0, variance 1/3
+    cfg = O.make_config()
+    rng = np.random.default_rng(0)
+    x = rng.uniform(-1, 1, 20000).astype(np.float32)
+    A = np.float32(0.5)
+    s = O.explosion_row(cfg, x, A, row=11, t=7)
+    z = (s.astype(np.float64) - x) / float(A)
+    assert z.min() >= -1.0 - 1e-6 and z.max() < 1.0 + 1e-6
+    assert abs(z.mean()) < 0.02
+    assert abs(z.var() - 1.0 / 3.0) < 0.02
+
+
+def test_explosion_mapping_keeps_box_and_is_uniform():
+    # A = 100 in [-5, 5]: nearly every coordinate leaves the box and is mapped uniformly
+    cfg = O.make_config()
+    x = np.full(20000, 4.9, np.float32)
+    s = O.explosion_row(cfg, x, 100.0, row=0, t=1)
+    assert s.min() >= -5.0 and s.max() <= 5.0
+    assert abs(s.mean()) < 0.15
+    assert abs(s.var() - 100.0 / 12.0) < 0.4
+
+
+def test_explosion_depends_on_generation_and_row():
+    cfg = O.make_config()
+    x = np.zeros(64, np.float32)
+    a = O.explosion_row(cfg, x, 1.0, 0, 1)
+    assert not np.array_equal(a, O.explosion_row(cfg, x, 1.0, 0, 2))
+    assert not np.array_equal(a, O.explosion_row(cfg, x, 1.0, 1, 1))
+    assert np.array_equal(a, O.explosion_row(cfg, x, 1.0, 0, 1))
+
+
+# ----------------------------------------------------------------- guiding
+def test_guiding_golden_cases():
+    with open(os.path.join(GOLDEN, "guiding_groups.json")) as fh:
+        g = json.load(fh)
+    for c in g["cases"]:
+        y = np.array([_f(v) for v in c["fitness"]], np.float32)
+        top, bot, tie, gs = O.guide_group(c["sparks"], y, c["x"], c["k"], c["boost"])
+        assert top.tolist() == c["top"], c["name"]
+        assert bot.tolist() == c["bottom"], c["name"]
+        assert tie == c["tie"], c["name"]
+        assert gs.tolist() == [float(np.float32(v)) for v in c["gs"]], c["name"]
+
+
+def _rank_sets(y, k):
+    """Brute force: sort (value with NaN as +inf, index) and cut."""
+    key = np.where(np.isnan(y), np.inf, y)
+    order = sorted(range(len(y)), key=lambda j: (key[j], j))
+    return sorted(order[:k]), sorted(order[-k:])
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_ranking_matches_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    m = int(rng.integers(2, 40))
+    k = max(1, int(math.floor(0.2 * m))) if seed % 2 else max(1, m // 2)
+    # many ties, signed zeros and infinities
+    pool = np.array([0.0, -0.0, 1.0, 2.5, -3.0, np.inf, 1e-30, -1e-30], np.float32)
+    y = pool[rng.integers(0, len(pool), m)] if seed % 3 else rng.standard_normal(m).astype(np.float32)
+    sparks = rng.standard_normal((m, 3)).astype(np.float32)
+    top, bot, tie, _ = O.guide_group(sparks, y, np.zeros(3, np.float32), k)
+    bt, bb = _rank_sets(y, k)
+    assert top.tolist() == bt and bot.tolist() == bb
+    assert tie == int(y.min() == y.max())
+
+
+def test_guiding_linear_objective_points_downhill():
+    # f(x) = c.x: the top sparks have smaller c.s, so c.delta < 0 for every group
+    rng = np.random.default_rng(3)
+    D = 40
+    c = rng.standard_normal(D)
+    for trial in range(20):
+        m = 20
+        x = rng.uniform(-1, 1, D).astype(np.float32)
+        sparks = (x + rng.uniform(-0.5, 0.5, (m, D))).astype(np.float32)
+        y = (sparks.astype(np.float64) @ c).astype(np.float32)
+        k = max(1, int(0.2 * m))
+        _, _, tie, gs = O.guide_group(sparks, y, x, k)
+        assert tie == 0
+        delta = gs.astype(np.float64) - x
+        assert float(c @ delta) < 0.0
+
+
+def test_all_tie_group_gives_zero_delta_through_state():
+    # every spark with equal fitness: every guiding spark equals its firework exactly
+    wl = inputs.random_mlp_problem((3, 2), (), "mse", 4, seed=0)
+    p = O.Problem(wl.widths, wl.acts, "mse")
+    o = O.Oracle(p, N=3, lam=8, G=2, T=10, seed=5)
+    o.init_positions()
+    o.tell_init(np.ones(3, np.float32))
+    o.explode()
+    o.tell_explosion(np.full(24, 2.0, np.float32))
+    o.guide()
+    v = o.view()
+    assert np.all(v["tie"] == 1)
+    for gf in range(3):
+        for g in range(2):
+            assert np.array_equal(v["SG"][gf * 2 + g], v["F"][gf])
+
+
+# ----------------------------------------------------------------- selection & loser-out
+def _tell_gen(o, gen, N, lam, G):
+    o.explode()
+    o.tell_explosion(np.array([[_f(v) for v in r] for r in gen["explosion"]], np.float32).reshape(-1))
+    o.guide()
+    o.tell_guiding(np.array([[_f(v) for v in r] for r in gen["guiding"]], np.float32).reshape(-1))
+    o.select()
+
+
+@pytest.mark.parametrize("B", [1, 3])
+def test_loser_out_golden_scenarios(B):
+    with open(os.path.join(GOLDEN, "loser_out_scenarios.json")) as fh:
+        sc = json.load(fh)
+    for s in sc["scenarios"]:
+        N, lam, G = s["N"], s["lam"], s["G"]
+        dim = 6
+        p = O.Problem((2, 2), (), "mse")   # dimension 6; fitness is told
+        o = O.Oracle(p, B=B, N=N, lam=lam, G=G, sigma=s["sigma"], T=s["T"], seed=17)
+        o.init_positions()
+        o.tell_init(np.tile(np.array(s["init"], np.float32), B))
+        prevA = o.view()["A"]
+        for gi, gen in enumerate(s["generations"]):
+            tiled = dict(explosion=gen["explosion"] * B, guiding=gen["guiding"] * B)
+            before = o.view()
+            _tell_gen(o, tiled, N, lam, G)
+            v = o.view()
+            for b in range(B):
+                sl = slice(b * N, (b + 1) * N)
+                name = f'{s["name"]} gen {gi + 1} pop {b}'
+                assert v["cstar"][sl].tolist() == gen["cstar"], name
+                assert v["improved"][sl].tolist() == gen["improved"], name
+                assert v["reinit"][sl].tolist() == gen["reinit"], name
+                assert v["fresh"][sl].tolist() == gen["fresh"], name
+                assert v["Y"][sl].tolist() == [float(_f(y)) for y in gen["Y"]], name
+                assert float(v["best_y"][b]) == float(_f(gen["best_y"])), name
+                assert int(v["best_f"][b]) == gen["best_f"], name
+                assert int(v["best_gen"][b]) == gen["best_gen"], name
+                # amplitude: reset to A0 on re-initialisation, else one binary32 product
+                a0 = np.float32(o.cfg.ub) - np.float32(o.cfg.lb)
+                for f in range(N):
+                    gf = b * N + f
+                    if gen["A_reset"][f]:
+                        assert v["A"][gf] == a0
+                    else:
+                        fac = np.float32(1.2) if gen["improved"][f] else np.float32(0.9)
+                        assert v["A"][gf] == np.float32(prevA[gf] * fac), name
+                    if gen["reinit"][f]:
+                        # re-initialised rows are fresh uniform draws, in the box
+                        assert not np.array_equal(v["F"][gf], before["F"][gf])
+                        assert v["F"][gf].min() >= -5 and v["F"][gf].max() <= 5
+            prevA = v["A"]
+            assert v["t"] == gi + 1
+            assert v["best_x"].shape == (B, dim)
+
+
+def test_loser_out_disabled_never_reinitialises():
+    p = O.Problem((2, 2), (), "mse")
+    o = O.Oracle(p, N=3, lam=2, G=1, sigma=0.5, T=2, seed=1, loser_out=0)
+    o.init_positions()
+    o.tell_init(np.array([4.0, 2.0, 6.0], np.float32))
+    for _ in range(3):
+        o.explode()
+        o.tell_explosion(np.array([9, 9, 9, 9, 9, 9], np.float32))
+        o.guide()
+        o.tell_guiding(np.array([9, 9, 9], np.float32))
+        o.select()
+        assert o.view()["reinit"].tolist() == [0, 0, 0]
+
+
+def test_nan_fitness_ranks_as_infinity():
+    p = O.Problem((2, 2), (), "mse")
+    o = O.Oracle(p, N=1, lam=4, G=1, sigma=0.5, T=10, seed=2)
+    o.init_positions()
+    o.tell_init(np.array([np.nan], np.float32))
+    assert o.view()["Y"][0] == np.inf
+    o.explode()
+    o.tell_explosion(np.array([np.nan, 3.0, np.nan, 2.0], np.float32))
+    v = o.view()
+    assert v["Yc"][0, :4].tolist() == [np.inf, 3.0, np.inf, 2.0]
+    o.guide()
+    v = o.view()
+    assert v["top"][0].tolist() == [1, 3] and v["bottom"][0].tolist() == [0, 2]
+    o.tell_guiding(np.array([np.nan], np.float32))
+    o.select()
+    v = o.view()
+    assert v["cstar"][0] == 3 and v["Y"][0] == 2.0
+
+
+def test_phase_order_enforced():
+    p = O.Problem((2, 2), (), "mse")
+    o = O.Oracle(p, N=2, lam=4, G=2, T=10)
+    with pytest.raises(RuntimeError):
+        o.explode()
+    o.init_positions()
+    with pytest.raises(RuntimeError):
+        o.guide()
+
+
+# ----------------------------------------------------------------- whole-run invariants
+def test_run_invariants_teacher():
+    wl = inputs.teacher_regression()
+    p = O.Problem.from_workload(wl)
+    o = O.Oracle(p, N=4, lam=32, G=4, T=60, seed=3)
+    o.init()
+    v = o.view()
+    best = [float(v["best_y"][0])]
+    lb, ub = -5.0, 5.0
+    for g in range(60):
+        prev = o.view()
+        o.generation()
+        v = o.view()
+        assert v["SE"].min() >= lb and v["SE"].max() <= ub
+        assert v["SG"].min() >= lb and v["SG"].max() <= ub
+        assert v["F"].min() >= lb and v["F"].max() <= ub
+        # elite never lost: the best firework is not re-initialised and best_y never rises
+        bf = int(np.argmin(v["Y"]))
+        assert v["reinit"][bf] == 0
+        assert v["best_y"][0] <= best[-1]
+        best.append(float(v["best_y"][0]))
+        assert float(v["best_y"][0]) == float(v["Y"].min())
+        np.testing.assert_array_equal(v["best_x"][0], v["F"][int(v["best_f"][0])])
+        # improved fireworks hold exactly the chosen candidate's fitness
+        for f in range(4):
+            if v["improved"][f] and not v["reinit"][f]:
+                assert v["Y"][f] == v["Yc"][f, v["cstar"][f]]
+                assert v["Y"][f] < prev["Y"][f]
+    assert best[-1] < best[0] / 10.0       # behavioural: the loss falls by 10x
+
+
+def test_run_is_deterministic_and_seeded():
+    wl = inputs.teacher_regression(n_samples=64)
+    p = O.Problem.from_workload(wl)
+    views = []
+    for seed in (7, 7, 8):
+        o = O.Oracle(p, N=3, lam=16, G=2, T=20, seed=seed)
+        o.run(10)
+        views.append(o.view())
+    assert np.array_equal(views[0]["F"], views[1]["F"])
+    assert np.array_equal(views[0]["best_y"], views[1]["best_y"])
+    assert not np.array_equal(views[0]["F"], views[2]["F"])
+
+
+def test_target_loss_stops_run():
+    wl = inputs.teacher_regression(n_samples=64)
+    p = O.Problem.from_workload(wl)
+    o = O.Oracle(p, N=3, lam=16, G=2, T=200, seed=1, use_target=1, target_loss=20.0)
+    o.run(200)
+    v = o.view()
+    assert v["done"] == 1 and v["best_y"][0] <= 20.0 and v["t"] < 200
