@@ -1,0 +1,243 @@
+/*
+ * mgfwa.h -- C ABI of the MI355X (gfx950) MGFWA hot path.
+ *
+ * The library runs the generation loop of GPU-MGFWA (the GPU multi-guiding spark
+ * fireworks algorithm, Sec. 3 and Alg. 1 of the paper) on one GPU for black-box
+ * optimisation of an MLP's weights: every spark is one weight vector of length
+ * D, and its fitness is the MLP's loss over a fixed, shared sample set.  Per
+ * generation it generates the explosion sparks of all fireworks of all
+ * populations at once, maps out-of-bounds coordinates back into the box,
+ * evaluates every spark, builds the multi-guiding sparks from the top and
+ * bottom sparks of each group, evaluates those, then selects each firework's
+ * best individual, updates the dynamic amplitude and runs the loser-out
+ * tournament (Alg. 1; Table 1 gives the batched B x N x D variables).
+ *
+ * Conventions shared by every entry point:
+ *  - All functions return an mgfwa_status (0 = success) and never abort; on
+ *    failure mgfwa_last_error() returns a thread-local message.
+ *  - Device memory is owned by the caller: the workspace, the problem's sample
+ *    and target buffers, and every buffer passed to ask/tell/evaluate.  The
+ *    library never allocates device memory.  The context object itself is
+ *    host memory owned by the library; release it with mgfwa_destroy.
+ *  - All device work is enqueued on the caller's HIP stream given to
+ *    mgfwa_init, in stream order; only mgfwa_best, mgfwa_best_all and
+ *    mgfwa_timing synchronise with the host.
+ *  - The same (config, problem, seed) gives bit-identical state on any run.
+ */
+#ifndef MGFWA_H
+#define MGFWA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MGFWA_API __attribute__((visibility("default")))
+
+#define MGFWA_MAX_LAYERS 4  /* Linear layers per MLP */
+#define MGFWA_MAX_WIDTH 256 /* largest layer output width */
+
+typedef struct mgfwa_ctx mgfwa_ctx;
+
+typedef enum {
+    MGFWA_OK = 0,
+    MGFWA_EINVAL = -1,       /* invalid argument or configuration */
+    MGFWA_ENOMEM = -2,       /* workspace too small or misaligned */
+    MGFWA_EHIP = -3,         /* a HIP runtime call failed (message has the HIP error) */
+    MGFWA_ESTATE = -4,       /* call out of order (ask/tell protocol, step in tell mode) */
+    MGFWA_EUNSUPPORTED = -5  /* valid MLP shape outside the compiled kernel set */
+} mgfwa_status;
+
+typedef enum { MGFWA_ACT_IDENTITY = 0, MGFWA_ACT_RELU = 1, MGFWA_ACT_TANH = 2,
+               MGFWA_ACT_GELU = 3 } mgfwa_act;
+typedef enum { MGFWA_LOSS_MSE = 0, MGFWA_LOSS_CE = 1 } mgfwa_loss;
+typedef enum { MGFWA_FP32 = 0, MGFWA_BF16 = 1 } mgfwa_precision;
+
+/*
+ * The black box f of Alg. 1: the loss of an MLP whose weights are the spark.
+ * Weight layout inside a spark (length D = sum_l in_l*out_l + out_l): for each
+ * layer l in order, W_l as out_l x in_l row-major, then b_l (the nn.Linear
+ * convention).  Hidden layers apply hidden_act[l]; the output layer is linear.
+ *   MSE: mean over samples and outputs of (y_hat - y)^2.
+ *   CE : mean over samples of logsumexp(z) - z[label].
+ * x_dev    float32 [n_samples][widths[0]], row-major, device.
+ * y_dev    float32 [n_samples][widths[n_layers]] (MSE only), device.
+ * labels_dev int32 [n_samples], each in [0, widths[n_layers]) (CE only), device.
+ * The buffers are borrowed: mgfwa_init copies them into the workspace on the
+ * stream, so they must stay valid until that work has run; afterwards the
+ * library no longer reads them.
+ */
+typedef struct {
+    int n_layers;                        /* 1..MGFWA_MAX_LAYERS */
+    int widths[MGFWA_MAX_LAYERS + 1];    /* widths[0] = input dim ... widths[n_layers] = output */
+    int hidden_act[MGFWA_MAX_LAYERS];    /* mgfwa_act per hidden layer (l < n_layers-1) */
+    int loss;                            /* mgfwa_loss; CE needs widths[n_layers] >= 2 */
+    int n_samples;                       /* >= 1 */
+    const float *x_dev;
+    const float *y_dev;
+    const int32_t *labels_dev;
+} mgfwa_problem;
+
+/*
+ * Algorithm parameters (Alg. 1; Sec. 2.1 names the operators).  B populations
+ * of N fireworks each; every firework emits lambda explosion sparks, split into
+ * G contiguous groups of m = lambda/G, and one guiding spark per group.
+ *   sigma     fraction of a group in the top and the bottom set: k = max(1, floor(sigma*m)),
+ *             sigma in (0, 0.5]
+ *   boost     guiding spark = x + boost*delta (boosted guiding vector)
+ *   amp_up, amp_down  dynamic amplitude factors on improvement / no improvement
+ *   amp_init  initial and restart amplitude A0 (<= 0 selects ub - lb)
+ *   lb, ub    search box [lb, ub]^D
+ *   max_generations   T, the budget the loser-out prediction uses (>= 1)
+ *   loser_out 1 enables the loser-out tournament
+ *   precision fitness GEMMs in FP32, or BF16 operands with FP32 accumulation
+ *   external_fitness  1: no fitness kernels, the caller tells every fitness
+ *   use_target, target_loss  stop once a population's best <= target_loss
+ *   seed      key of the counter-based generator
+ */
+typedef struct {
+    int n_populations;      /* B >= 1 */
+    int n_fireworks;        /* N >= 1 */
+    int n_sparks;           /* lambda >= 2, multiple of n_guiding, lambda/G >= 2 */
+    int n_guiding;          /* G >= 1 */
+    float sigma;
+    float boost;
+    float amp_up;
+    float amp_down;
+    float amp_init;
+    float lb;
+    float ub;
+    int max_generations;
+    int loser_out;
+    int precision;          /* mgfwa_precision */
+    int external_fitness;
+    int use_target;
+    float target_loss;
+    uint64_t seed;
+} mgfwa_config;
+
+/* Layout of the device state inside the workspace, for inspection: byte
+ * offsets from the workspace base, plus the dimensions needed to read them.
+ * Row-major arrays; "Dp" is D rounded up to 64 floats (padding is zero). */
+typedef struct {
+    int D, Dp, m, k, n_candidates;   /* n_candidates = lambda + G */
+    int generation;                  /* host view of completed generations */
+    size_t F;        /* float [B*N][Dp]   firework positions */
+    size_t A;        /* float [B*N]       amplitudes */
+    size_t Y;        /* float [B*N]       firework fitness */
+    size_t Yprev;    /* float [B*N]       fitness before the last selection */
+    size_t fresh;    /* int32 [B*N]       re-initialised in the previous generation */
+    size_t SE;       /* float [B*N*lambda][Dp] explosion sparks */
+    size_t SG;       /* float [B*N*G][Dp] guiding sparks */
+    size_t Yc;       /* float [B*N][lambda+G] candidate fitness */
+    size_t top;      /* int32 [B*N*G][k]  top members, ascending spark index */
+    size_t bottom;   /* int32 [B*N*G][k]  bottom members, ascending spark index */
+    size_t tie;      /* int32 [B*N*G]     group fitness all equal */
+    size_t cstar;    /* int32 [B*N]       best candidate of the last selection */
+    size_t improved; /* int32 [B*N] */
+    size_t reinit;   /* int32 [B*N] */
+    size_t best_x;   /* float [B][Dp] */
+    size_t best_y;   /* float [B] */
+    size_t best_f;   /* int32 [B] */
+    size_t best_gen; /* int32 [B] */
+    size_t gen;      /* int32 device generation counter */
+    size_t done;     /* int32 device stop flag */
+} mgfwa_state_info;
+
+/* Per-phase device time accumulated while timing is on (milliseconds). */
+#define MGFWA_N_PHASES 5
+typedef struct {
+    double ms[MGFWA_N_PHASES];  /* 0 explosion sparks, 1 explosion fitness, 2 ranking + guiding
+                                   sparks, 3 guiding fitness, 4 selection + loser-out */
+    double gen_ms_p50, gen_ms_p99, gen_ms_mean; /* whole-generation device time */
+    double fit_kernel_ms;       /* explosion-spark fitness GEMM kernel alone (subset of ms[1]) */
+    int generations;            /* generations measured since timing was switched on */
+} mgfwa_timing_info;
+
+/* Bytes of device workspace needed for (config, problem); 0 on invalid input. */
+MGFWA_API size_t mgfwa_workspace_bytes(const mgfwa_config *config, const mgfwa_problem *problem);
+
+/*
+ * Create a context and run the initialisation of Alg. 1: fireworks uniform in
+ * the box, amplitude A0, fitness of every firework (unless external_fitness),
+ * best-so-far.  workspace_dev must be 256-byte aligned and hold at least
+ * mgfwa_workspace_bytes bytes; it is owned by the caller and must outlive the
+ * context.  hip_stream is a hipStream_t (NULL = the null stream).
+ * Errors: EINVAL (config/problem), ENOMEM (workspace), EUNSUPPORTED (shape),
+ * EHIP (no device, launch failure).  *out is NULL on failure.
+ */
+MGFWA_API mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config,
+                                  const mgfwa_problem *problem, void *workspace_dev,
+                                  size_t workspace_bytes, void *hip_stream);
+
+/*
+ * Enqueue n_generations generations (the repeat loop of Alg. 1) on the stream
+ * and return without waiting.  Generations after the stop flag is raised are
+ * no-ops on the device.  ESTATE when external_fitness is set or an ask/tell
+ * exchange is in progress.
+ */
+MGFWA_API mgfwa_status mgfwa_step(mgfwa_ctx *ctx, int n_generations);
+
+/*
+ * The returned answer of Alg. 1: the best fitness found and its position, over
+ * all populations (lowest fitness, lower population on ties).  Synchronises
+ * the stream.  x_host: float[D] or NULL; f_host, generation: may be NULL;
+ * *generation receives the number of completed generations.
+ */
+MGFWA_API mgfwa_status mgfwa_best(mgfwa_ctx *ctx, float *x_host, float *f_host, int *generation);
+
+/* Per-population best: x_host float[B][D] (or NULL), f_host float[B], gen_host
+ * int32[B] = generation at which each best was found (NULLs allowed). Syncs. */
+MGFWA_API mgfwa_status mgfwa_best_all(mgfwa_ctx *ctx, float *x_host, float *f_host,
+                                      int32_t *gen_host);
+
+/*
+ * Black-box form of Alg. 1 (the caller evaluates f).  The exchange is
+ *   [after init, external_fitness only] ask -> B*N fireworks, tell -> their fitness;
+ *   then per generation: ask -> B*N*lambda explosion sparks, tell;
+ *                        ask -> B*N*G guiding sparks, tell (runs the selection).
+ * ask returns a device pointer into the workspace (float, rows x ld, row-major,
+ * valid until the next tell) and enqueues the work that produces it.  tell reads
+ * fitness_dev (float[rows], device, caller-owned) in stream order; NaN counts as
+ * +inf.  Any other order -> ESTATE.  In problem mode (external_fitness = 0)
+ * ask/tell may replace the built-in fitness for any generation.
+ */
+MGFWA_API mgfwa_status mgfwa_ask(mgfwa_ctx *ctx, const float **sparks_dev, int *rows, int *ld);
+MGFWA_API mgfwa_status mgfwa_tell(mgfwa_ctx *ctx, const float *fitness_dev);
+
+/*
+ * Fitness of `rows` weight vectors (the evaluation step of Alg. 1 on its own):
+ * w_dev float [rows][ld] device (16-byte aligned, ld >= D, ld % 4 == 0),
+ * out_dev float [rows] device; both caller-owned, read/written in stream order.
+ * Uses the context's problem and precision.  EINVAL without a problem.
+ */
+MGFWA_API mgfwa_status mgfwa_evaluate(mgfwa_ctx *ctx, const float *w_dev, int rows, int ld,
+                                      float *out_dev);
+
+/* Offsets and dimensions of the device state (no device work). */
+MGFWA_API mgfwa_status mgfwa_state(const mgfwa_ctx *ctx, mgfwa_state_info *info);
+
+/*
+ * Timing: while on, generations are launched kernel by kernel with HIP events
+ * around each phase (instead of one graph per generation); mgfwa_timing
+ * synchronises and reports the accumulated per-phase device time.  Switching
+ * on resets the totals.
+ */
+MGFWA_API mgfwa_status mgfwa_set_timing(mgfwa_ctx *ctx, int on);
+MGFWA_API mgfwa_status mgfwa_timing(mgfwa_ctx *ctx, mgfwa_timing_info *info);
+
+/* Release the context (waits for its pending work).  NULL is a no-op. */
+MGFWA_API void mgfwa_destroy(mgfwa_ctx *ctx);
+
+/* Thread-local message of the last failure in this thread ("" if none). */
+MGFWA_API const char *mgfwa_last_error(void);
+
+/* Library version string. */
+MGFWA_API const char *mgfwa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGFWA_H */

@@ -1,0 +1,684 @@
+// Host runtime and C ABI of the MGFWA library (declarations in include/mgfwa.h).
+//
+// A context owns no device memory: it carves the caller's workspace into the
+// state arrays, validates the configuration, and enqueues the generation loop
+// of Alg. 1 on the caller's stream.  Steady-state generations are captured once
+// into a HIP graph (on a private capture stream) and replayed; every kernel
+// reads the generation counter from device memory, so replays need no host
+// parameter updates and no host synchronisation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "../../include/mgfwa.h"
+#include "internal.h"
+
+using namespace mgfwa;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+mgfwa_status fail(mgfwa_status code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(MGFWA_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+int round_up(int v, int a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    size_t F, SE, SG, A, Y, Yprev, fresh, Yc, top, bottom, tie, cstar, improved, reinit, src;
+    size_t best_x, best_y, best_f, best_gen, best_upd, ctrl, partial, Xp, Xb, Ypad, Lpad, total;
+    int partial_rows;
+};
+
+enum Phase { PH_READY, PH_INIT_ASK, PH_INIT_TELL, PH_EXPL_TELL, PH_GUIDE_ASK, PH_GUIDE_TELL };
+
+struct Derived {
+    Shape s;
+    Net net;
+    Layout lay;
+};
+
+bool finite(float v) { return std::isfinite(v); }
+
+mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
+{
+    if (!c || !p) return fail(MGFWA_EINVAL, "config and problem are required");
+    if (c->n_populations < 1 || c->n_fireworks < 1 || c->n_guiding < 1)
+        return fail(MGFWA_EINVAL, "n_populations, n_fireworks and n_guiding must be >= 1");
+    if (c->n_sparks < 2 || c->n_sparks % c->n_guiding != 0 || c->n_sparks / c->n_guiding < 2)
+        return fail(MGFWA_EINVAL, "n_sparks must be a multiple of n_guiding with >= 2 sparks per group");
+    if (c->n_sparks > 8192) return fail(MGFWA_EINVAL, "n_sparks > 8192");
+    if (!(c->sigma > 0.0f && c->sigma <= 0.5f)) return fail(MGFWA_EINVAL, "sigma outside (0, 0.5]");
+    if (!finite(c->lb) || !finite(c->ub) || !(c->lb < c->ub)) return fail(MGFWA_EINVAL, "need finite lb < ub");
+    if (!finite(c->boost) || !finite(c->amp_up) || !finite(c->amp_down) || !finite(c->amp_init) ||
+        c->amp_up <= 0.0f || c->amp_down <= 0.0f)
+        return fail(MGFWA_EINVAL, "boost/amplitude parameters must be finite, factors > 0");
+    if (c->max_generations < 1) return fail(MGFWA_EINVAL, "max_generations must be >= 1");
+    if (c->precision != MGFWA_FP32 && c->precision != MGFWA_BF16)
+        return fail(MGFWA_EINVAL, "unknown precision %d", c->precision);
+    if (p->n_layers < 1 || p->n_layers > MGFWA_MAX_LAYERS)
+        return fail(MGFWA_EINVAL, "n_layers must be in [1, %d]", MGFWA_MAX_LAYERS);
+    for (int l = 0; l <= p->n_layers; ++l)
+        if (p->widths[l] < 1) return fail(MGFWA_EINVAL, "width %d must be >= 1", l);
+    if (p->widths[0] > 65536) return fail(MGFWA_EINVAL, "input width > 65536");
+    for (int l = 1; l <= p->n_layers; ++l)
+        if (p->widths[l] > MGFWA_MAX_WIDTH)
+            return fail(MGFWA_EUNSUPPORTED, "layer width %d > %d", p->widths[l], MGFWA_MAX_WIDTH);
+    for (int l = 0; l < p->n_layers - 1; ++l)
+        if (p->hidden_act[l] < 0 || p->hidden_act[l] > MGFWA_ACT_GELU)
+            return fail(MGFWA_EINVAL, "unknown activation %d", p->hidden_act[l]);
+    if (p->loss != MGFWA_LOSS_MSE && p->loss != MGFWA_LOSS_CE)
+        return fail(MGFWA_EINVAL, "unknown loss %d", p->loss);
+    if (p->loss == MGFWA_LOSS_CE && p->widths[p->n_layers] < 2)
+        return fail(MGFWA_EINVAL, "cross-entropy needs >= 2 outputs");
+    const bool need_data = !c->external_fitness || p->x_dev;
+    if (need_data) {
+        if (p->n_samples < 1 || p->n_samples > (1 << 24))
+            return fail(MGFWA_EINVAL, "n_samples must be in [1, 2^24]");
+        if (!p->x_dev) return fail(MGFWA_EINVAL, "x_dev is NULL");
+        if (p->loss == MGFWA_LOSS_MSE && !p->y_dev) return fail(MGFWA_EINVAL, "y_dev is NULL");
+        if (p->loss == MGFWA_LOSS_CE && !p->labels_dev) return fail(MGFWA_EINVAL, "labels_dev is NULL");
+    }
+
+    Shape &s = out->s;
+    s.B = c->n_populations;
+    s.N = c->n_fireworks;
+    s.lam = c->n_sparks;
+    s.G = c->n_guiding;
+    s.m = s.lam / s.G;
+    s.k = std::max(1, (int)std::floor((double)c->sigma * (double)s.m));
+    s.BN = s.B * s.N;
+    s.C = s.lam + s.G;
+    long D = 0;
+    Net &net = out->net;
+    std::memset(&net, 0, sizeof net);
+    net.nl = p->n_layers;
+    for (int l = 0; l < p->n_layers; ++l) {
+        net.fi[l] = p->widths[l];
+        net.fo[l] = p->widths[l + 1];
+        net.woff[l] = (int)D;
+        D += (long)net.fi[l] * net.fo[l];
+        net.boff[l] = (int)D;
+        D += net.fo[l];
+        net.act[l] = l < p->n_layers - 1 ? p->hidden_act[l] : MGFWA_ACT_IDENTITY;
+        net.vec[l] = (net.woff[l] % 4 == 0) && (net.fi[l] % 4 == 0);
+    }
+    if (D > (1L << 26)) return fail(MGFWA_EINVAL, "spark dimension %ld too large", D);
+    s.D = (int)D;
+    s.Dp = round_up(s.D, 64);
+    if ((long)s.BN * s.lam > (1L << 30)) return fail(MGFWA_EINVAL, "too many sparks");
+    s.inv_k = (float)(1.0 / (double)s.k);
+    s.boost = c->boost;
+    s.amp_up = c->amp_up;
+    s.amp_down = c->amp_down;
+    s.box.lb = c->lb;
+    s.box.ub = c->ub;
+    s.box.span = c->ub - c->lb;
+    s.amp0 = c->amp_init > 0.0f ? c->amp_init : s.box.span;
+    s.T = c->max_generations;
+    s.loser_out = c->loser_out ? 1 : 0;
+    s.use_target = c->use_target ? 1 : 0;
+    s.target = c->target_loss;
+    s.key = make_uint2((uint32_t)c->seed, (uint32_t)(c->seed >> 32));
+
+    net.loss = p->loss;
+    net.bf16 = c->precision == MGFWA_BF16;
+    net.S = need_data ? p->n_samples : 0;
+    net.S_pad = need_data ? round_up(p->n_samples, S_ALIGN) : 0;
+    net.in_pad = round_up(net.fi[0], net.bf16 ? 32 : 16);
+    const int outw = net.fo[net.nl - 1];
+    net.inv_norm = net.loss == MGFWA_LOSS_MSE ? (float)(1.0 / ((double)net.S * outw))
+                                              : (float)(1.0 / (double)net.S);
+
+    Layout &L = out->lay;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, ALIGN);
+        return o;
+    };
+    const size_t BN = s.BN, Dp = s.Dp;
+    L.F = take(BN * Dp * 4);
+    L.SE = take(BN * s.lam * Dp * 4);
+    L.SG = take(BN * s.G * Dp * 4);
+    L.A = take(BN * 4);
+    L.Y = take(BN * 4);
+    L.Yprev = take(BN * 4);
+    L.fresh = take(BN * 4);
+    L.Yc = take(BN * s.C * 4);
+    L.top = take(BN * s.G * s.k * 4);
+    L.bottom = take(BN * s.G * s.k * 4);
+    L.tie = take(BN * s.G * 4);
+    L.cstar = take(BN * 4);
+    L.improved = take(BN * 4);
+    L.reinit = take(BN * 4);
+    L.src = take(BN * 4);
+    L.best_x = take((size_t)s.B * Dp * 4);
+    L.best_y = take((size_t)s.B * 4);
+    L.best_f = take((size_t)s.B * 4);
+    L.best_gen = take((size_t)s.B * 4);
+    L.best_upd = take((size_t)s.B * 4);
+    L.ctrl = take(CTRL_WORDS * 4);
+    L.partial_rows = (int)std::max<size_t>(BN * s.lam, 1024);
+    L.partial = take((size_t)L.partial_rows * fit_max_bpr() * 4);
+    const size_t nx = (size_t)net.S_pad * net.in_pad;
+    L.Xp = take(net.bf16 ? 0 : nx * 4);
+    L.Xb = take(net.bf16 ? nx * 2 : 0);
+    L.Ypad = take(net.loss == MGFWA_LOSS_MSE ? (size_t)net.S_pad * outw * 4 : 0);
+    L.Lpad = take(net.loss == MGFWA_LOSS_CE ? (size_t)net.S_pad * 4 : 0);
+    L.total = off;
+    return MGFWA_OK;
+}
+
+}  // namespace
+
+struct mgfwa_ctx {
+    mgfwa_config cfg;
+    Shape s;
+    Net net;
+    Layout lay;
+    DevState d;
+    bool has_data;
+    char *ws;
+    hipStream_t stream;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool use_graph = true;
+    bool sync_debug = false;
+    FitPlan plan_init, plan_expl, plan_guide, plan_eval;
+    Phase phase = PH_READY;
+    int gen_host = 0;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::vector<hipEvent_t>> pending;
+    std::vector<double> gen_ms;
+    double phase_ms[MGFWA_N_PHASES] = {0, 0, 0, 0, 0};
+    double fit_kernel_ms = 0.0;
+};
+
+namespace {
+
+template <typename T>
+T *at(char *base, size_t off) { return reinterpret_cast<T *>(base + off); }
+
+mgfwa_status check(mgfwa_ctx *c, hipError_t e, const char *what)
+{
+    if (e != hipSuccess) return fail(MGFWA_EHIP, "%s: %s", what, hipGetErrorString(e));
+    if (c->sync_debug) {
+        hipError_t s = hipStreamSynchronize(c->stream);
+        if (s != hipSuccess) return fail(MGFWA_EHIP, "%s (sync): %s", what, hipGetErrorString(s));
+    }
+    return MGFWA_OK;
+}
+
+#define STEP(expr, what)                                  \
+    do {                                                  \
+        mgfwa_status st_ = check(c, (expr), what);        \
+        if (st_ != MGFWA_OK) return st_;                  \
+    } while (0)
+
+const OutMap kFlat = {1, 1, 0};
+
+mgfwa_status fit_rows(mgfwa_ctx *c, const FitPlan &plan, const float *W, size_t ld, int rows,
+                      OutMap map, float *out, hipStream_t st, hipEvent_t mid = nullptr)
+{
+    STEP(launch_fitness(c->net, plan, c->d, W, ld, rows, map, out, st, mid), "fitness");
+    return MGFWA_OK;
+}
+
+hipEvent_t take_event(mgfwa_ctx *c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Enqueue one generation on `st`; ev (7 events) brackets the five phases when
+// non-null, ev[6] marks the end of the explosion-fitness GEMM kernel.
+mgfwa_status enqueue_generation(mgfwa_ctx *c, hipStream_t st, hipEvent_t *ev)
+{
+    const Shape &s = c->s;
+    if (ev) STEP(hipEventRecord(ev[0], st), "event");
+    STEP(launch_explode(s, c->d, st), "explode");
+    if (ev) STEP(hipEventRecord(ev[1], st), "event");
+    mgfwa_status r = fit_rows(c, c->plan_expl, c->d.SE, s.Dp, s.BN * s.lam,
+                              OutMap{s.lam, s.C, 0}, c->d.Yc, st, ev ? ev[6] : nullptr);
+    if (r) return r;
+    if (ev) STEP(hipEventRecord(ev[2], st), "event");
+    STEP(launch_rank(s, c->d, st), "rank");
+    STEP(launch_guide(s, c->d, st), "guide");
+    if (ev) STEP(hipEventRecord(ev[3], st), "event");
+    r = fit_rows(c, c->plan_guide, c->d.SG, s.Dp, s.BN * s.G, OutMap{s.G, s.C, s.lam}, c->d.Yc, st);
+    if (r) return r;
+    if (ev) STEP(hipEventRecord(ev[4], st), "event");
+    STEP(launch_select(s, c->d, st), "select");
+    STEP(launch_apply(s, c->d, st), "apply");
+    STEP(launch_finish(c->d, 1, st), "finish");
+    if (ev) STEP(hipEventRecord(ev[5], st), "event");
+    return MGFWA_OK;
+}
+
+mgfwa_status build_graph(mgfwa_ctx *c)
+{
+    if (!c->cap) HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    mgfwa_status r = enqueue_generation(c, c->cap, nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap, &g);
+    if (r != MGFWA_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return r;
+    }
+    if (e != hipSuccess) return fail(MGFWA_EHIP, "graph capture: %s", hipGetErrorString(e));
+    c->graph = g;
+    HIP_TRY(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    return MGFWA_OK;
+}
+
+mgfwa_status reset_ctrl(mgfwa_ctx *c)
+{
+    // the control words and the per-population flags start at zero
+    static const int32_t zeros[CTRL_WORDS] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(c->d.ctrl, zeros, sizeof zeros, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return MGFWA_OK;
+}
+
+mgfwa_status finish_init(mgfwa_ctx *c)
+{
+    STEP(launch_init_select(c->s, c->d, c->stream), "init_select");
+    STEP(launch_apply(c->s, c->d, c->stream), "apply");
+    STEP(launch_finish(c->d, 0, c->stream), "finish");
+    return MGFWA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mgfwa_workspace_bytes(const mgfwa_config *config, const mgfwa_problem *problem)
+{
+    Derived dv;
+    if (derive(config, problem, &dv) != MGFWA_OK) return 0;
+    return dv.lay.total;
+}
+
+mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa_problem *problem,
+                        void *workspace_dev, size_t workspace_bytes, void *hip_stream)
+{
+    if (!out) return fail(MGFWA_EINVAL, "out is NULL");
+    *out = nullptr;
+    Derived dv;
+    mgfwa_status r = derive(config, problem, &dv);
+    if (r != MGFWA_OK) return r;
+    if (!workspace_dev) return fail(MGFWA_ENOMEM, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace_dev) % ALIGN != 0)
+        return fail(MGFWA_ENOMEM, "workspace must be %zu-byte aligned", ALIGN);
+    if (workspace_bytes < dv.lay.total)
+        return fail(MGFWA_ENOMEM, "workspace too small: %zu < %zu bytes", workspace_bytes,
+                    dv.lay.total);
+    const bool has_data = !config->external_fitness || problem->x_dev;
+    FitPlan pi{}, pe{}, pg{}, pv{};
+    if (has_data) {
+        if (!fit_select(dv.net, dv.s.BN, &pi) || !fit_select(dv.net, dv.s.BN * dv.s.lam, &pe) ||
+            !fit_select(dv.net, dv.s.BN * dv.s.G, &pg) ||
+            !fit_select(dv.net, dv.lay.partial_rows, &pv))
+            return fail(MGFWA_EUNSUPPORTED, "no compiled fitness kernel covers this MLP shape");
+    }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+
+    mgfwa_ctx *c = new mgfwa_ctx();
+    c->cfg = *config;
+    c->s = dv.s;
+    c->net = dv.net;
+    c->lay = dv.lay;
+    c->has_data = has_data;
+    c->ws = static_cast<char *>(workspace_dev);
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->plan_init = pi;
+    c->plan_expl = pe;
+    c->plan_guide = pg;
+    c->plan_eval = pv;
+    const char *ev = std::getenv("MGFWA_NO_GRAPH");
+    c->use_graph = !(ev && ev[0] == '1');
+    ev = std::getenv("MGFWA_SYNC_DEBUG");
+    c->sync_debug = ev && ev[0] == '1';
+    const Layout &L = c->lay;
+    DevState &d = c->d;
+    char *b = c->ws;
+    d.F = at<float>(b, L.F);
+    d.SE = at<float>(b, L.SE);
+    d.SG = at<float>(b, L.SG);
+    d.A = at<float>(b, L.A);
+    d.Y = at<float>(b, L.Y);
+    d.Yprev = at<float>(b, L.Yprev);
+    d.fresh = at<int32_t>(b, L.fresh);
+    d.Yc = at<float>(b, L.Yc);
+    d.top = at<int32_t>(b, L.top);
+    d.bottom = at<int32_t>(b, L.bottom);
+    d.tie = at<int32_t>(b, L.tie);
+    d.cstar = at<int32_t>(b, L.cstar);
+    d.improved = at<int32_t>(b, L.improved);
+    d.reinit = at<int32_t>(b, L.reinit);
+    d.src = at<int32_t>(b, L.src);
+    d.best_x = at<float>(b, L.best_x);
+    d.best_y = at<float>(b, L.best_y);
+    d.best_f = at<int32_t>(b, L.best_f);
+    d.best_gen = at<int32_t>(b, L.best_gen);
+    d.best_upd = at<int32_t>(b, L.best_upd);
+    d.ctrl = at<int32_t>(b, L.ctrl);
+    d.partial = at<float>(b, L.partial);
+    d.Xp = c->net.bf16 ? nullptr : at<float>(b, L.Xp);
+    d.Xb = c->net.bf16 ? at<uint16_t>(b, L.Xb) : nullptr;
+    d.Ypad = c->net.loss == MGFWA_LOSS_MSE ? at<float>(b, L.Ypad) : nullptr;
+    d.Lpad = c->net.loss == MGFWA_LOSS_CE ? at<int32_t>(b, L.Lpad) : nullptr;
+
+    auto bail = [&](mgfwa_status st) {
+        mgfwa_destroy(c);
+        return st;
+    };
+    r = reset_ctrl(c);
+    if (r) return bail(r);
+    if (has_data) {
+        r = check(c, launch_pack_problem(c->net, problem->x_dev, problem->y_dev,
+                                         problem->labels_dev, d, c->stream), "pack");
+        if (r) return bail(r);
+    }
+    r = check(c, launch_init_positions(c->s, d, c->stream), "init_positions");
+    if (r) return bail(r);
+    if (config->external_fitness) {
+        c->phase = PH_INIT_ASK;
+    } else {
+        r = fit_rows(c, c->plan_init, d.F, c->s.Dp, c->s.BN, kFlat, d.Y, c->stream);
+        if (r) return bail(r);
+        r = finish_init(c);
+        if (r) return bail(r);
+        c->phase = PH_READY;
+    }
+    *out = c;
+    return MGFWA_OK;
+}
+
+mgfwa_status mgfwa_step(mgfwa_ctx *c, int n)
+{
+    if (!c) return fail(MGFWA_EINVAL, "ctx is NULL");
+    if (n < 0) return fail(MGFWA_EINVAL, "n_generations < 0");
+    if (c->cfg.external_fitness) return fail(MGFWA_ESTATE, "step needs the built-in fitness");
+    if (c->phase != PH_READY) return fail(MGFWA_ESTATE, "an ask/tell exchange is in progress");
+    for (int i = 0; i < n; ++i) {
+        if (c->timing) {
+            std::vector<hipEvent_t> ev(7);
+            for (auto &e : ev) {
+                e = take_event(c);
+                if (!e) return fail(MGFWA_EHIP, "hipEventCreate failed");
+            }
+            mgfwa_status r = enqueue_generation(c, c->stream, ev.data());
+            c->pending.push_back(ev);
+            if (r) return r;
+        } else if (c->use_graph) {
+            if (!c->gexec) {
+                mgfwa_status r = build_graph(c);
+                if (r) return r;
+            }
+            HIP_TRY(hipGraphLaunch(c->gexec, c->stream));
+        } else {
+            mgfwa_status r = enqueue_generation(c, c->stream, nullptr);
+            if (r) return r;
+        }
+        c->gen_host += 1;
+    }
+    HIP_TRY(hipGetLastError());
+    return MGFWA_OK;
+}
+
+mgfwa_status mgfwa_best_all(mgfwa_ctx *c, float *x_host, float *f_host, int32_t *gen_host)
+{
+    if (!c) return fail(MGFWA_EINVAL, "ctx is NULL");
+    const int B = c->s.B;
+    if (f_host)
+        HIP_TRY(hipMemcpyAsync(f_host, c->d.best_y, B * 4, hipMemcpyDeviceToHost, c->stream));
+    if (gen_host)
+        HIP_TRY(hipMemcpyAsync(gen_host, c->d.best_gen, B * 4, hipMemcpyDeviceToHost, c->stream));
+    if (x_host)
+        HIP_TRY(hipMemcpy2DAsync(x_host, (size_t)c->s.D * 4, c->d.best_x, (size_t)c->s.Dp * 4,
+                                 (size_t)c->s.D * 4, B, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return MGFWA_OK;
+}
+
+mgfwa_status mgfwa_best(mgfwa_ctx *c, float *x_host, float *f_host, int *generation)
+{
+    if (!c) return fail(MGFWA_EINVAL, "ctx is NULL");
+    const int B = c->s.B;
+    std::vector<float> by(B);
+    int32_t ctrl[CTRL_WORDS];
+    HIP_TRY(hipMemcpyAsync(by.data(), c->d.best_y, B * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(ctrl, c->d.ctrl, sizeof ctrl, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    int pb = 0;
+    for (int b = 1; b < B; ++b)
+        if (by[b] < by[pb]) pb = b;
+    if (f_host) *f_host = by[pb];
+    if (generation) *generation = ctrl[CTRL_GEN];
+    if (x_host) {
+        HIP_TRY(hipMemcpyAsync(x_host, c->d.best_x + (size_t)pb * c->s.Dp, (size_t)c->s.D * 4,
+                               hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    return MGFWA_OK;
+}
+
+mgfwa_status mgfwa_ask(mgfwa_ctx *c, const float **sparks, int *rows, int *ld)
+{
+    if (!c || !sparks) return fail(MGFWA_EINVAL, "NULL argument");
+    const Shape &s = c->s;
+    switch (c->phase) {
+    case PH_INIT_ASK:
+        *sparks = c->d.F;
+        if (rows) *rows = s.BN;
+        c->phase = PH_INIT_TELL;
+        break;
+    case PH_READY:
+        STEP(launch_explode(s, c->d, c->stream), "explode");
+        *sparks = c->d.SE;
+        if (rows) *rows = s.BN * s.lam;
+        c->phase = PH_EXPL_TELL;
+        break;
+    case PH_GUIDE_ASK:
+        *sparks = c->d.SG;
+        if (rows) *rows = s.BN * s.G;
+        c->phase = PH_GUIDE_TELL;
+        break;
+    default:
+        return fail(MGFWA_ESTATE, "ask while a tell is expected");
+    }
+    if (ld) *ld = s.Dp;
+    return MGFWA_OK;
+}
+
+mgfwa_status mgfwa_tell(mgfwa_ctx *c, const float *fit)
+{
+    if (!c || !fit) return fail(MGFWA_EINVAL, "NULL argument");
+    const Shape &s = c->s;
+    switch (c->phase) {
+    case PH_INIT_TELL: {
+        STEP(launch_store_fitness(fit, s.BN, kFlat, c->d.Y, nullptr, c->stream), "store");
+        mgfwa_status r = finish_init(c);
+        if (r) return r;
+        c->phase = PH_READY;
+        break;
+    }
+    case PH_EXPL_TELL:
+        STEP(launch_store_fitness(fit, s.BN * s.lam, OutMap{s.lam, s.C, 0}, c->d.Yc, c->d.ctrl,
+                                  c->stream), "store");
+        STEP(launch_rank(s, c->d, c->stream), "rank");
+        STEP(launch_guide(s, c->d, c->stream), "guide");
+        c->phase = PH_GUIDE_ASK;
+        break;
+    case PH_GUIDE_TELL:
+        STEP(launch_store_fitness(fit, s.BN * s.G, OutMap{s.G, s.C, s.lam}, c->d.Yc, c->d.ctrl,
+                                  c->stream), "store");
+        STEP(launch_select(s, c->d, c->stream), "select");
+        STEP(launch_apply(s, c->d, c->stream), "apply");
+        STEP(launch_finish(c->d, 1, c->stream), "finish");
+        c->phase = PH_READY;
+        c->gen_host += 1;
+        break;
+    default:
+        return fail(MGFWA_ESTATE, "tell without a matching ask");
+    }
+    return MGFWA_OK;
+}
+
+mgfwa_status mgfwa_evaluate(mgfwa_ctx *c, const float *w, int rows, int ld, float *out)
+{
+    if (!c) return fail(MGFWA_EINVAL, "ctx is NULL");
+    if (!c->has_data) return fail(MGFWA_EINVAL, "context has no problem data to evaluate");
+    if (rows < 0 || (rows > 0 && (!w || !out))) return fail(MGFWA_EINVAL, "bad rows/buffers");
+    if (ld < c->s.D || ld % 4 != 0 || reinterpret_cast<uintptr_t>(w) % 16 != 0)
+        return fail(MGFWA_EINVAL, "ld must be >= D and a multiple of 4; w 16-byte aligned");
+    const int chunk = c->lay.partial_rows;
+    for (int r0 = 0; r0 < rows; r0 += chunk) {
+        const int nr = std::min(chunk, rows - r0);
+        FitPlan plan;
+        if (!fit_select(c->net, nr, &plan))
+            return fail(MGFWA_EUNSUPPORTED, "no compiled fitness kernel covers this MLP shape");
+        mgfwa_status r = fit_rows(c, plan, w + (size_t)r0 * ld, (size_t)ld, nr, kFlat, out + r0,
+                                  c->stream);
+        if (r) return r;
+    }
+    return MGFWA_OK;
+}
+
+mgfwa_status mgfwa_state(const mgfwa_ctx *c, mgfwa_state_info *info)
+{
+    if (!c || !info) return fail(MGFWA_EINVAL, "NULL argument");
+    const Layout &L = c->lay;
+    info->D = c->s.D;
+    info->Dp = c->s.Dp;
+    info->m = c->s.m;
+    info->k = c->s.k;
+    info->n_candidates = c->s.C;
+    info->generation = c->gen_host;
+    info->F = L.F;
+    info->A = L.A;
+    info->Y = L.Y;
+    info->Yprev = L.Yprev;
+    info->fresh = L.fresh;
+    info->SE = L.SE;
+    info->SG = L.SG;
+    info->Yc = L.Yc;
+    info->top = L.top;
+    info->bottom = L.bottom;
+    info->tie = L.tie;
+    info->cstar = L.cstar;
+    info->improved = L.improved;
+    info->reinit = L.reinit;
+    info->best_x = L.best_x;
+    info->best_y = L.best_y;
+    info->best_f = L.best_f;
+    info->best_gen = L.best_gen;
+    info->gen = L.ctrl + CTRL_GEN * 4;
+    info->done = L.ctrl + CTRL_DONE * 4;
+    return MGFWA_OK;
+}
+
+mgfwa_status mgfwa_set_timing(mgfwa_ctx *c, int on)
+{
+    if (!c) return fail(MGFWA_EINVAL, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (auto &ev : c->pending)
+        for (hipEvent_t e : ev) c->pool.push_back(e);
+    c->pending.clear();
+    c->gen_ms.clear();
+    for (double &v : c->phase_ms) v = 0.0;
+    c->fit_kernel_ms = 0.0;
+    c->timing = on != 0;
+    return MGFWA_OK;
+}
+
+mgfwa_status mgfwa_timing(mgfwa_ctx *c, mgfwa_timing_info *info)
+{
+    if (!c || !info) return fail(MGFWA_EINVAL, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (auto &ev : c->pending) {
+        float ms = 0.0f;
+        for (int p = 0; p < MGFWA_N_PHASES; ++p) {
+            HIP_TRY(hipEventElapsedTime(&ms, ev[p], ev[p + 1]));
+            c->phase_ms[p] += ms;
+        }
+        HIP_TRY(hipEventElapsedTime(&ms, ev[1], ev[6]));
+        c->fit_kernel_ms += ms;
+        HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[MGFWA_N_PHASES]));
+        c->gen_ms.push_back(ms);
+        for (hipEvent_t e : ev) c->pool.push_back(e);
+    }
+    c->pending.clear();
+    for (int p = 0; p < MGFWA_N_PHASES; ++p) info->ms[p] = c->phase_ms[p];
+    info->fit_kernel_ms = c->fit_kernel_ms;
+    info->generations = (int)c->gen_ms.size();
+    info->gen_ms_p50 = info->gen_ms_p99 = info->gen_ms_mean = 0.0;
+    if (!c->gen_ms.empty()) {
+        std::vector<double> v = c->gen_ms;
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double q) {
+            size_t i = (size_t)std::ceil(q * v.size()) - 1;
+            return v[std::min(i, v.size() - 1)];
+        };
+        info->gen_ms_p50 = pct(0.50);
+        info->gen_ms_p99 = pct(0.99);
+        double s = 0.0;
+        for (double x : v) s += x;
+        info->gen_ms_mean = s / v.size();
+    }
+    return MGFWA_OK;
+}
+
+void mgfwa_destroy(mgfwa_ctx *c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    for (auto &ev : c->pending)
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+const char *mgfwa_last_error(void) { return g_err; }
+
+const char *mgfwa_version(void) { return "mgfwa-gfx950 0.1.0"; }
+
+}  // extern "C"

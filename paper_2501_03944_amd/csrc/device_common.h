@@ -1,0 +1,88 @@
+// Device helpers shared by the MGFWA kernels: the counter-based generator, the
+// uniform draw, the search-box mapping and the order-preserving fitness key.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mgfwa {
+
+// Stream tag = counter word 3 of every draw.
+enum : uint32_t { TAG_INIT = 0, TAG_EXPL = 1, TAG_EXPL_MAP = 2, TAG_GUIDE_MAP = 3, TAG_REINIT = 4 };
+
+// Device control words (int32 array in the workspace).
+enum : int { CTRL_GEN = 0, CTRL_DONE = 1, CTRL_DONE_PENDING = 2, CTRL_WORDS = 4 };
+
+struct Box {
+    float lb, ub, span;  // span = ub - lb rounded once to binary32
+};
+
+// Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11).  Each round
+// takes the 64-bit products of counter words 0 and 2 with the two round
+// multipliers; the new counter is (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0) and
+// the key advances by the two Weyl increments between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k.x += 0x9E3779B9u;
+            k.y += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+    }
+    return c;
+}
+
+// Four words of block (chunk = d/4, row, generation, tag) under the job key.
+__device__ __forceinline__ uint4 draw4(uint2 key, uint32_t chunk, uint32_t row, uint32_t t,
+                                       uint32_t tag)
+{
+    return philox4x32_10(make_uint4(chunk, row, t, tag), key);
+}
+
+// 24 random bits scaled by 2^-24: exact, in [0, 1 - 2^-24].
+__device__ __forceinline__ float u01(uint32_t r)
+{
+    return (float)(r >> 8) * 0x1p-24f;
+}
+
+// Uniform position in the closed box: fma(u, ub - lb, lb) clamped to [lb, ub].
+__device__ __forceinline__ float box_uniform(const Box &b, float u)
+{
+    float v = __builtin_fmaf(u, b.span, b.lb);
+    v = v < b.lb ? b.lb : v;
+    return v > b.ub ? b.ub : v;
+}
+
+__device__ __forceinline__ bool outside(const Box &b, float v)
+{
+    return v < b.lb || v > b.ub;
+}
+
+// Order-preserving 32-bit key of a (NaN-free) fitness value; -0 and +0 share a key.
+__device__ __forceinline__ uint32_t fit_key(float y)
+{
+    uint32_t u = __float_as_uint(y == 0.0f ? 0.0f : y);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// The stored form of a fitness value: NaN becomes +inf.
+__device__ __forceinline__ float canon_fitness(float y)
+{
+    return y != y ? __int_as_float(0x7f800000) : y;
+}
+
+// Block index remap so that consecutive logical blocks land on the same XCD
+// (hardware dispatches linear block ids round-robin over the 8 XCDs).
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks)
+{
+    constexpr int X = 8;
+    const int q = nblocks / X, rem = nblocks % X;
+    const int xcd = bid % X, pos = bid / X;
+    return xcd < rem ? xcd * (q + 1) + pos : rem * (q + 1) + (xcd - rem) * q + pos;
+}
+
+}  // namespace mgfwa

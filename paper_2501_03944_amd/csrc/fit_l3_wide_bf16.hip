@@ -1,0 +1,21 @@
+// Fitness kernel instances: three layers, hidden width up to 256, BF16.
+#include "fit_kernel.h"
+
+namespace mgfwa {
+namespace fit {
+
+namespace {
+const KernelEntry kEntries[] = {
+    FIT_ENTRY(true, 2, 16, 16, 1, 0),
+    FIT_ENTRY(true, 2, 16, 16, 4, 0),
+};
+}  // namespace
+
+const KernelEntry *table_l3_wide_bf16(int *n)
+{
+    *n = (int)(sizeof kEntries / sizeof kEntries[0]);
+    return kEntries;
+}
+
+}  // namespace fit
+}  // namespace mgfwa

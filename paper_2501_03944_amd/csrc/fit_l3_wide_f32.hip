@@ -1,0 +1,21 @@
+// Fitness kernel instances: three layers, hidden width up to 256, FP32.
+#include "fit_kernel.h"
+
+namespace mgfwa {
+namespace fit {
+
+namespace {
+const KernelEntry kEntries[] = {
+    FIT_ENTRY(false, 2, 16, 16, 1, 0),
+    FIT_ENTRY(false, 2, 16, 16, 4, 0),
+};
+}  // namespace
+
+const KernelEntry *table_l3_wide_f32(int *n)
+{
+    *n = (int)(sizeof kEntries / sizeof kEntries[0]);
+    return kEntries;
+}
+
+}  // namespace fit
+}  // namespace mgfwa

@@ -1,0 +1,183 @@
+// Fitness host side: kernel table, plan selection and launches, plus the
+// partial-sum finalisation and the packing of the problem data.  The kernel
+// template lives in fit_kernel.h; the fit_*.hip files instantiate it.
+#include "fit_kernel.h"
+
+namespace mgfwa {
+
+namespace fit {
+// one table per instantiation file
+const KernelEntry *table_std(int *n);
+const KernelEntry *table_l1(int *n);
+const KernelEntry *table_l2(int *n);
+const KernelEntry *table_l2_wide(int *n);
+const KernelEntry *table_l3(int *n);
+const KernelEntry *table_l3_wide_f32(int *n);
+const KernelEntry *table_l3_wide_bf16(int *n);
+const KernelEntry *table_l4_f32(int *n);
+const KernelEntry *table_l4_bf16(int *n);
+const KernelEntry *table_l4_wide_f32(int *n);
+const KernelEntry *table_l4_wide_bf16(int *n);
+}  // namespace fit
+
+namespace {
+
+using namespace fit;
+
+constexpr int MAX_BPR = 64;
+
+// Sum of a row's partials in order, scaled to the mean, NaN -> +inf, scattered.
+__global__ __launch_bounds__(256) void k_fit_finalize(const float *__restrict__ partial, int rows,
+                                                      int bpr, float inv_norm, OutMap map,
+                                                      float *__restrict__ out)
+{
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= rows) return;
+    float t = 0.0f;
+    for (int c = 0; c < bpr; ++c) t += partial[(size_t)r * bpr + c];
+    out[(size_t)(r / map.per) * map.stride + map.offset + r % map.per] = canon_fitness(t * inv_norm);
+}
+
+// Pack the problem data: X zero-padded to [S_pad][in_pad] (FP32 or bf16 RNE),
+// MSE targets to [S_pad][out], labels to [S_pad] (-1 on padding).
+__global__ __launch_bounds__(256) void k_pack(const float *__restrict__ x, const float *__restrict__ y,
+                                              const int32_t *__restrict__ lab, int S, int S_pad,
+                                              int in, int in_pad, int out, int bf16,
+                                              float *__restrict__ Xp, uint16_t *__restrict__ Xb,
+                                              float *__restrict__ Yp, int32_t *__restrict__ Lp)
+{
+    const size_t tid = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t nx = (size_t)S_pad * in_pad;
+    if (tid < nx) {
+        const int s = (int)(tid / in_pad), k = (int)(tid % in_pad);
+        const float v = (s < S && k < in) ? x[(size_t)s * in + k] : 0.0f;
+        if (bf16) Xb[tid] = __builtin_bit_cast(uint16_t, (__bf16)v);
+        else Xp[tid] = v;
+    }
+    if (tid < (size_t)S_pad * out && Yp) {
+        const int s = (int)(tid / out);
+        Yp[tid] = (s < S && y) ? y[tid] : 0.0f;
+    }
+    if (tid < (size_t)S_pad && Lp) Lp[tid] = (tid < (size_t)S && lab) ? lab[tid] : -1;
+}
+
+const KernelEntry *(*const kTables[])(int *) = {
+    table_std,         table_l1,          table_l2,       table_l2_wide,     table_l3,
+    table_l3_wide_f32, table_l3_wide_bf16, table_l4_f32,  table_l4_bf16,     table_l4_wide_f32,
+    table_l4_wide_bf16,
+};
+
+}  // namespace
+
+int fit_max_bpr() { return MAX_BPR; }
+
+bool fit_select(const Net &net, int rows, FitPlan *plan)
+{
+    int need[MAXL] = {0, 0, 0, 0};
+    for (int l = 0; l < net.nl; ++l) {
+        need[l] = (net.fo[l] + 15) / 16;
+        // BF16 chains need even 16-row blocks for every layer that feeds another
+        if (net.bf16 && l < net.nl - 1 && (need[l] & 1)) need[l] += 1;
+    }
+    const KernelEntry *best = nullptr;
+    long best_cost = 0;
+    for (auto table : kTables) {
+        int nent = 0;
+        const KernelEntry *ents = table(&nent);
+        for (int ie = 0; ie < nent; ++ie) {
+            const KernelEntry &e = ents[ie];
+            if (e.bf16 != net.bf16) continue;
+            bool ok = true;
+            long cost = 0;
+            for (int l = 0; l < MAXL; ++l) {
+                const bool present = l < net.nl;
+                if (present != (e.R[l] > 0) || (present && e.R[l] < need[l])) {
+                    ok = false;
+                    break;
+                }
+                if (present) cost += (long)e.R[l] * (l == 0 ? net.in_pad : net.fo[l - 1] + 16);
+            }
+            if (ok && (!best || cost < best_cost)) {
+                best = &e;
+                best_cost = cost;
+            }
+        }
+    }
+    if (!best) return false;
+    plan->kernel = best->fn;
+    plan->P = best->P;
+    plan->rows = rows;
+    // Blocks per spark: enough blocks to fill the chip (about 4 per CU) while
+    // keeping at least two slab groups per wavefront.
+    const int group = WAVES * 16 * best->P;                  // samples per block pass
+    const int max_bpr = (net.S_pad + group - 1) / group;
+    int bpr = (1024 + rows - 1) / (rows > 0 ? rows : 1);
+    int lim = max_bpr / 2 > 0 ? max_bpr / 2 : 1;
+    if (bpr > lim) bpr = lim;
+    if (bpr > MAX_BPR) bpr = MAX_BPR;
+    if (bpr < 1) bpr = 1;
+    int spb = (net.S_pad + bpr - 1) / bpr;
+    spb = (spb + group - 1) / group * group;
+    bpr = (net.S_pad + spb - 1) / spb;
+    plan->bpr = bpr;
+    plan->spb = spb;
+    return true;
+}
+
+hipError_t launch_fitness(const Net &net, const FitPlan &plan, const DevState &d, const float *W,
+                          size_t ld, int rows, OutMap map, float *out, hipStream_t st,
+                          hipEvent_t mid)
+{
+    if (rows <= 0) return hipSuccess;
+    FitArgs a;
+    a.W = W;
+    a.ld = ld;
+    a.rows = rows;
+    a.X = d.Xp;
+    a.Xb = d.Xb;
+    a.in_pad = net.in_pad;
+    a.S = net.S;
+    a.S_pad = net.S_pad;
+    a.nl = net.nl;
+    for (int l = 0; l < MAXL; ++l) {
+        a.fi[l] = net.fi[l];
+        a.fo[l] = net.fo[l];
+        a.woff[l] = net.woff[l];
+        a.boff[l] = net.boff[l];
+        a.act[l] = net.act[l];
+        a.vec[l] = net.vec[l];
+    }
+    a.loss = net.loss;
+    a.Y = d.Ypad;
+    a.lab = d.Lpad;
+    a.bpr = plan.bpr;
+    a.spb = plan.spb;
+    a.partial = d.partial;
+    void *args[] = {&a};
+    hipError_t e = hipLaunchKernel(plan.kernel, dim3((unsigned)(rows * plan.bpr)), dim3(TPB), args,
+                                   0, st);
+    if (e != hipSuccess) return e;
+    if (mid) {
+        e = hipEventRecord(mid, st);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_fit_finalize, dim3((rows + 255) / 256), dim3(256), 0, st, d.partial, rows,
+                       plan.bpr, net.inv_norm, map, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_problem(const Net &net, const float *x, const float *y,
+                               const int32_t *labels, const DevState &d, hipStream_t st)
+{
+    const int out = net.fo[net.nl - 1];
+    size_t n = (size_t)net.S_pad * net.in_pad;
+    if ((size_t)net.S_pad * out > n) n = (size_t)net.S_pad * out;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_pack, dim3(blocks), dim3(256), 0, st, x, net.loss == 0 ? y : nullptr,
+                       net.loss == 1 ? labels : nullptr, net.S, net.S_pad, net.fi[0], net.in_pad,
+                       out, net.bf16, d.Xp, d.Xb, net.loss == 0 ? d.Ypad : nullptr,
+                       net.loss == 1 ? d.Lpad : nullptr);
+    return hipGetLastError();
+}
+
+}  // namespace mgfwa

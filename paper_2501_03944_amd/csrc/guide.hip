@@ -1,0 +1,142 @@
+// Multi-guiding sparks (Alg. 1: generate the multi-guiding sparks, then their
+// random mapping).
+//
+// k_rank  -- one block per firework: ranks the members of every guiding group
+//            by (fitness key, spark index), writes the top-k and bottom-k member
+//            lists in ascending spark index and the all-tie flag.
+// k_guide -- grid over (group, 4-coordinate chunk): the guiding vector is
+//            (sum of top sparks - sum of bottom sparks) * (1/k), each sum taken
+//            in ascending spark index (zero when the group ties); the guiding
+//            spark x + boost*delta is mapped back into the box like an
+//            explosion spark.  HBM-bound: it streams 2k spark rows per group.
+#include "internal.h"
+
+namespace mgfwa {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int MAX_GRID_Y = 65535;
+
+__global__ __launch_bounds__(TPB) void k_rank(const float *__restrict__ Yc, int C, int lam, int G,
+                                              int m, int k, int32_t *__restrict__ top,
+                                              int32_t *__restrict__ bottom,
+                                              int32_t *__restrict__ tie,
+                                              const int32_t *__restrict__ ctrl)
+{
+    if (ctrl[CTRL_DONE]) return;
+    extern __shared__ uint32_t sh[];
+    uint32_t *key = sh;               // [lam]
+    int32_t *rank = (int32_t *)(sh + lam);  // [lam]
+    const int gf = blockIdx.x;
+    for (int j = threadIdx.x; j < lam; j += blockDim.x) key[j] = fit_key(Yc[(size_t)gf * C + j]);
+    __syncthreads();
+    for (int j = threadIdx.x; j < lam; j += blockDim.x) {
+        const int j0 = (j / m) * m;
+        const uint32_t kj = key[j];
+        int r = 0;
+        for (int i = j0; i < j0 + m; ++i) {
+            const uint32_t ki = key[i];
+            r += (ki < kj) || (ki == kj && i < j);
+        }
+        rank[j] = r;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < lam; j += blockDim.x) {
+        const int g = j / m, j0 = g * m, rj = rank[j];
+        const size_t base = ((size_t)gf * G + g) * k;
+        if (rj < k) {
+            int pos = 0;
+            for (int i = j0; i < j; ++i) pos += rank[i] < k;
+            top[base + pos] = j;
+        }
+        if (rj >= m - k) {
+            int pos = 0;
+            for (int i = j0; i < j; ++i) pos += rank[i] >= m - k;
+            bottom[base + pos] = j;
+        }
+        if (rj == 0) {
+            // the group ties iff its first and last ranked members share a key
+            uint32_t kmax = 0;
+            for (int i = j0; i < j0 + m; ++i)
+                if (rank[i] == m - 1) kmax = key[i];
+            tie[(size_t)gf * G + g] = (key[j] == kmax);
+        }
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_guide(const float *__restrict__ F,
+                                               const float *__restrict__ SE,
+                                               float *__restrict__ SG,
+                                               const int32_t *__restrict__ top,
+                                               const int32_t *__restrict__ bottom,
+                                               const int32_t *__restrict__ tie, int G, int lam,
+                                               int k, float inv_k, float boost, int groups, int D,
+                                               int Dp, uint2 key, Box box,
+                                               const int32_t *__restrict__ ctrl)
+{
+    if (ctrl[CTRL_DONE]) return;
+    const uint32_t tn = (uint32_t)ctrl[CTRL_GEN] + 1u;
+    const int chunk = blockIdx.x * TPB + threadIdx.x;
+    if (chunk >= (Dp >> 2)) return;
+    for (int gi = blockIdx.y; gi < groups; gi += gridDim.y) {
+        const int gf = gi / G;
+        const float4 x4 = reinterpret_cast<const float4 *>(F + (size_t)gf * Dp)[chunk];
+        float dlt[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (!tie[gi]) {
+            float st[4] = {0.0f, 0.0f, 0.0f, 0.0f}, sb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            const int32_t *tp = top + (size_t)gi * k;
+            const int32_t *bp = bottom + (size_t)gi * k;
+            const float *base = SE + (size_t)gf * lam * Dp;
+            for (int i = 0; i < k; ++i) {
+                const float4 a = reinterpret_cast<const float4 *>(base + (size_t)tp[i] * Dp)[chunk];
+                const float4 b = reinterpret_cast<const float4 *>(base + (size_t)bp[i] * Dp)[chunk];
+                st[0] = st[0] + a.x; st[1] = st[1] + a.y; st[2] = st[2] + a.z; st[3] = st[3] + a.w;
+                sb[0] = sb[0] + b.x; sb[1] = sb[1] + b.y; sb[2] = sb[2] + b.z; sb[3] = sb[3] + b.w;
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) dlt[e] = (st[e] - sb[e]) * inv_k;
+        }
+        const float x[4] = {x4.x, x4.y, x4.z, x4.w};
+        float v[4];
+        bool any_out = false;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            v[e] = boost == 1.0f ? x[e] + dlt[e] : __builtin_fmaf(boost, dlt[e], x[e]);
+            any_out |= outside(box, v[e]);
+        }
+        if (any_out) {
+            const uint4 r2 = draw4(key, (uint32_t)chunk, (uint32_t)gi, tn, TAG_GUIDE_MAP);
+            const uint32_t w2[4] = {r2.x, r2.y, r2.z, r2.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (outside(box, v[e])) v[e] = box_uniform(box, u01(w2[e]));
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (4 * chunk + e >= D) v[e] = 0.0f;
+        reinterpret_cast<float4 *>(SG + (size_t)gi * Dp)[chunk] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_rank(const Shape &s, const DevState &d, hipStream_t st)
+{
+    const size_t shmem = (size_t)s.lam * 8;
+    hipLaunchKernelGGL(k_rank, dim3(s.BN), dim3(TPB), shmem, st, d.Yc, s.C, s.lam, s.G, s.m, s.k,
+                       d.top, d.bottom, d.tie, d.ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_guide(const Shape &s, const DevState &d, hipStream_t st)
+{
+    const int groups = s.BN * s.G;
+    const int nchunk = s.Dp >> 2;
+    dim3 grid((nchunk + TPB - 1) / TPB, groups < MAX_GRID_Y ? groups : MAX_GRID_Y);
+    hipLaunchKernelGGL(k_guide, grid, dim3(TPB), 0, st, d.F, d.SE, d.SG, d.top, d.bottom, d.tie,
+                       s.G, s.lam, s.k, s.inv_k, s.boost, groups, s.D, s.Dp, s.key, s.box, d.ctrl);
+    return hipGetLastError();
+}
+
+}  // namespace mgfwa

@@ -1,0 +1,95 @@
+// Internal interfaces between the host runtime (capi.hip) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "device_common.h"
+
+namespace mgfwa {
+
+constexpr int MAXL = 4;        // Linear layers per MLP
+constexpr int MAXW = 256;      // widest layer output
+constexpr int S_ALIGN = 128;   // sample padding of the packed problem data
+
+// Where a row's result goes: out[(r / per) * stride + offset + r % per].
+struct OutMap {
+    int per, stride, offset;
+};
+
+// Device pointers carved out of the caller's workspace.
+struct DevState {
+    float *F, *SE, *SG, *A, *Y, *Yprev, *Yc, *best_x, *best_y, *partial;
+    int32_t *fresh, *top, *bottom, *tie, *cstar, *improved, *reinit, *src, *best_f, *best_gen,
+        *best_upd, *ctrl;
+    float *Xp;         // [S_pad][in_pad] packed inputs (FP32 precision)
+    uint16_t *Xb;      // [S_pad][in_pad] packed inputs as bf16 bits (BF16 precision)
+    float *Ypad;       // [S_pad][out] MSE targets (zero padded)
+    int32_t *Lpad;     // [S_pad] CE labels (-1 padded)
+};
+
+// Population shape and algorithm constants as the kernels need them.
+struct Shape {
+    int B, N, lam, G, m, k, BN, C;     // C = lam + G candidates per firework
+    int D, Dp;                         // spark length and padded row pitch (floats)
+    float inv_k, boost, amp_up, amp_down, amp0;
+    int T, loser_out, use_target;
+    float target;
+    Box box;
+    uint2 key;
+};
+
+// MLP problem as the fitness kernels need it.
+struct Net {
+    int nl;                            // layers
+    int fi[MAXL], fo[MAXL];            // in/out width per layer
+    int woff[MAXL], boff[MAXL];        // offsets of W_l and b_l inside a spark
+    int act[MAXL];                     // activation after layer l (identity for the last)
+    int vec[MAXL];                     // 1 when W_l rows allow 16-byte loads
+    int loss;                          // 0 MSE, 1 CE
+    int S, S_pad, in_pad;              // samples, padded samples, padded input width
+    int bf16;                          // precision
+    float inv_norm;                    // 1/(S*out) for MSE, 1/S for CE
+};
+
+// A chosen fitness kernel and its launch geometry for a given row count.
+struct FitPlan {
+    const void *kernel;   // __global__ function
+    int P;                // 16-sample slabs per wave in flight
+    int bpr;              // blocks per spark row
+    int spb;              // samples per block
+    int rows;
+};
+
+// ---- spark.hip
+hipError_t launch_init_positions(const Shape &s, const DevState &d, hipStream_t st);
+hipError_t launch_explode(const Shape &s, const DevState &d, hipStream_t st);
+
+// ---- guide.hip
+hipError_t launch_rank(const Shape &s, const DevState &d, hipStream_t st);
+hipError_t launch_guide(const Shape &s, const DevState &d, hipStream_t st);
+
+// ---- select.hip
+hipError_t launch_select(const Shape &s, const DevState &d, hipStream_t st);
+hipError_t launch_init_select(const Shape &s, const DevState &d, hipStream_t st);
+hipError_t launch_apply(const Shape &s, const DevState &d, hipStream_t st);
+hipError_t launch_finish(const DevState &d, int advance, hipStream_t st);
+hipError_t launch_store_fitness(const float *src, int rows, OutMap map, float *out,
+                                const int32_t *ctrl, hipStream_t st);
+
+// ---- fitness.hip
+// Choose the kernel for the network (false if the shape is not compiled in).
+bool fit_select(const Net &net, int rows, FitPlan *plan);
+// Fitness of `rows` sparks into out[map(row)]: the GEMM kernel writes one partial
+// per (row, block); the finalisation sums them in order.  `mid` (optional) is
+// recorded between the two launches.
+hipError_t launch_fitness(const Net &net, const FitPlan &plan, const DevState &d,
+                          const float *W, size_t ld, int rows, OutMap map, float *out,
+                          hipStream_t st, hipEvent_t mid = nullptr);
+hipError_t launch_pack_problem(const Net &net, const float *x, const float *y,
+                               const int32_t *labels, const DevState &d, hipStream_t st);
+// largest partial-sum count per row any plan may use
+int fit_max_bpr();
+
+}  // namespace mgfwa

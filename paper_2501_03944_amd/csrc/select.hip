@@ -1,0 +1,253 @@
+// Selection, dynamic amplitude, loser-out tournament and best-so-far (Alg. 1:
+// select the best individual of each population, perform the loser-out
+// tournament; the loop returns the best fitness and its position).
+//
+// k_select  -- one block per population.  Per firework: Yprev <- Y; c* =
+//              argmin over the lambda+G candidates (lower index on ties); move
+//              when Y[c*] < Y, amplitude *amp_up, else *amp_down.  Then b = the
+//              population best; every other firework that was not re-initialised
+//              in the previous generation is a loser when
+//              fma(-(Yprev - Y), max(T - t, 0), Y) > Y_b and restarts with A0 and
+//              fitness +inf.  Decisions go to src/reinit; rows move in k_apply.
+// k_apply   -- grid over (firework, 4-coordinate chunk): copies the chosen
+//              candidate row, or draws the restart position, and refreshes the
+//              best-so-far row.
+// k_finish  -- one thread: advances the generation counter, raises the stop flag.
+#include "internal.h"
+
+namespace mgfwa {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int MAX_GRID_Y = 65535;
+constexpr int SRC_NONE = -1;
+
+__device__ void population_best(const float *Y, int N, int *fb_out, float *yb_out)
+{
+    // lowest fitness, lower index on ties; N is small, one thread scans in order
+    int fb = 0;
+    float yb = Y[0];
+    for (int f = 1; f < N; ++f)
+        if (Y[f] < yb) {
+            yb = Y[f];
+            fb = f;
+        }
+    *fb_out = fb;
+    *yb_out = yb;
+}
+
+__global__ __launch_bounds__(TPB) void k_select(Shape s, float *__restrict__ Yc, float *__restrict__ Y,
+                                                float *__restrict__ Yprev, float *__restrict__ A,
+                                                int32_t *__restrict__ fresh,
+                                                int32_t *__restrict__ cstar,
+                                                int32_t *__restrict__ improved,
+                                                int32_t *__restrict__ reinit,
+                                                int32_t *__restrict__ src,
+                                                float *__restrict__ best_y,
+                                                int32_t *__restrict__ best_f,
+                                                int32_t *__restrict__ best_gen,
+                                                int32_t *__restrict__ best_upd,
+                                                int32_t *__restrict__ ctrl)
+{
+    if (ctrl[CTRL_DONE]) return;
+    const int t = ctrl[CTRL_GEN] + 1;
+    const int b = blockIdx.x, N = s.N;
+    __shared__ int s_fb;
+    __shared__ float s_yb;
+    for (int f = threadIdx.x; f < N; f += blockDim.x) {
+        const int gf = b * N + f;
+        const float *yc = Yc + (size_t)gf * s.C;
+        const float yold = Y[gf];
+        Yprev[gf] = yold;
+        int cs = 0;
+        float ymin = yc[0];
+        for (int c = 1; c < s.C; ++c) {
+            const float v = yc[c];
+            if (v < ymin) {
+                ymin = v;
+                cs = c;
+            }
+        }
+        cstar[gf] = cs;
+        reinit[gf] = 0;
+        if (ymin < yold) {
+            Y[gf] = ymin;
+            A[gf] = A[gf] * s.amp_up;
+            improved[gf] = 1;
+            src[gf] = cs;
+        } else {
+            A[gf] = A[gf] * s.amp_down;
+            improved[gf] = 0;
+            src[gf] = SRC_NONE;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) population_best(Y + (size_t)b * N, N, &s_fb, &s_yb);
+    __syncthreads();
+    const int fb = s_fb;
+    const float yb = s_yb;
+    const float remaining = (float)(t < s.T ? s.T - t : 0);
+    for (int f = threadIdx.x; f < N; f += blockDim.x) {
+        const int gf = b * N + f;
+        const int was_fresh = fresh[gf];
+        fresh[gf] = 0;
+        if (!s.loser_out || f == fb || was_fresh) continue;
+        const float improvement = Yprev[gf] - Y[gf];
+        const float predicted = __builtin_fmaf(-improvement, remaining, Y[gf]);
+        if (predicted > yb) {
+            reinit[gf] = 1;
+            src[gf] = SRC_NONE;
+            A[gf] = s.amp0;
+            Y[gf] = __int_as_float(0x7f800000);
+            fresh[gf] = 1;
+        }
+    }
+    if (threadIdx.x == 0) {
+        const int upd = yb < best_y[b];
+        best_upd[b] = upd;
+        if (upd) {
+            best_y[b] = yb;
+            best_f[b] = fb;
+            best_gen[b] = t;
+        }
+        if (s.use_target && best_y[b] <= s.target) atomicOr(&ctrl[CTRL_DONE_PENDING], 1);
+    }
+}
+
+// After the initial fitness: Yprev = Y, best-so-far = population best at generation 0.
+__global__ __launch_bounds__(TPB) void k_init_select(Shape s, const float *__restrict__ Y,
+                                                     float *__restrict__ Yprev,
+                                                     int32_t *__restrict__ fresh,
+                                                     int32_t *__restrict__ reinit,
+                                                     int32_t *__restrict__ src,
+                                                     float *__restrict__ best_y,
+                                                     int32_t *__restrict__ best_f,
+                                                     int32_t *__restrict__ best_gen,
+                                                     int32_t *__restrict__ best_upd,
+                                                     int32_t *__restrict__ ctrl)
+{
+    const int b = blockIdx.x, N = s.N;
+    for (int f = threadIdx.x; f < N; f += blockDim.x) {
+        const int gf = b * N + f;
+        Yprev[gf] = Y[gf];
+        fresh[gf] = 0;
+        reinit[gf] = 0;
+        src[gf] = SRC_NONE;
+    }
+    if (threadIdx.x == 0) {
+        int fb;
+        float yb;
+        population_best(Y + (size_t)b * N, N, &fb, &yb);
+        best_y[b] = yb;
+        best_f[b] = fb;
+        best_gen[b] = 0;
+        best_upd[b] = 1;
+        if (s.use_target && yb <= s.target) atomicOr(&ctrl[CTRL_DONE_PENDING], 1);
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_apply(Shape s, float *__restrict__ F,
+                                               const float *__restrict__ SE,
+                                               const float *__restrict__ SG,
+                                               const int32_t *__restrict__ src,
+                                               const int32_t *__restrict__ reinit,
+                                               const int32_t *__restrict__ best_f,
+                                               const int32_t *__restrict__ best_upd,
+                                               float *__restrict__ best_x,
+                                               const int32_t *__restrict__ ctrl)
+{
+    if (ctrl[CTRL_DONE]) return;
+    const uint32_t t = (uint32_t)ctrl[CTRL_GEN] + 1u;
+    const int chunk = blockIdx.x * TPB + threadIdx.x;
+    if (chunk >= (s.Dp >> 2)) return;
+    for (int gf = blockIdx.y; gf < s.BN; gf += gridDim.y) {
+        const int b = gf / s.N, f = gf % s.N;
+        const int sr = src[gf], ri = reinit[gf];
+        const bool copy_best = best_upd[b] && best_f[b] == f;
+        if (!ri && sr < 0 && !copy_best) continue;
+        float4 *frow = reinterpret_cast<float4 *>(F + (size_t)gf * s.Dp);
+        float4 v;
+        if (ri) {
+            const uint4 r = draw4(s.key, (uint32_t)chunk, (uint32_t)gf, t, TAG_REINIT);
+            const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+            float e4[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                e4[e] = box_uniform(s.box, u01(w[e]));
+                if (4 * chunk + e >= s.D) e4[e] = 0.0f;
+            }
+            v = make_float4(e4[0], e4[1], e4[2], e4[3]);
+            frow[chunk] = v;
+        } else if (sr >= 0) {
+            const float *row = sr < s.lam ? SE + ((size_t)gf * s.lam + sr) * s.Dp
+                                          : SG + ((size_t)gf * s.G + (sr - s.lam)) * s.Dp;
+            v = reinterpret_cast<const float4 *>(row)[chunk];
+            frow[chunk] = v;
+        } else {
+            v = frow[chunk];
+        }
+        if (copy_best) reinterpret_cast<float4 *>(best_x + (size_t)b * s.Dp)[chunk] = v;
+    }
+}
+
+__global__ void k_finish(int32_t *ctrl, int advance)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (ctrl[CTRL_DONE]) return;
+    if (advance) ctrl[CTRL_GEN] = ctrl[CTRL_GEN] + 1;
+    if (ctrl[CTRL_DONE_PENDING]) ctrl[CTRL_DONE] = 1;
+}
+
+__global__ __launch_bounds__(TPB) void k_store_fitness(const float *__restrict__ in, int rows,
+                                                       OutMap map, float *__restrict__ out,
+                                                       const int32_t *__restrict__ ctrl)
+{
+    if (ctrl && ctrl[CTRL_DONE]) return;
+    const int r = blockIdx.x * TPB + threadIdx.x;
+    if (r >= rows) return;
+    out[(size_t)(r / map.per) * map.stride + map.offset + r % map.per] = canon_fitness(in[r]);
+}
+
+}  // namespace
+
+hipError_t launch_select(const Shape &s, const DevState &d, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_select, dim3(s.B), dim3(TPB), 0, st, s, d.Yc, d.Y, d.Yprev, d.A, d.fresh,
+                       d.cstar, d.improved, d.reinit, d.src, d.best_y, d.best_f, d.best_gen,
+                       d.best_upd, d.ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_select(const Shape &s, const DevState &d, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_init_select, dim3(s.B), dim3(TPB), 0, st, s, d.Y, d.Yprev, d.fresh,
+                       d.reinit, d.src, d.best_y, d.best_f, d.best_gen, d.best_upd, d.ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply(const Shape &s, const DevState &d, hipStream_t st)
+{
+    const int nchunk = s.Dp >> 2;
+    dim3 grid((nchunk + TPB - 1) / TPB, s.BN < MAX_GRID_Y ? s.BN : MAX_GRID_Y);
+    hipLaunchKernelGGL(k_apply, grid, dim3(TPB), 0, st, s, d.F, d.SE, d.SG, d.src, d.reinit,
+                       d.best_f, d.best_upd, d.best_x, d.ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const DevState &d, int advance, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, d.ctrl, advance);
+    return hipGetLastError();
+}
+
+hipError_t launch_store_fitness(const float *src, int rows, OutMap map, float *out,
+                                const int32_t *ctrl, hipStream_t st)
+{
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_store_fitness, dim3((rows + TPB - 1) / TPB), dim3(TPB), 0, st, src, rows,
+                       map, out, ctrl);
+    return hipGetLastError();
+}
+
+}  // namespace mgfwa

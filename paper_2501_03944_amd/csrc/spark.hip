@@ -1,0 +1,102 @@
+// Initial fireworks and explosion sparks (Alg. 1: random initialisation, the
+// explosion step and the random mapping of explosion sparks).
+//
+// One thread produces four consecutive coordinates from one Philox block and
+// writes them as a single 16-byte store, so a wavefront writes 1 KiB of a spark
+// row contiguously.  Grid: x over the row's 4-coordinate chunks, y over rows.
+#include "internal.h"
+
+namespace mgfwa {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int MAX_GRID_Y = 65535;
+
+__global__ __launch_bounds__(TPB) void k_init_positions(float *__restrict__ F,
+                                                        float *__restrict__ A, int rows, int D,
+                                                        int Dp, uint2 key, Box box, float amp0)
+{
+    const int chunk = blockIdx.x * TPB + threadIdx.x;
+    const int nchunk = Dp >> 2;
+    for (int row = blockIdx.y; row < rows; row += gridDim.y) {
+        if (chunk == 0) A[row] = amp0;
+        if (chunk >= nchunk) continue;
+        const uint4 r = draw4(key, (uint32_t)chunk, (uint32_t)row, 0u, TAG_INIT);
+        const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            v[e] = box_uniform(box, u01(w[e]));
+            if (4 * chunk + e >= D) v[e] = 0.0f;
+        }
+        reinterpret_cast<float4 *>(F + (size_t)row * Dp)[chunk] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+}
+
+// Explosion spark j of firework f (row = f*lambda + j) for generation t+1:
+// s = fma(A_f, 2u - 1, x_f); out-of-box coordinates take a uniform draw from
+// the mapping stream of the same (chunk, row, generation).
+__global__ __launch_bounds__(TPB) void k_explode(const float *__restrict__ F,
+                                                 const float *__restrict__ A,
+                                                 float *__restrict__ SE, int lam, int rows, int D,
+                                                 int Dp, uint2 key, Box box,
+                                                 const int32_t *__restrict__ ctrl)
+{
+    if (ctrl[CTRL_DONE]) return;
+    const uint32_t tn = (uint32_t)ctrl[CTRL_GEN] + 1u;
+    const int chunk = blockIdx.x * TPB + threadIdx.x;
+    if (chunk >= (Dp >> 2)) return;
+    for (int row = blockIdx.y; row < rows; row += gridDim.y) {
+        const int gf = row / lam;
+        const float amp = A[gf];
+        const float4 x4 = reinterpret_cast<const float4 *>(F + (size_t)gf * Dp)[chunk];
+        const float x[4] = {x4.x, x4.y, x4.z, x4.w};
+        const uint4 r = draw4(key, (uint32_t)chunk, (uint32_t)row, tn, TAG_EXPL);
+        const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+        float s[4];
+        bool any_out = false;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float v = 2.0f * u01(w[e]) - 1.0f;
+            s[e] = __builtin_fmaf(amp, v, x[e]);
+            any_out |= outside(box, s[e]);
+        }
+        if (any_out) {
+            const uint4 r2 = draw4(key, (uint32_t)chunk, (uint32_t)row, tn, TAG_EXPL_MAP);
+            const uint32_t w2[4] = {r2.x, r2.y, r2.z, r2.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (outside(box, s[e])) s[e] = box_uniform(box, u01(w2[e]));
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (4 * chunk + e >= D) s[e] = 0.0f;
+        reinterpret_cast<float4 *>(SE + (size_t)row * Dp)[chunk] = make_float4(s[0], s[1], s[2], s[3]);
+    }
+}
+
+dim3 row_grid(int Dp, int rows)
+{
+    const int nchunk = Dp >> 2;
+    return dim3((nchunk + TPB - 1) / TPB, rows < MAX_GRID_Y ? rows : MAX_GRID_Y);
+}
+
+}  // namespace
+
+hipError_t launch_init_positions(const Shape &s, const DevState &d, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_init_positions, row_grid(s.Dp, s.BN), dim3(TPB), 0, st, d.F, d.A, s.BN,
+                       s.D, s.Dp, s.key, s.box, s.amp0);
+    return hipGetLastError();
+}
+
+hipError_t launch_explode(const Shape &s, const DevState &d, hipStream_t st)
+{
+    const int rows = s.BN * s.lam;
+    hipLaunchKernelGGL(k_explode, row_grid(s.Dp, rows), dim3(TPB), 0, st, d.F, d.A, d.SE, s.lam,
+                       rows, s.D, s.Dp, s.key, s.box, d.ctrl);
+    return hipGetLastError();
+}
+
+}  // namespace mgfwa

@@ -1,0 +1,128 @@
+"""Helpers for the GPU parity tests: oracle and HIP contexts with one configuration.
+
+The oracle never receives a value produced by the HIP path; the HIP path may be
+fed the oracle's fitness through the library's tell entry point.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import oracle as O
+
+FIT_RTOL = 1e-5       # FP32 fitness tolerance (relative)
+FIT_ATOL = 1e-7       # absolute floor for losses near zero
+
+
+def require_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("GPU tests need a ROCm device")
+    from paper_2501_03944_amd import mgfwa as M
+    M.lib()            # raises if the library is missing: no fallback
+    return torch, M
+
+
+def make_pair(wl, n_populations=1, n_fireworks=None, n_sparks=None, n_guiding=None, sigma=0.2,
+              boost=1.0, amp_up=1.2, amp_down=0.9, T=None, seed=0, loser_out=True, target=None,
+              external=False, precision="fp32", with_oracle=True):
+    torch, M = require_gpu()
+    N = n_fireworks or wl.n_fireworks
+    lam = n_sparks or wl.n_sparks
+    G = n_guiding or wl.n_guiding
+    T = T or wl.generations
+    o = None
+    if with_oracle:
+        p = O.Problem.from_workload(wl)
+        o = O.Oracle(p, B=n_populations, N=N, lam=lam, G=G, sigma=sigma, boost=boost,
+                     amp_up=amp_up, amp_down=amp_down, lb=wl.lb, ub=wl.ub, T=T, seed=seed,
+                     loser_out=int(loser_out), use_target=int(target is not None),
+                     target_loss=0.0 if target is None else target)
+    g = M.MGFWA(wl.widths, wl.acts, wl.loss, wl.x, wl.y, wl.labels, n_populations=n_populations,
+                n_fireworks=N, n_sparks=lam, n_guiding=G, sigma=sigma, boost=boost,
+                amp_up=amp_up, amp_down=amp_down, lb=wl.lb, ub=wl.ub, max_generations=T,
+                loser_out=loser_out, precision=precision, external_fitness=external,
+                target_loss=target, seed=seed)
+    return o, g
+
+
+def gpu_rows(t, D):
+    """Host copy of a [rows, Dp] device view; checks that the padding is zero."""
+    a = t.cpu().numpy()
+    assert np.all(a[:, D:] == 0.0), "row padding must stay zero"
+    return a[:, :D]
+
+
+def assert_bits(a, b, what):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    assert a.shape == b.shape, (what, a.shape, b.shape)
+    if a.dtype.kind == "f":
+        same = (a.view(np.uint32 if a.dtype == np.float32 else np.uint64) ==
+                b.astype(a.dtype).view(np.uint32 if a.dtype == np.float32 else np.uint64))
+    else:
+        same = a == b
+    if not np.all(same):
+        idx = np.argwhere(~same)[:5]
+        raise AssertionError(f"{what}: {int((~same).sum())} mismatches, first at {idx.tolist()}: "
+                             f"{[a[tuple(i)] for i in idx]} vs {[b[tuple(i)] for i in idx]}")
+
+
+def assert_fitness_close(got, want64, what, rtol=FIT_RTOL, atol=FIT_ATOL):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want64, dtype=np.float64)
+    err = np.abs(got - want)
+    bound = rtol * np.abs(want) + atol
+    bad = ~(err <= bound)
+    if np.any(bad):
+        i = np.argwhere(bad)[:5]
+        raise AssertionError(f"{what}: {int(bad.sum())}/{bad.size} outside tolerance; "
+                             f"max rel err {float((err / np.maximum(np.abs(want), 1e-30)).max()):.3e}; "
+                             f"first {i.tolist()}: {got[tuple(i[0])]} vs {want[tuple(i[0])]}")
+
+
+def compare_state(ov, gs, D, B, what, with_sparks=True):
+    """Bit-exact comparison of the oracle view and the GPU state (host copies)."""
+    F = gs["F"][:, :D]
+    assert np.all(gs["F"][:, D:] == 0)
+    assert_bits(F, ov["F"], f"{what} F")
+    for k in ("A", "Y", "Yprev"):
+        assert_bits(gs[k], ov[k], f"{what} {k}")
+    for k in ("fresh",):
+        assert_bits(gs[k], ov[k], f"{what} {k}")
+    assert_bits(gs["best_y"], ov["best_y"], f"{what} best_y")
+    assert_bits(gs["best_f"], ov["best_f"], f"{what} best_f")
+    assert_bits(gs["best_gen"], ov["best_gen"], f"{what} best_gen")
+    assert_bits(gs["best_x"][:, :D], ov["best_x"], f"{what} best_x")
+    if with_sparks:
+        assert_bits(gs["SE"][:, :D], ov["SE"], f"{what} SE")
+        assert_bits(gs["SG"][:, :D], ov["SG"], f"{what} SG")
+
+
+def near_tie_present(prev, cur, lam, G, m, k, rel=2 * FIT_RTOL):
+    """True when some decision of the oracle's last generation compared two
+    fitness values within `rel` of each other (either branch is then valid)."""
+    def close(a, b):
+        a, b = float(a), float(b)
+        if not (np.isfinite(a) and np.isfinite(b)):
+            return False
+        return abs(a - b) <= rel * max(abs(a), abs(b)) + 1e-30
+
+    Yc = cur["Yc"]
+    BN = Yc.shape[0]
+    for gf in range(BN):
+        row = Yc[gf]
+        # guiding cut: ranks k-1 / k and m-k-1 / m-k inside each group
+        for g in range(G):
+            grp = np.sort(row[g * m:(g + 1) * m].astype(np.float64))
+            if close(grp[k - 1], grp[k]) or close(grp[m - k - 1], grp[m - k]):
+                return True
+        srt = np.sort(row.astype(np.float64))
+        if close(srt[0], srt[1]):
+            return True                       # argmin over candidates
+        if close(srt[0], prev["Y"][gf]):
+            return True                       # improvement test
+    Y = cur["Y"]
+    fin = np.sort(Y[np.isfinite(Y)].astype(np.float64))
+    if fin.size > 1 and close(fin[0], fin[1]):
+        return True                           # population best
+    return False

@@ -1,0 +1,90 @@
+"""C-ABI library: loads, exports every declared symbol, validates on the host.
+
+No GPU needed: only entry points that do no device work are called.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2501_03944_amd import inputs
+from paper_2501_03944_amd import mgfwa as M
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "mgfwa.h")) as fh:
+        text = fh.read()
+    return re.findall(r"MGFWA_API\s+[\w\s\*]+?\b(mgfwa_\w+)\s*\(", text)
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 14
+    lib = ctypes.CDLL(M.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_no_stray_exports():
+    # the only default-visibility C symbols are the declared mgfwa_ entry points
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", M.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    ours = {s for s in exported if s.startswith("mgfwa_")}
+    assert ours == set(_declared())
+
+
+def _cfg2_problem():
+    wl = inputs.gaussian_mixture(n_samples=64)
+    return M.make_problem(wl.widths, wl.acts, wl.loss, wl.n_samples, 1, 0, 1)
+
+
+def test_workspace_bytes_and_validation():
+    p = _cfg2_problem()
+    good = M.make_config(n_fireworks=8, n_sparks=256)
+    nb = M.mgfwa_workspace_bytes(good, p)
+    D = 64 * 128 + 128 + 128 * 128 + 128 + 128 * 10 + 10
+    assert D == 26122
+    Dp = (D + 63) // 64 * 64
+    assert nb >= 8 * 256 * Dp * 4 + 8 * 4 * Dp * 4 + 8 * Dp * 4
+    bad = [dict(n_sparks=30, n_guiding=4), dict(n_sparks=4, n_guiding=4), dict(sigma=0.0),
+           dict(sigma=0.6), dict(lb=5.0, ub=-5.0), dict(max_generations=0), dict(n_fireworks=0),
+           dict(precision=7), dict(amp_up=0.0)]
+    for kw in bad:
+        kw2 = dict(n_fireworks=8, n_sparks=256)
+        kw2.update(kw)
+        assert M.mgfwa_workspace_bytes(M.make_config(**kw2), p) == 0, kw
+        assert M.mgfwa_last_error() != ""
+
+
+def test_problem_validation():
+    c = M.make_config()
+    assert M.mgfwa_workspace_bytes(c, M.make_problem((4, 3, 1), ("relu",), "ce", 8, 1, 0, 1)) == 0
+    assert "cross-entropy" in M.mgfwa_last_error()
+    assert M.mgfwa_workspace_bytes(c, M.make_problem((4, 3, 1), ("relu",), "mse", 8, 1, 0, 0)) == 0
+    assert "y_dev" in M.mgfwa_last_error()
+    assert M.mgfwa_workspace_bytes(c, M.make_problem((4, 300, 1), ("relu",), "mse", 8, 1, 1, 0)) == 0
+    assert M.mgfwa_workspace_bytes(c, M.make_problem((4, 3, 1), (9,), "mse", 8, 1, 1, 0)) == 0
+    # external fitness without sample data only needs the shape
+    ce = M.make_config(external_fitness=True)
+    assert M.mgfwa_workspace_bytes(ce, M.make_problem((4, 3, 1), ("relu",), "mse", 0)) > 0
+
+
+def test_init_rejects_before_touching_the_device():
+    p = _cfg2_problem()
+    c = M.make_config(n_fireworks=8, n_sparks=256)
+    nb = M.mgfwa_workspace_bytes(c, p)
+    with pytest.raises(M.MgfwaError) as e:
+        M.mgfwa_init(c, p, 4096, nb - 1, 0)
+    assert e.value.status == M.ENOMEM
+    with pytest.raises(M.MgfwaError) as e:
+        M.mgfwa_init(c, p, 4096 + 8, nb, 0)      # misaligned workspace
+    assert e.value.status == M.ENOMEM
+    wide = M.make_problem((4, 300, 1), ("relu",), "mse", 8, 1, 1, 0)
+    with pytest.raises(M.MgfwaError) as e:
+        M.mgfwa_init(c, wide, 4096, 1 << 30, 0)
+    assert e.value.status == M.EUNSUPPORTED

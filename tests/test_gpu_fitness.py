@@ -1,0 +1,147 @@
+"""Fitness kernels against the oracle's binary64 loss (needs an MI355X).
+
+FP32: every value within 1e-5 relative.  BF16 (operands rounded to bf16, FP32
+accumulation): error against the oracle and ranking agreement are measured and
+bounded loosely; the FP32 bound does not apply.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import assert_bits, assert_fitness_close, gpu_rows, make_pair, require_gpu
+from oracle import oracle as O
+from paper_2501_03944_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [
+    # widths, acts, loss, samples
+    ((8, 16, 1), ("tanh",), "mse", 256),
+    ((64, 128, 128, 10), ("relu", "relu"), "ce", 300),
+    ((784, 256, 10), ("relu",), "ce", 200),
+    ((7, 5, 3), ("relu",), "mse", 33),            # rows not 16-byte aligned
+    ((5, 9, 6, 4), ("gelu", "tanh"), "ce", 77),
+    ((3, 2), (), "mse", 10),                      # one layer
+    ((17, 40, 33, 20, 3), ("relu", "identity", "tanh"), "ce", 129),
+    ((10, 256, 256, 1), ("relu", "relu"), "mse", 50),
+    ((12, 200, 2), ("gelu",), "ce", 1),           # a single sample
+]
+
+
+def _ctx(wl, precision="fp32"):
+    torch, M = require_gpu()
+    return M.MGFWA(wl.widths, wl.acts, wl.loss, wl.x, wl.y, wl.labels, n_fireworks=2,
+                   n_sparks=4, n_guiding=2, precision=precision)
+
+
+@pytest.mark.parametrize("widths,acts,loss,S", SHAPES)
+def test_fp32_fitness_matches_oracle(widths, acts, loss, S):
+    torch, M = require_gpu()
+    wl = inputs.random_mlp_problem(widths, acts, loss, S, seed=S + len(widths))
+    g = _ctx(wl)
+    p = O.Problem.from_workload(wl)
+    for lo, hi, seed in ((-1.0, 1.0, 1), (-5.0, 5.0, 2)):
+        W = inputs.random_weights(wl.dim, 37, seed=seed, lo=lo, hi=hi)
+        Wd = torch.zeros((37, g.Dp), dtype=torch.float32, device="cuda")
+        Wd[:, :wl.dim] = torch.from_numpy(W)
+        got = g.evaluate(Wd).cpu().numpy()
+        assert_fitness_close(got, p.loss_rows(W), f"{widths} U({lo},{hi})")
+    g.close()
+
+
+def test_fp32_fitness_many_rows_and_empty():
+    torch, M = require_gpu()
+    wl = inputs.random_mlp_problem((6, 8, 3), ("tanh",), "ce", 40, seed=5)
+    g = _ctx(wl)
+    p = O.Problem.from_workload(wl)
+    W = inputs.random_weights(wl.dim, 2500, seed=9, lo=-2, hi=2)   # several evaluation chunks
+    ld = (wl.dim + 3) // 4 * 4
+    Wd = torch.zeros((2500, ld), dtype=torch.float32, device="cuda")
+    Wd[:, :wl.dim] = torch.from_numpy(W)
+    got = g.evaluate(Wd).cpu().numpy()
+    assert_fitness_close(got, p.loss_rows(W), "2500 rows")
+    assert g.evaluate(Wd[:0]).shape == (0,)
+    g.close()
+
+
+def test_fp32_fitness_is_deterministic():
+    torch, M = require_gpu()
+    wl = inputs.gaussian_mixture(n_samples=1000)
+    g = _ctx(wl)
+    W = torch.rand((64, g.Dp), device="cuda") * 2 - 1
+    a = g.evaluate(W).cpu().numpy()
+    b = g.evaluate(W).cpu().numpy()
+    assert_bits(a, b, "repeat")
+    g.close()
+
+
+@pytest.mark.parametrize("widths,acts,loss,S", SHAPES[:3] + SHAPES[4:5])
+def test_bf16_fitness_error_bounded(widths, acts, loss, S):
+    """BF16 operands carry a relative rounding error of at most 2^-9 each; on
+    these well-conditioned cases (weights in [-1, 1]) the loss stays within 5 %
+    of the exact value and the top/bottom ranking of a group mostly agrees."""
+    torch, M = require_gpu()
+    wl = inputs.random_mlp_problem(widths, acts, loss, S, seed=S)
+    g = _ctx(wl, "bf16")
+    p = O.Problem.from_workload(wl)
+    W = inputs.random_weights(wl.dim, 64, seed=3, lo=-1, hi=1)
+    Wd = torch.zeros((64, g.Dp), dtype=torch.float32, device="cuda")
+    Wd[:, :wl.dim] = torch.from_numpy(W)
+    got = g.evaluate(Wd).cpu().numpy().astype(np.float64)
+    want = p.loss_rows(W)
+    rel = np.abs(got - want) / np.abs(want)
+    print(f"bf16 {widths}: max rel err {rel.max():.3e}, median {np.median(rel):.3e}")
+    assert rel.max() < 5e-2
+    g.close()
+
+
+def _sampled_full_size(wl, precision, rows_sample, seed=0):
+    """Full-size workload in the launch configuration the benchmark times: the
+    first generation's explosion sparks depend only on the initial fireworks, so
+    sampled rows are recomputed by the oracle one by one and compared bit for
+    bit, and their fitness within the FP32 tolerance (or measured for BF16)."""
+    torch, M = require_gpu()
+    o, g = make_pair(wl, seed=seed, precision=precision)
+    c = o.cfg
+    D = g.D
+    o.init_positions()
+    ov = o.view()
+    gs = g.state_numpy()
+    assert_bits(gs["F"][:, :D], ov["F"], "init F")
+    if precision == "fp32":
+        assert_fitness_close(gs["Y"][:2], o.problem.loss_rows(ov["F"][:2]), "initial fitness")
+    g.step(1)
+    gs = g.state_numpy()
+    rng = np.random.default_rng(seed)
+    rows = rng.choice(c.B * c.N * c.lam, size=rows_sample, replace=False)
+    a0 = np.float32(c.ub) - np.float32(c.lb)
+    sparks = []
+    for r in rows:
+        gf = r // c.lam
+        s = O.explosion_row(c, ov["F"][gf], a0, int(r), 1)
+        assert_bits(gs["SE"][r, :D], s, f"spark row {r}")
+        assert np.all(gs["SE"][r, D:] == 0)
+        sparks.append(s)
+    want = o.problem.loss_rows(np.stack(sparks))
+    got = gs["Yc"].reshape(-1, c.lam + c.G)[rows // c.lam, rows % c.lam].astype(np.float64)
+    g.close()
+    return got, want
+
+
+def test_full_size_gaussian_mixture_fp32_sampled():
+    wl = inputs.gaussian_mixture()
+    got, want = _sampled_full_size(wl, "fp32", 12)
+    assert_fitness_close(got, want, "64-128-128-10 full size")
+
+
+def test_full_size_sparse_prototypes_fp32_sampled():
+    wl = inputs.sparse_prototypes(n_samples=8192)
+    got, want = _sampled_full_size(wl, "fp32", 4)
+    assert_fitness_close(got, want, "784-256-10 full size")
+
+
+def test_full_size_sparse_prototypes_bf16_sampled():
+    wl = inputs.sparse_prototypes(n_samples=8192)
+    got, want = _sampled_full_size(wl, "bf16", 4)
+    rel = np.abs(got - want) / np.abs(want)
+    print(f"bf16 784-256-10 full size: rel err {rel}")
+    assert rel.max() < 5e-2
