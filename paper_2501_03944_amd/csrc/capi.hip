@@ -356,6 +356,16 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
     }
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
+    int lds_max = 0;
+    HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    dv.net.lds_max = lds_max - 256;   // leave room for the kernels' static LDS
+    if (has_data) {
+        if (!fit_select(dv.net, dv.s.BN, &pi) || !fit_select(dv.net, dv.s.BN * dv.s.lam, &pe) ||
+            !fit_select(dv.net, dv.s.BN * dv.s.G, &pg) ||
+            !fit_select(dv.net, dv.lay.partial_rows, &pv))
+            return fail(MGFWA_EUNSUPPORTED, "no compiled fitness kernel covers this MLP shape");
+        for (const FitPlan *fp : {&pi, &pe, &pg, &pv}) HIP_TRY(fit_prepare(*fp));
+    }
 
     mgfwa_ctx *c = new mgfwa_ctx();
     c->cfg = *config;
@@ -573,6 +583,7 @@ mgfwa_status mgfwa_evaluate(mgfwa_ctx *c, const float *w, int rows, int ld, floa
         FitPlan plan;
         if (!fit_select(c->net, nr, &plan))
             return fail(MGFWA_EUNSUPPORTED, "no compiled fitness kernel covers this MLP shape");
+        HIP_TRY(fit_prepare(plan));
         mgfwa_status r = fit_rows(c, plan, w + (size_t)r0 * ld, (size_t)ld, nr, kFlat, out + r0,
                                   c->stream);
         if (r) return r;

@@ -15,15 +15,25 @@
 // and the loss run in the accumulator registers; a block reduces its samples'
 // losses in a fixed order into one partial per (spark, block) and a second
 // kernel sums the partials of a spark in order.  No floating-point atomics:
-// the result is deterministic and independent of the launch geometry's timing.
+// the result is deterministic.
 //
 // FP32:  v_mfma_f32_16x16x4_f32,  K step 4 per MFMA (4 MFMAs per 16-row block).
 // BF16:  v_mfma_f32_16x16x32_bf16, K step 32; operands rounded to bf16 (RNE),
 //        FP32 accumulation, bias/activation/loss in FP32.
 //
-// Template parameters fix the number of 16-row output blocks of every layer
-// (R1..R4, 0 = absent) and the number P of 16-sample slabs a wavefront keeps in
-// flight, so that all activation tiles live in registers.
+// Weight source (template flag WL):
+//   WL = true   the block copies its spark's weights once into LDS, every
+//               layer zero-padded to whole 16-row blocks and to the padded K,
+//               with a row pitch of an odd number of 16-byte (FP32) or 8-byte
+//               (BF16) units so the fragment reads of a quarter-wavefront hit
+//               distinct banks; biases in an FP32 area after the weights.
+//   WL = false  fragments are read from the spark row in global memory (L2),
+//               with row/column guards; used when the weights exceed the LDS.
+//
+// Template parameters also fix the number of 16-row output blocks of every
+// layer (R1..R4, 0 = absent), the wavefronts per block (NW) and the number P of
+// 16-sample slabs a wavefront keeps in flight, so that all activation tiles
+// live in registers.
 #pragma once
 
 #include "internal.h"
@@ -36,9 +46,6 @@ namespace fit {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int TPB = 256;   // 4 wavefronts
-constexpr int WAVES = TPB / 64;
-
 struct FitArgs {
     const float *W;        // spark rows
     size_t ld;             // row pitch (floats)
@@ -48,6 +55,10 @@ struct FitArgs {
     int in_pad, S, S_pad;
     int nl;
     int fi[MAXL], fo[MAXL], woff[MAXL], boff[MAXL], act[MAXL], vec[MAXL];
+    // LDS layout (WL kernels), per layer: weight offset and row pitch in
+    // elements of the storage type, padded rows and columns, bias offset (floats)
+    int lw[MAXL], lpitch[MAXL], lrows[MAXL], lcols[MAXL], lb[MAXL];
+    int lbias_byte;        // start of the FP32 bias area
     int loss;
     const float *Y;        // [S_pad][out]
     const int32_t *lab;    // [S_pad]
@@ -61,7 +72,8 @@ __device__ __forceinline__ floatx4 zero4()
     return z;
 }
 
-// Four consecutive weights W[row][kbase..kbase+3]; zero outside the layer.
+// Four consecutive weights W[row][kbase..kbase+3] from global memory; zero
+// outside the layer.
 __device__ __forceinline__ floatx4 ldw4(const float *p, bool row_ok, int kbase, int fi, int vec)
 {
     floatx4 r = zero4();
@@ -86,196 +98,265 @@ __device__ __forceinline__ bf16x8 to_bf16x8(floatx4 lo, floatx4 hi)
     return r;
 }
 
-__device__ __forceinline__ float act_fn(int act, float z)
-{
-    switch (act) {
-    case 1: return z > 0.0f ? z : 0.0f;
-    case 2: return tanhf(z);
-    case 3: return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
-    default: return z;
+// One lane's view of one layer's weights, anchored at row n of output block 0
+// and column 4g.
+template <bool BF, bool WL>
+struct WView {
+    const float *gp;     // global source (WL = false)
+    const char *sp;      // LDS source (WL = true)
+    int fi, fo, vec, pitch, n, gq;
+
+    __device__ __forceinline__ WView(const FitArgs &a, const float *w, const char *smem, int l,
+                                     int n_, int g_)
+    {
+        n = n_;
+        gq = g_;
+        fi = a.fi[l];
+        fo = a.fo[l];
+        vec = a.vec[l];
+        pitch = a.lpitch[l];
+        if constexpr (WL) {
+            constexpr int es = BF ? 2 : 4;
+            sp = smem + (size_t)(a.lw[l] + n * pitch + 4 * g_) * es;
+            gp = nullptr;
+        } else {
+            gp = w + a.woff[l] + (size_t)n * fi + 4 * g_;
+            sp = nullptr;
+        }
     }
+
+    // FP32 fragment: row 16rb + n, k = 16kb + 4g .. +3
+    __device__ __forceinline__ floatx4 f32(int rb, int kb) const
+    {
+        if constexpr (WL) {
+            return *reinterpret_cast<const floatx4 *>(sp + (size_t)(16 * rb * pitch + 16 * kb) * 4);
+        } else {
+            const bool ok = 16 * rb + n < fo;
+            return ldw4(gp + (size_t)(ok ? 16 * rb : 0) * fi + 16 * kb, ok, 16 * kb + 4 * gq, fi,
+                        vec);
+        }
+    }
+
+    // BF16 fragment: row 16rb + n, k = 32kb + 4g .. +3 then 32kb + 16 + 4g .. +3
+    __device__ __forceinline__ bf16x8 b16(int rb, int kb) const
+    {
+        if constexpr (WL) {
+            const char *p = sp + (size_t)(16 * rb * pitch + 32 * kb) * 2;
+            const uint2 lo = *reinterpret_cast<const uint2 *>(p);
+            const uint2 hi = *reinterpret_cast<const uint2 *>(p + 32);
+            return __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+        } else {
+            const bool ok = 16 * rb + n < fo;
+            const float *p = gp + (size_t)(ok ? 16 * rb : 0) * fi + 32 * kb;
+            return to_bf16x8(ldw4(p, ok, 32 * kb + 4 * gq, fi, vec),
+                             ldw4(p + 16, ok, 32 * kb + 16 + 4 * gq, fi, vec));
+        }
+    }
+};
+
+// Copy the spark's weights into LDS (zero-padded layout) and its biases into
+// the FP32 bias area.
+template <bool BF>
+__device__ __forceinline__ void stage_weights(const FitArgs &a, const float *w, char *smem)
+{
+    float *bias = reinterpret_cast<float *>(smem + a.lbias_byte);
+    for (int l = 0; l < a.nl; ++l) {
+        const int fo = a.fo[l], fi = a.fi[l], rows = a.lrows[l], cols = a.lcols[l];
+        const int pitch = a.lpitch[l], base = a.lw[l];
+        const float *src = w + a.woff[l];
+        const int n = rows * cols;
+        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+            const int o = idx / cols, k = idx - o * cols;
+            const float v = (o < fo && k < fi) ? src[(size_t)o * fi + k] : 0.0f;
+            if constexpr (BF)
+                reinterpret_cast<uint16_t *>(smem)[base + o * pitch + k] =
+                    __builtin_bit_cast(uint16_t, (__bf16)v);
+            else
+                reinterpret_cast<float *>(smem)[base + o * pitch + k] = v;
+        }
+        for (int o = threadIdx.x; o < rows; o += blockDim.x)
+            bias[a.lb[l] + o] = o < fo ? w[a.boff[l] + o] : 0.0f;
+    }
+    __syncthreads();
 }
 
 // ---- first layer: B operand from the packed samples ------------------------
-template <int P, int RO>
-__device__ __forceinline__ void layer_x_f32(const FitArgs &a, const float *w, int s0, int n, int g,
-                                            floatx4 (&out)[P][RO])
+template <bool BF, bool WL, int P, int RO, int SCHED = 1>
+__device__ __forceinline__ void layer_x(const FitArgs &a, const WView<BF, WL> &wv, int s0, int n,
+                                        int g, floatx4 (&out)[P][RO])
 {
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
         for (int rb = 0; rb < RO; ++rb) out[p][rb] = zero4();
-    const int fi = a.fi[0], fo = a.fo[0], vec = a.vec[0];
-    const float *xp[P];
+    if constexpr (!BF) {
+        const float *xp[P];
 #pragma unroll
-    for (int p = 0; p < P; ++p) xp[p] = a.X + (size_t)(s0 + 16 * p + n) * a.in_pad + 4 * g;
-    const float *wr[RO];
-    bool rok[RO];
+        for (int p = 0; p < P; ++p) xp[p] = a.X + (size_t)(s0 + 16 * p + n) * a.in_pad + 4 * g;
+        const int nkb = a.in_pad >> 4;
+        for (int kb = 0; kb < nkb; ++kb) {
+            floatx4 bx[P];
 #pragma unroll
-    for (int rb = 0; rb < RO; ++rb) {
-        const int row = 16 * rb + n;
-        rok[rb] = row < fo;
-        wr[rb] = w + a.woff[0] + (size_t)(rok[rb] ? row : 0) * fi + 4 * g;
-    }
-    const int nkb = a.in_pad >> 4;
-    for (int kb = 0; kb < nkb; ++kb) {
-        floatx4 bx[P];
+            for (int p = 0; p < P; ++p) bx[p] = *reinterpret_cast<const floatx4 *>(xp[p] + 16 * kb);
+            floatx4 aw = wv.f32(0, kb);
 #pragma unroll
-        for (int p = 0; p < P; ++p) bx[p] = *reinterpret_cast<const floatx4 *>(xp[p] + 16 * kb);
-        const int kbase = 16 * kb + 4 * g;
+            for (int rb = 0; rb < RO; ++rb) {
+                // fetch the next block's fragment before this block's MFMAs
+                const floatx4 an = SCHED && rb + 1 < RO ? wv.f32(rb + 1, kb) : aw;
+                if constexpr (!SCHED) aw = wv.f32(rb, kb);
 #pragma unroll
-        for (int rb = 0; rb < RO; ++rb) {
-            const floatx4 aw = ldw4(wr[rb] + 16 * kb, rok[rb], kbase, fi, vec);
+                for (int v = 0; v < 4; ++v)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
+                    for (int p = 0; p < P; ++p)
+                        out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[v], bx[p][v], out[p][rb], 0, 0, 0);
+                aw = an;
+            }
+        }
+    } else {
+        // lane (n, g) element e: k = 32kb + 4g + e (e < 4), 32kb + 16 + 4g + e - 4 (e >= 4)
+        const uint16_t *xp[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) xp[p] = a.Xb + (size_t)(s0 + 16 * p + n) * a.in_pad + 4 * g;
+        const int nkb = a.in_pad >> 5;
+        for (int kb = 0; kb < nkb; ++kb) {
+            bf16x8 bx[P];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const uint2 lo = *reinterpret_cast<const uint2 *>(xp[p] + 32 * kb);
+                const uint2 hi = *reinterpret_cast<const uint2 *>(xp[p] + 32 * kb + 16);
+                bx[p] = __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+            }
+            bf16x8 aw = wv.b16(0, kb);
+#pragma unroll
+            for (int rb = 0; rb < RO; ++rb) {
+                const bf16x8 an = SCHED && rb + 1 < RO ? wv.b16(rb + 1, kb) : aw;
+                if constexpr (!SCHED) aw = wv.b16(rb, kb);
 #pragma unroll
                 for (int p = 0; p < P; ++p)
-                    out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[v], bx[p][v], out[p][rb], 0, 0, 0);
-        }
-    }
-}
-
-template <int P, int RO>
-__device__ __forceinline__ void layer_x_bf16(const FitArgs &a, const float *w, int s0, int n,
-                                             int g, floatx4 (&out)[P][RO])
-{
-#pragma unroll
-    for (int p = 0; p < P; ++p)
-#pragma unroll
-        for (int rb = 0; rb < RO; ++rb) out[p][rb] = zero4();
-    const int fi = a.fi[0], fo = a.fo[0], vec = a.vec[0];
-    const uint16_t *xp[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) xp[p] = a.Xb + (size_t)(s0 + 16 * p + n) * a.in_pad + 4 * g;
-    const float *wr[RO];
-    bool rok[RO];
-#pragma unroll
-    for (int rb = 0; rb < RO; ++rb) {
-        const int row = 16 * rb + n;
-        rok[rb] = row < fo;
-        wr[rb] = w + a.woff[0] + (size_t)(rok[rb] ? row : 0) * fi + 4 * g;
-    }
-    const int nkb = a.in_pad >> 5;
-    for (int kb = 0; kb < nkb; ++kb) {
-        // lane (n, g) element e: k = 32kb + 4g + e (e < 4), 32kb + 16 + 4g + e - 4 (e >= 4)
-        bf16x8 bx[P];
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const uint2 lo = *reinterpret_cast<const uint2 *>(xp[p] + 32 * kb);
-            const uint2 hi = *reinterpret_cast<const uint2 *>(xp[p] + 32 * kb + 16);
-            const uint4 q = make_uint4(lo.x, lo.y, hi.x, hi.y);
-            bx[p] = __builtin_bit_cast(bf16x8, q);
-        }
-        const int k0 = 32 * kb + 4 * g;
-#pragma unroll
-        for (int rb = 0; rb < RO; ++rb) {
-            const floatx4 lo = ldw4(wr[rb] + 32 * kb, rok[rb], k0, fi, vec);
-            const floatx4 hi = ldw4(wr[rb] + 32 * kb + 16, rok[rb], k0 + 16, fi, vec);
-            const bf16x8 aw = to_bf16x8(lo, hi);
-#pragma unroll
-            for (int p = 0; p < P; ++p)
-                out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bx[p], out[p][rb], 0, 0, 0);
+                    out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bx[p], out[p][rb], 0, 0, 0);
+                aw = an;
+            }
         }
     }
 }
 
 // ---- later layers: B operand from the previous layer's accumulators ----------
-template <int P, int RI, int RO>
-__device__ __forceinline__ void layer_h_f32(const FitArgs &a, const float *w, int l, int n, int g,
-                                            const floatx4 (&in)[P][RI], floatx4 (&out)[P][RO])
+template <bool BF, bool WL, int P, int RI, int RO, int SCHED = 1>
+__device__ __forceinline__ void layer_h(const WView<BF, WL> &wv, const floatx4 (&in)[P][RI],
+                                        floatx4 (&out)[P][RO])
 {
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
         for (int rb = 0; rb < RO; ++rb) out[p][rb] = zero4();
-    const int fi = a.fi[l], fo = a.fo[l], vec = a.vec[l];
-    const float *wr[RO];
-    bool rok[RO];
+    if constexpr (!BF) {
+        // fragments of (kb, rb) in order; the next one is fetched before the
+        // current one's MFMAs so the LDS latency overlaps matrix work
+        // staged weights are zero-padded to RI blocks: no early exit needed
+        const int nkb = WL ? RI : ((wv.fi + 15) >> 4 < RI ? (wv.fi + 15) >> 4 : RI);
+        floatx4 aw = wv.f32(0, 0);
 #pragma unroll
-    for (int rb = 0; rb < RO; ++rb) {
-        const int row = 16 * rb + n;
-        rok[rb] = row < fo;
-        wr[rb] = w + a.woff[l] + (size_t)(rok[rb] ? row : 0) * fi + 4 * g;
-    }
+        for (int kb = 0; kb < RI; ++kb) {
+            if (kb >= nkb) break;
 #pragma unroll
-    for (int kb = 0; kb < RI; ++kb) {
-        if (16 * kb >= fi) break;
-        const int kbase = 16 * kb + 4 * g;
+            for (int rb = 0; rb < RO; ++rb) {
+                floatx4 an = aw;
+                if constexpr (!SCHED) aw = wv.f32(rb, kb);
+                else if (rb + 1 < RO) an = wv.f32(rb + 1, kb);
+                else if (kb + 1 < nkb) an = wv.f32(0, kb + 1);
 #pragma unroll
-        for (int rb = 0; rb < RO; ++rb) {
-            const floatx4 aw = ldw4(wr[rb] + 16 * kb, rok[rb], kbase, fi, vec);
+                for (int v = 0; v < 4; ++v)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
+                    for (int p = 0; p < P; ++p)
+                        out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[v], in[p][kb][v], out[p][rb], 0, 0, 0);
+                aw = an;
+            }
+        }
+    } else {
+        constexpr int NKB = (RI + 1) / 2;
+        const int nkb = WL ? NKB : ((wv.fi + 31) >> 5 < NKB ? (wv.fi + 31) >> 5 : NKB);
+        bf16x8 aw = wv.b16(0, 0);
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb) {
+            if (kb >= nkb) break;
+            bf16x8 bx[P];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                floatx4 hi = zero4();
+                if (2 * kb + 1 < RI) hi = in[p][(2 * kb + 1) < RI ? 2 * kb + 1 : 0];
+                bx[p] = to_bf16x8(in[p][2 * kb], hi);
+            }
+#pragma unroll
+            for (int rb = 0; rb < RO; ++rb) {
+                bf16x8 an = aw;
+                if constexpr (!SCHED) aw = wv.b16(rb, kb);
+                else if (rb + 1 < RO) an = wv.b16(rb + 1, kb);
+                else if (kb + 1 < nkb) an = wv.b16(0, kb + 1);
 #pragma unroll
                 for (int p = 0; p < P; ++p)
-                    out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[v], in[p][kb][v], out[p][rb], 0, 0, 0);
-        }
-    }
-}
-
-template <int P, int RI, int RO>
-__device__ __forceinline__ void layer_h_bf16(const FitArgs &a, const float *w, int l, int n,
-                                             int g, const floatx4 (&in)[P][RI],
-                                             floatx4 (&out)[P][RO])
-{
-#pragma unroll
-    for (int p = 0; p < P; ++p)
-#pragma unroll
-        for (int rb = 0; rb < RO; ++rb) out[p][rb] = zero4();
-    const int fi = a.fi[l], fo = a.fo[l], vec = a.vec[l];
-    const float *wr[RO];
-    bool rok[RO];
-#pragma unroll
-    for (int rb = 0; rb < RO; ++rb) {
-        const int row = 16 * rb + n;
-        rok[rb] = row < fo;
-        wr[rb] = w + a.woff[l] + (size_t)(rok[rb] ? row : 0) * fi + 4 * g;
-    }
-    constexpr int NKB = (RI + 1) / 2;
-#pragma unroll
-    for (int kb = 0; kb < NKB; ++kb) {
-        if (32 * kb >= fi) break;
-        bf16x8 bx[P];
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const floatx4 lo = in[p][2 * kb];
-            floatx4 hi = zero4();
-            if (2 * kb + 1 < RI) hi = in[p][(2 * kb + 1) < RI ? 2 * kb + 1 : 0];
-            bx[p] = to_bf16x8(lo, hi);
-        }
-        const int k0 = 32 * kb + 4 * g;
-#pragma unroll
-        for (int rb = 0; rb < RO; ++rb) {
-            const floatx4 lo = ldw4(wr[rb] + 32 * kb, rok[rb], k0, fi, vec);
-            const floatx4 hi = ldw4(wr[rb] + 32 * kb + 16, rok[rb], k0 + 16, fi, vec);
-            const bf16x8 aw = to_bf16x8(lo, hi);
-#pragma unroll
-            for (int p = 0; p < P; ++p)
-                out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bx[p], out[p][rb], 0, 0, 0);
+                    out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bx[p], out[p][rb], 0, 0, 0);
+                aw = an;
+            }
         }
     }
 }
 
 // ---- bias, activation, loss ---------------------------------------------------
-template <int P, int R>
-__device__ __forceinline__ void bias_act(const FitArgs &a, const float *w, int l, int g,
-                                         bool apply_act, floatx4 (&h)[P][R])
+template <int ACT>
+__device__ __forceinline__ float act_c(float z)
 {
-    const int fo = a.fo[l];
-    const float *bias = w + a.boff[l];
-    const int act = apply_act ? a.act[l] : 0;
+    if constexpr (ACT == 1) return z > 0.0f ? z : 0.0f;
+    else if constexpr (ACT == 2) return tanhf(z);
+    else if constexpr (ACT == 3) return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+    else return z;
+}
+
+template <int ACT, int P, int R>
+__device__ __forceinline__ void add_act(floatx4 (&h)[P][R], const floatx4 (&bb)[R])
+{
 #pragma unroll
-    for (int rb = 0; rb < R; ++rb) {
-        floatx4 bb;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int o = 16 * rb + 4 * g + v;
-            bb[v] = o < fo ? bias[o] : 0.0f;
-        }
+    for (int rb = 0; rb < R; ++rb)
 #pragma unroll
         for (int p = 0; p < P; ++p)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) h[p][rb][v] = act_fn(act, h[p][rb][v] + bb[v]);
+            for (int v = 0; v < 4; ++v) h[p][rb][v] = act_c<ACT>(h[p][rb][v] + bb[rb][v]);
+}
+
+// Bias then activation of layer l.  ACT >= 0 fixes the hidden activation at
+// compile time; ACT < 0 dispatches once per call on the runtime code.
+template <int ACT, bool WL, int P, int R>
+__device__ __forceinline__ void bias_act(const FitArgs &a, const float *w, const char *smem, int l,
+                                         int g, bool apply_act, floatx4 (&h)[P][R])
+{
+    const int fo = a.fo[l];
+    floatx4 bb[R];
+#pragma unroll
+    for (int rb = 0; rb < R; ++rb) {
+        if constexpr (WL) {
+            bb[rb] = *reinterpret_cast<const floatx4 *>(smem + a.lbias_byte +
+                                                        (size_t)(a.lb[l] + 16 * rb + 4 * g) * 4);
+        } else {
+            const float *bias = w + a.boff[l];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int o = 16 * rb + 4 * g + v;
+                bb[rb][v] = o < fo ? bias[o] : 0.0f;
+            }
+        }
+    }
+    if (!apply_act) {
+        add_act<0, P, R>(h, bb);
+        return;
+    }
+    if constexpr (ACT >= 0) {
+        add_act<ACT, P, R>(h, bb);
+    } else {
+        switch (a.act[l]) {
+        case 1: add_act<1, P, R>(h, bb); break;
+        case 2: add_act<2, P, R>(h, bb); break;
+        case 3: add_act<3, P, R>(h, bb); break;
+        default: add_act<0, P, R>(h, bb); break;
+        }
     }
 }
 
@@ -357,80 +438,83 @@ __device__ __forceinline__ float slab_loss(const FitArgs &a, int l, int s0, int 
     return total;
 }
 
-template <bool BF, int P, int RI, int RO>
-__device__ __forceinline__ void layer_h(const FitArgs &a, const float *w, int l, int n, int g,
-                                        const floatx4 (&in)[P][RI], floatx4 (&out)[P][RO])
+template <bool BF, bool WL, int NW, int P, int ACT, int R1, int R2, int R3, int R4, int SCHED = 1>
+__global__ __launch_bounds__(NW * 64) void k_fit(FitArgs a)
 {
-    if constexpr (BF) layer_h_bf16<P, RI, RO>(a, w, l, n, g, in, out);
-    else layer_h_f32<P, RI, RO>(a, w, l, n, g, in, out);
-}
-
-template <bool BF, int P, int R1, int R2, int R3, int R4>
-__global__ __launch_bounds__(TPB) void k_fit(FitArgs a)
-{
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    __shared__ float red[NW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int n = lane & 15, g = lane >> 4;
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int r = bid / a.bpr, c = bid % a.bpr;
     const float *w = a.W + (size_t)r * a.ld;
+    if constexpr (WL) stage_weights<BF>(a, w, smem);
+    const WView<BF, WL> w0(a, w, smem, 0, n, g), w1(a, w, smem, 1, n, g);
+    const WView<BF, WL> w2(a, w, smem, 2, n, g), w3(a, w, smem, 3, n, g);
     const int s_begin = c * a.spb;
     const int s_end = min(s_begin + a.spb, a.S_pad);
     float lsum = 0.0f;
-    for (int s0 = s_begin + wave * 16 * P; s0 < s_end; s0 += WAVES * 16 * P) {
+    for (int s0 = s_begin + wave * 16 * P; s0 < s_end; s0 += NW * 16 * P) {
         floatx4 h1[P][R1];
-        if constexpr (BF) layer_x_bf16<P, R1>(a, w, s0, n, g, h1);
-        else layer_x_f32<P, R1>(a, w, s0, n, g, h1);
+        layer_x<BF, WL, P, R1, SCHED>(a, w0, s0, n, g, h1);
         if constexpr (R2 == 0) {
-            bias_act<P, R1>(a, w, 0, g, false, h1);
+            bias_act<ACT, WL, P, R1>(a, w, smem, 0, g, false, h1);
             lsum += slab_loss<P, R1>(a, 0, s0, n, g, h1);
         } else {
-            bias_act<P, R1>(a, w, 0, g, true, h1);
+            bias_act<ACT, WL, P, R1>(a, w, smem, 0, g, true, h1);
             floatx4 h2[P][R2];
-            layer_h<BF, P, R1, R2>(a, w, 1, n, g, h1, h2);
+            layer_h<BF, WL, P, R1, R2, SCHED>(w1, h1, h2);
             if constexpr (R3 == 0) {
-                bias_act<P, R2>(a, w, 1, g, false, h2);
+                bias_act<ACT, WL, P, R2>(a, w, smem, 1, g, false, h2);
                 lsum += slab_loss<P, R2>(a, 1, s0, n, g, h2);
             } else {
-                bias_act<P, R2>(a, w, 1, g, true, h2);
+                bias_act<ACT, WL, P, R2>(a, w, smem, 1, g, true, h2);
                 floatx4 h3[P][R3];
-                layer_h<BF, P, R2, R3>(a, w, 2, n, g, h2, h3);
+                layer_h<BF, WL, P, R2, R3, SCHED>(w2, h2, h3);
                 if constexpr (R4 == 0) {
-                    bias_act<P, R3>(a, w, 2, g, false, h3);
+                    bias_act<ACT, WL, P, R3>(a, w, smem, 2, g, false, h3);
                     lsum += slab_loss<P, R3>(a, 2, s0, n, g, h3);
                 } else {
-                    bias_act<P, R3>(a, w, 2, g, true, h3);
+                    bias_act<ACT, WL, P, R3>(a, w, smem, 2, g, true, h3);
                     floatx4 h4[P][R4];
-                    layer_h<BF, P, R3, R4>(a, w, 3, n, g, h3, h4);
-                    bias_act<P, R4>(a, w, 3, g, false, h4);
+                    layer_h<BF, WL, P, R3, R4, SCHED>(w3, h3, h4);
+                    bias_act<ACT, WL, P, R4>(a, w, smem, 3, g, false, h4);
                     lsum += slab_loss<P, R4>(a, 3, s0, n, g, h4);
                 }
             }
         }
     }
-    // fixed-order reduction: wavefront butterfly, then the 4 wavefronts in order
+    // fixed-order reduction: wavefront butterfly, then the wavefronts in order
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) lsum += __shfl_xor(lsum, off);
-    __shared__ float red[WAVES];
     if (lane == 0) red[wave] = lsum;
     __syncthreads();
     if (threadIdx.x == 0) {
         float t = red[0];
 #pragma unroll
-        for (int i = 1; i < WAVES; ++i) t += red[i];
+        for (int i = 1; i < NW; ++i) t += red[i];
         a.partial[(size_t)r * a.bpr + c] = t;
     }
 }
 
-
-// One compiled fitness kernel: precision, slabs in flight, 16-row blocks per layer.
+// One compiled fitness kernel: precision, weight source, wavefronts per block,
+// slabs in flight, hidden activation (-1: chosen at run time), 16-row blocks
+// per layer.
 struct KernelEntry {
-    int bf16, P, R[MAXL];
+    int bf16, wl, nw, P, act, R[MAXL];
     const void *fn;
 };
 
-#define FIT_ENTRY(BF, P, R1, R2, R3, R4) \
-    {BF, P, {R1, R2, R3, R4}, reinterpret_cast<const void *>(&::mgfwa::fit::k_fit<BF, P, R1, R2, R3, R4>)}
-#define FIT_BOTH(P, R1, R2, R3, R4) FIT_ENTRY(false, P, R1, R2, R3, R4), FIT_ENTRY(true, P, R1, R2, R3, R4)
+#define FIT_ENTRY_ACT(BF, WL, NW, P, ACT, R1, R2, R3, R4)                                   \
+    {BF, WL, NW, P, ACT, {R1, R2, R3, R4},                                                   \
+     reinterpret_cast<const void *>(&::mgfwa::fit::k_fit<BF, WL, NW, P, ACT, R1, R2, R3, R4>)}
+#define FIT_ENTRY(BF, WL, NW, P, R1, R2, R3, R4) FIT_ENTRY_ACT(BF, WL, NW, P, -1, R1, R2, R3, R4)
+// global-weight kernels in both precisions
+#define FIT_BOTH(P, R1, R2, R3, R4) \
+    FIT_ENTRY(false, false, 4, P, R1, R2, R3, R4), FIT_ENTRY(true, false, 4, P, R1, R2, R3, R4)
+// LDS-weight kernels in both precisions
+#define FIT_BOTH_LDS(P, R1, R2, R3, R4) \
+    FIT_ENTRY(false, true, 4, P, R1, R2, R3, R4), FIT_ENTRY(true, true, 4, P, R1, R2, R3, R4)
 
 }  // namespace fit
 }  // namespace mgfwa

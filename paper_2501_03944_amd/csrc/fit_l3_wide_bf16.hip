@@ -6,8 +6,8 @@ namespace fit {
 
 namespace {
 const KernelEntry kEntries[] = {
-    FIT_ENTRY(true, 2, 16, 16, 1, 0),
-    FIT_ENTRY(true, 2, 16, 16, 4, 0),
+    FIT_ENTRY(true, false, 4, 2, 16, 16, 1, 0),
+    FIT_ENTRY(true, false, 4, 2, 16, 16, 4, 0),
 };
 }  // namespace
 

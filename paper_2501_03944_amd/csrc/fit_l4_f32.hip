@@ -6,11 +6,11 @@ namespace fit {
 
 namespace {
 const KernelEntry kEntries[] = {
-    FIT_ENTRY(false, 4, 2, 2, 2, 1),
-    FIT_ENTRY(false, 4, 4, 4, 4, 1),
-    FIT_ENTRY(false, 4, 4, 4, 4, 4),
-    FIT_ENTRY(false, 4, 8, 8, 8, 1),
-    FIT_ENTRY(false, 4, 8, 8, 8, 4),
+    FIT_ENTRY(false, false, 4, 4, 2, 2, 2, 1),
+    FIT_ENTRY(false, false, 4, 4, 4, 4, 4, 1),
+    FIT_ENTRY(false, false, 4, 4, 4, 4, 4, 4),
+    FIT_ENTRY(false, false, 4, 4, 8, 8, 8, 1),
+    FIT_ENTRY(false, false, 4, 4, 8, 8, 8, 4),
 };
 }  // namespace
 

@@ -6,7 +6,7 @@ namespace fit {
 
 namespace {
 const KernelEntry kEntries[] = {
-    FIT_ENTRY(true, 2, 16, 16, 16, 1),
+    FIT_ENTRY(true, false, 4, 2, 16, 16, 16, 1),
 };
 }  // namespace
 

@@ -6,7 +6,7 @@ namespace fit {
 
 namespace {
 const KernelEntry kEntries[] = {
-    FIT_ENTRY(false, 2, 16, 16, 16, 1),
+    FIT_ENTRY(false, false, 4, 2, 16, 16, 16, 1),
 };
 }  // namespace
 

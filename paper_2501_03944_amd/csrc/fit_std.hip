@@ -6,10 +6,17 @@ namespace fit {
 
 namespace {
 const KernelEntry kEntries[] = {
-    FIT_ENTRY(false, 4, 1, 1, 0, 0),
-    FIT_ENTRY(true, 4, 2, 1, 0, 0),
-    FIT_BOTH(4, 8, 8, 1, 0),
-    FIT_BOTH(2, 16, 1, 0, 0),
+    // 8-16-1 tanh: weights in LDS
+    FIT_ENTRY_ACT(false, true, 4, 4, 2, 1, 1, 0, 0),
+    FIT_ENTRY_ACT(true, true, 4, 4, 2, 2, 1, 0, 0),
+    // 64-128-128-10 ReLU: weights in LDS, 4 or 8 wavefronts per block
+    FIT_ENTRY_ACT(false, true, 4, 4, 1, 8, 8, 1, 0),
+    FIT_ENTRY_ACT(false, true, 8, 2, 1, 8, 8, 1, 0),
+    FIT_ENTRY_ACT(true, true, 4, 4, 1, 8, 8, 1, 0),
+    FIT_ENTRY_ACT(true, true, 8, 2, 1, 8, 8, 1, 0),
+    // 784-256-10 ReLU: the first layer does not fit in LDS
+    FIT_ENTRY_ACT(false, false, 4, 2, 1, 16, 1, 0, 0),
+    FIT_ENTRY_ACT(true, false, 4, 2, 1, 16, 1, 0, 0),
 };
 }  // namespace
 

@@ -3,6 +3,8 @@
 // template lives in fit_kernel.h; the fit_*.hip files instantiate it.
 #include "fit_kernel.h"
 
+#include <cstdlib>
+
 namespace mgfwa {
 
 namespace fit {
@@ -71,6 +73,34 @@ const KernelEntry *(*const kTables[])(int *) = {
 
 int fit_max_bpr() { return MAX_BPR; }
 
+// LDS layout of the staged weights for kernel entry e; returns the byte size.
+static int lds_layout(const Net &net, const KernelEntry &e, FitPlan *p)
+{
+    const int es = e.bf16 ? 2 : 4;          // storage bytes per weight
+    const int unit = e.bf16 ? 8 : 4;        // pitch padding: 16 / 8 bytes
+    int off = 0, boff = 0;
+    for (int l = 0; l < MAXL; ++l) {
+        p->lw[l] = p->lpitch[l] = p->lrows[l] = p->lcols[l] = p->lb[l] = 0;
+        if (l >= net.nl) continue;
+        const int rows = 16 * e.R[l];
+        int cols;
+        if (l == 0) cols = net.in_pad;
+        else cols = e.bf16 ? 32 * ((e.R[l - 1] + 1) / 2) : 16 * e.R[l - 1];
+        const int pitch = cols + unit;
+        off = (off + (16 / es) - 1) / (16 / es) * (16 / es);   // 16-byte aligned layer base
+        p->lw[l] = off;
+        p->lpitch[l] = pitch;
+        p->lrows[l] = rows;
+        p->lcols[l] = cols;
+        p->lb[l] = boff;
+        off += rows * pitch;
+        boff += rows;
+    }
+    p->lbias_byte = (off * es + 15) / 16 * 16;
+    p->lds_bytes = p->lbias_byte + boff * 4;
+    return p->lds_bytes;
+}
+
 bool fit_select(const Net &net, int rows, FitPlan *plan)
 {
     int need[MAXL] = {0, 0, 0, 0};
@@ -79,25 +109,40 @@ bool fit_select(const Net &net, int rows, FitPlan *plan)
         // BF16 chains need even 16-row blocks for every layer that feeds another
         if (net.bf16 && l < net.nl - 1 && (need[l] & 1)) need[l] += 1;
     }
+    const char *env = std::getenv("MGFWA_FIT_NW");
+    const int prefer_nw = env ? std::atoi(env) : 8;
     const KernelEntry *best = nullptr;
-    long best_cost = 0;
+    double best_cost = 0.0;
+    FitPlan tmp{};
     for (auto table : kTables) {
         int nent = 0;
         const KernelEntry *ents = table(&nent);
         for (int ie = 0; ie < nent; ++ie) {
             const KernelEntry &e = ents[ie];
             if (e.bf16 != net.bf16) continue;
+            if (e.act >= 0) {
+                bool same = true;              // a fixed activation must match every hidden layer
+                for (int l = 0; l < net.nl - 1; ++l) same = same && net.act[l] == e.act;
+                if (!same) continue;
+            }
             bool ok = true;
-            long cost = 0;
+            double cost = 0.0;
             for (int l = 0; l < MAXL; ++l) {
                 const bool present = l < net.nl;
                 if (present != (e.R[l] > 0) || (present && e.R[l] < need[l])) {
                     ok = false;
                     break;
                 }
-                if (present) cost += (long)e.R[l] * (l == 0 ? net.in_pad : net.fo[l - 1] + 16);
+                if (present) cost += (double)e.R[l] * (l == 0 ? net.in_pad : net.fo[l - 1] + 16);
             }
-            if (ok && (!best || cost < best_cost)) {
+            if (!ok) continue;
+            if (e.wl) {
+                if (lds_layout(net, e, &tmp) > net.lds_max) continue;
+                cost *= 0.5;                  // staged weights beat global fragment loads
+            }
+            if (e.act >= 0) cost *= 0.9;      // specialised activation: straight-line epilogue
+            if (e.nw != prefer_nw) cost *= 1.01;
+            if (!best || cost < best_cost) {
                 best = &e;
                 best_cost = cost;
             }
@@ -105,11 +150,18 @@ bool fit_select(const Net &net, int rows, FitPlan *plan)
     }
     if (!best) return false;
     plan->kernel = best->fn;
+    plan->nw = best->nw;
     plan->P = best->P;
+    plan->wl = best->wl;
     plan->rows = rows;
+    if (best->wl) lds_layout(net, *best, plan);
+    else {
+        lds_layout(net, *best, plan);
+        plan->lds_bytes = 0;
+    }
     // Blocks per spark: enough blocks to fill the chip (about 4 per CU) while
     // keeping at least two slab groups per wavefront.
-    const int group = WAVES * 16 * best->P;                  // samples per block pass
+    const int group = best->nw * 16 * best->P;               // samples per block pass
     const int max_bpr = (net.S_pad + group - 1) / group;
     int bpr = (1024 + rows - 1) / (rows > 0 ? rows : 1);
     int lim = max_bpr / 2 > 0 ? max_bpr / 2 : 1;
@@ -122,6 +174,13 @@ bool fit_select(const Net &net, int rows, FitPlan *plan)
     plan->bpr = bpr;
     plan->spb = spb;
     return true;
+}
+
+hipError_t fit_prepare(const FitPlan &plan)
+{
+    if (plan.lds_bytes <= 0) return hipSuccess;
+    return hipFuncSetAttribute(plan.kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               plan.lds_bytes);
 }
 
 hipError_t launch_fitness(const Net &net, const FitPlan &plan, const DevState &d, const float *W,
@@ -146,7 +205,13 @@ hipError_t launch_fitness(const Net &net, const FitPlan &plan, const DevState &d
         a.boff[l] = net.boff[l];
         a.act[l] = net.act[l];
         a.vec[l] = net.vec[l];
+        a.lw[l] = plan.lw[l];
+        a.lpitch[l] = plan.lpitch[l];
+        a.lrows[l] = plan.lrows[l];
+        a.lcols[l] = plan.lcols[l];
+        a.lb[l] = plan.lb[l];
     }
+    a.lbias_byte = plan.lbias_byte;
     a.loss = net.loss;
     a.Y = d.Ypad;
     a.lab = d.Lpad;
@@ -154,8 +219,8 @@ hipError_t launch_fitness(const Net &net, const FitPlan &plan, const DevState &d
     a.spb = plan.spb;
     a.partial = d.partial;
     void *args[] = {&a};
-    hipError_t e = hipLaunchKernel(plan.kernel, dim3((unsigned)(rows * plan.bpr)), dim3(TPB), args,
-                                   0, st);
+    hipError_t e = hipLaunchKernel(plan.kernel, dim3((unsigned)(rows * plan.bpr)),
+                                   dim3(64 * plan.nw), args, (size_t)plan.lds_bytes, st);
     if (e != hipSuccess) return e;
     if (mid) {
         e = hipEventRecord(mid, st);

@@ -51,15 +51,21 @@ struct Net {
     int S, S_pad, in_pad;              // samples, padded samples, padded input width
     int bf16;                          // precision
     float inv_norm;                    // 1/(S*out) for MSE, 1/S for CE
+    int lds_max;                       // LDS bytes a block may use (0: weights stay in global)
 };
 
 // A chosen fitness kernel and its launch geometry for a given row count.
 struct FitPlan {
     const void *kernel;   // __global__ function
+    int nw;               // wavefronts per block
     int P;                // 16-sample slabs per wave in flight
+    int wl;               // weights staged in LDS
     int bpr;              // blocks per spark row
     int spb;              // samples per block
     int rows;
+    // LDS layout of the staged weights (wl = 1)
+    int lw[MAXL], lpitch[MAXL], lrows[MAXL], lcols[MAXL], lb[MAXL];
+    int lbias_byte, lds_bytes;
 };
 
 // ---- spark.hip
@@ -81,6 +87,8 @@ hipError_t launch_store_fitness(const float *src, int rows, OutMap map, float *o
 // ---- fitness.hip
 // Choose the kernel for the network (false if the shape is not compiled in).
 bool fit_select(const Net &net, int rows, FitPlan *plan);
+// Device-side preparation of a chosen plan (dynamic LDS limit); needs a device.
+hipError_t fit_prepare(const FitPlan &plan);
 // Fitness of `rows` sparks into out[map(row)]: the GEMM kernel writes one partial
 // per (row, block); the finalisation sums them in order.  `mid` (optional) is
 // recorded between the two launches.
