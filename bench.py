@@ -46,7 +46,24 @@ def parse():
     ap.add_argument("--precision-study", action="store_true",
                     help="also run the 784-256-10 workload in BF16 and FP32 and compare")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--calib-copy-mib", type=int, default=256,
+                    help="size of a plain device copy run once before the timed region; its "
+                         "FETCH_SIZE / WRITE_SIZE readings scale the fitness kernel's counters")
     return ap.parse_args()
+
+
+def calibration_copy(mib):
+    """A plain device-to-device copy of known size (read mib MiB, write mib MiB)."""
+    import torch
+
+    if mib <= 0:
+        return
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def run_gpu(wl, precision, steps, warmup, seed):
@@ -139,6 +156,7 @@ def main():
 
     wl = inputs.workload(args.workload)
     precision = args.precision or "fp32"
+    calibration_copy(args.calib_copy_mib)
     r = run_gpu(wl, precision, args.steps, args.warmup, args.seed)
     K = args.steps
     value = r["C"] * K / (r["ms"] / 1e3)

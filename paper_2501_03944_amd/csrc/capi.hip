@@ -48,7 +48,8 @@ int round_up(int v, int a) { return (v + a - 1) / a * a; }
 
 struct Layout {
     size_t F, SE, SG, A, Y, Yprev, fresh, Yc, top, bottom, tie, cstar, improved, reinit, src;
-    size_t best_x, best_y, best_f, best_gen, best_upd, ctrl, partial, Xp, Xb, Ypad, Lpad, total;
+    size_t best_x, best_y, best_f, best_gen, best_upd, ctrl, partial, Xp, Xb, Ypad, Lpad;
+    size_t Wpack, Xw, total;
     int partial_rows;
 };
 
@@ -151,6 +152,14 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
     const int outw = net.fo[net.nl - 1];
     net.inv_norm = net.loss == MGFWA_LOSS_MSE ? (float)(1.0 / ((double)net.S * outw))
                                               : (float)(1.0 / (double)net.S);
+    // Two-layer networks whose staged weights exceed the LDS stream their first
+    // layer through LDS instead (MGFWA_FORCE_WIDE=1 forces it, for tests).
+    const char *fw = std::getenv("MGFWA_FORCE_WIDE");
+    const bool force_wide = fw && fw[0] == '1';
+    net.wide = need_data && wide_applicable(net) &&
+               (force_wide || resident_lds_bytes(net) > 160 * 1024 - 512);
+    if (net.wide && net.S_pad / 256 > fit_max_bpr())
+        return fail(MGFWA_EUNSUPPORTED, "too many samples for the wide fitness kernel");
 
     Layout &L = out->lay;
     size_t off = 0;
@@ -188,6 +197,8 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
     L.Xb = take(net.bf16 ? nx * 2 : 0);
     L.Ypad = take(net.loss == MGFWA_LOSS_MSE ? (size_t)net.S_pad * outw * 4 : 0);
     L.Lpad = take(net.loss == MGFWA_LOSS_CE ? (size_t)net.S_pad * 4 : 0);
+    L.Wpack = take(net.wide ? (size_t)L.partial_rows * wide_row_bytes(net) : 0);
+    L.Xw = take(net.wide ? (size_t)net.S_pad * wide_kp(net) * (net.bf16 ? 2 : 4) : 0);
     L.total = off;
     return MGFWA_OK;
 }
@@ -246,7 +257,10 @@ const OutMap kFlat = {1, 1, 0};
 mgfwa_status fit_rows(mgfwa_ctx *c, const FitPlan &plan, const float *W, size_t ld, int rows,
                       OutMap map, float *out, hipStream_t st, hipEvent_t mid = nullptr)
 {
-    STEP(launch_fitness(c->net, plan, c->d, W, ld, rows, map, out, st, mid), "fitness");
+    if (c->net.wide)
+        STEP(launch_fitness_wide(c->net, c->d, W, ld, rows, map, out, st, mid), "fitness_wide");
+    else
+        STEP(launch_fitness(c->net, plan, c->d, W, ld, rows, map, out, st, mid), "fitness");
     return MGFWA_OK;
 }
 
@@ -348,7 +362,7 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
                     dv.lay.total);
     const bool has_data = !config->external_fitness || problem->x_dev;
     FitPlan pi{}, pe{}, pg{}, pv{};
-    if (has_data) {
+    if (has_data && !dv.net.wide) {
         if (!fit_select(dv.net, dv.s.BN, &pi) || !fit_select(dv.net, dv.s.BN * dv.s.lam, &pe) ||
             !fit_select(dv.net, dv.s.BN * dv.s.G, &pg) ||
             !fit_select(dv.net, dv.lay.partial_rows, &pv))
@@ -359,7 +373,14 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
     int lds_max = 0;
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     dv.net.lds_max = lds_max - 256;   // leave room for the kernels' static LDS
-    if (has_data) {
+    int num_cu = 0;
+    HIP_TRY(hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    dv.net.num_cu = num_cu > 0 ? num_cu : 1;
+    if (has_data && dv.net.wide) {
+        if (wide_lds_bytes(dv.net) > lds_max - 64)
+            return fail(MGFWA_EUNSUPPORTED, "device LDS too small for the wide fitness kernel");
+        HIP_TRY(wide_prepare(dv.net));
+    } else if (has_data) {
         if (!fit_select(dv.net, dv.s.BN, &pi) || !fit_select(dv.net, dv.s.BN * dv.s.lam, &pe) ||
             !fit_select(dv.net, dv.s.BN * dv.s.G, &pg) ||
             !fit_select(dv.net, dv.lay.partial_rows, &pv))
@@ -412,6 +433,8 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
     d.Xb = c->net.bf16 ? at<uint16_t>(b, L.Xb) : nullptr;
     d.Ypad = c->net.loss == MGFWA_LOSS_MSE ? at<float>(b, L.Ypad) : nullptr;
     d.Lpad = c->net.loss == MGFWA_LOSS_CE ? at<int32_t>(b, L.Lpad) : nullptr;
+    d.Wpack = c->net.wide ? at<char>(b, L.Wpack) : nullptr;
+    d.Xw = c->net.wide ? at<char>(b, L.Xw) : nullptr;
 
     auto bail = [&](mgfwa_status st) {
         mgfwa_destroy(c);
@@ -423,6 +446,10 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
         r = check(c, launch_pack_problem(c->net, problem->x_dev, problem->y_dev,
                                          problem->labels_dev, d, c->stream), "pack");
         if (r) return bail(r);
+        if (c->net.wide) {
+            r = check(c, launch_pack_wide_x(c->net, problem->x_dev, d.Xw, c->stream), "pack_x");
+            if (r) return bail(r);
+        }
     }
     r = check(c, launch_init_positions(c->s, d, c->stream), "init_positions");
     if (r) return bail(r);
@@ -580,10 +607,12 @@ mgfwa_status mgfwa_evaluate(mgfwa_ctx *c, const float *w, int rows, int ld, floa
     const int chunk = c->lay.partial_rows;
     for (int r0 = 0; r0 < rows; r0 += chunk) {
         const int nr = std::min(chunk, rows - r0);
-        FitPlan plan;
-        if (!fit_select(c->net, nr, &plan))
-            return fail(MGFWA_EUNSUPPORTED, "no compiled fitness kernel covers this MLP shape");
-        HIP_TRY(fit_prepare(plan));
+        FitPlan plan{};
+        if (!c->net.wide) {
+            if (!fit_select(c->net, nr, &plan))
+                return fail(MGFWA_EUNSUPPORTED, "no compiled fitness kernel covers this MLP shape");
+            HIP_TRY(fit_prepare(plan));
+        }
         mgfwa_status r = fit_rows(c, plan, w + (size_t)r0 * ld, (size_t)ld, nr, kFlat, out + r0,
                                   c->stream);
         if (r) return r;

@@ -164,6 +164,42 @@ __device__ __forceinline__ void stage_weights(const FitArgs &a, const float *w, 
         const int fo = a.fo[l], fi = a.fi[l], rows = a.lrows[l], cols = a.lcols[l];
         const int pitch = a.lpitch[l], base = a.lw[l];
         const float *src = w + a.woff[l];
+        if (a.vec[l]) {
+            // 16-byte loads, four in flight per thread (fi, cols and the row
+            // offsets are multiples of 4, so a chunk is all-valid or all-padding)
+            const int n4 = rows * cols / 4;
+            const int nt = blockDim.x;
+            for (int i0 = threadIdx.x; i0 < n4; i0 += 4 * nt) {
+                floatx4 v[4];
+                int dst[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int idx = i0 + u * nt;
+                    const int o = (4 * idx) / cols, k = 4 * idx - o * cols;
+                    dst[u] = idx < n4 ? base + o * pitch + k : -1;
+                    v[u] = (idx < n4 && o < fo && k < fi)
+                               ? *reinterpret_cast<const floatx4 *>(src + (size_t)o * fi + k)
+                               : zero4();
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (dst[u] < 0) continue;
+                    if constexpr (BF) {
+                        const uint32_t lo = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[u][0]) |
+                                            ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[u][1]) << 16);
+                        const uint32_t hi = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[u][2]) |
+                                            ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[u][3]) << 16);
+                        *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(smem) + dst[u]) =
+                            make_uint2(lo, hi);
+                    } else {
+                        *reinterpret_cast<floatx4 *>(reinterpret_cast<float *>(smem) + dst[u]) = v[u];
+                    }
+                }
+            }
+            for (int o = threadIdx.x; o < rows; o += blockDim.x)
+                bias[a.lb[l] + o] = o < fo ? w[a.boff[l] + o] : 0.0f;
+            continue;
+        }
         const int n = rows * cols;
         for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
             const int o = idx / cols, k = idx - o * cols;
@@ -505,9 +541,11 @@ struct KernelEntry {
     const void *fn;
 };
 
-#define FIT_ENTRY_ACT(BF, WL, NW, P, ACT, R1, R2, R3, R4)                                   \
+#define FIT_ENTRY_SCHED(BF, WL, NW, P, ACT, SCHED, R1, R2, R3, R4)                          \
     {BF, WL, NW, P, ACT, {R1, R2, R3, R4},                                                   \
-     reinterpret_cast<const void *>(&::mgfwa::fit::k_fit<BF, WL, NW, P, ACT, R1, R2, R3, R4>)}
+     reinterpret_cast<const void *>(&::mgfwa::fit::k_fit<BF, WL, NW, P, ACT, R1, R2, R3, R4, SCHED>)}
+#define FIT_ENTRY_ACT(BF, WL, NW, P, ACT, R1, R2, R3, R4) \
+    FIT_ENTRY_SCHED(BF, WL, NW, P, ACT, 1, R1, R2, R3, R4)
 #define FIT_ENTRY(BF, WL, NW, P, R1, R2, R3, R4) FIT_ENTRY_ACT(BF, WL, NW, P, -1, R1, R2, R3, R4)
 // global-weight kernels in both precisions
 #define FIT_BOTH(P, R1, R2, R3, R4) \

@@ -1,0 +1,221 @@
+// Wide-first-layer fitness: packing of sparks and samples, kernel instances,
+// plan selection and launches (kernel template in fit_wide.h).
+#include "fit_wide.h"
+
+namespace mgfwa {
+
+using namespace fit;
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int MAX_GRID_Y = 65535;
+
+// One 16-byte chunk of a packed spark row per thread.  Chunk ranges:
+//   W1aug  [256][Kp]     value(o, k) = W1[o][k] (k < in), b1[o] (k == in), 0
+//   W2     [16][256]     BF16: chunk (i, kb, g) holds W2[i][32kb + p(g, e)], e = 0..7,
+//                        p(g, e) = 4g + e (e < 4) or 16 + 4g + e - 4 (e >= 4);
+//                        FP32: natural order
+//   b2     [16]          FP32
+template <bool BF>
+__global__ __launch_bounds__(TPB) void k_pack_wide_rows(const float *__restrict__ W, size_t ld,
+                                                        int rows, char *__restrict__ Wp, size_t pr,
+                                                        int in, int hid, int out, int Kp, int woff1,
+                                                        int boff1, int woff2, int boff2)
+{
+    constexpr int ES = BF ? 2 : 4, EPC = 16 / ES;   // elements per chunk
+    const int c1 = WT_M * Kp / EPC;                  // chunks of W1aug
+    const int c2 = 16 * WT_M / EPC;                  // chunks of W2
+    const int nchunk = c1 + c2 + 4;
+    const int chunk = blockIdx.x * TPB + threadIdx.x;
+    if (chunk >= nchunk) return;
+    for (int r = blockIdx.y; r < rows; r += gridDim.y) {
+        const float *w = W + (size_t)r * ld;
+        float v[EPC];
+        if (chunk < c1) {
+            const int e0 = chunk * EPC, o = e0 / Kp, k0 = e0 % Kp;
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+                const int k = k0 + e;
+                float x = 0.0f;
+                if (o < hid) {
+                    if (k < in) x = w[woff1 + (size_t)o * in + k];
+                    else if (k == in) x = w[boff1 + o];
+                }
+                v[e] = x;
+            }
+        } else if (chunk < c1 + c2) {
+            const int e0 = (chunk - c1) * EPC, i = e0 / WT_M, c0 = e0 % WT_M;
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+                int col = c0 + e;
+                if (BF) {
+                    const int blk = c0 & ~31, g = (c0 & 31) >> 3;   // c0 = 32kb + 8g
+                    col = blk + (e < 4 ? 4 * g + e : 16 + 4 * g + e - 4);
+                }
+                v[e] = (i < out && col < hid) ? w[woff2 + (size_t)i * hid + col] : 0.0f;
+            }
+        } else {
+            const int i0 = (chunk - c1 - c2) * 4;
+            float *dst = reinterpret_cast<float *>(Wp + (size_t)r * pr + (size_t)c1 * 16 + (size_t)c2 * 16);
+            float4 b;
+            b.x = i0 + 0 < out ? w[boff2 + i0 + 0] : 0.0f;
+            b.y = i0 + 1 < out ? w[boff2 + i0 + 1] : 0.0f;
+            b.z = i0 + 2 < out ? w[boff2 + i0 + 2] : 0.0f;
+            b.w = i0 + 3 < out ? w[boff2 + i0 + 3] : 0.0f;
+            reinterpret_cast<float4 *>(dst)[i0 / 4] = b;
+            continue;
+        }
+        uint4 q;
+        if constexpr (BF) {
+            uint32_t h[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                h[e] = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[2 * e]) |
+                       ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[2 * e + 1]) << 16);
+            q = make_uint4(h[0], h[1], h[2], h[3]);
+        } else {
+            q = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
+                           __float_as_uint(v[3]));
+        }
+        reinterpret_cast<uint4 *>(Wp + (size_t)r * pr)[chunk] = q;
+    }
+}
+
+// Samples for the wide kernel: [S_pad][Kp], column `in` = 1 (the folded bias).
+template <bool BF>
+__global__ __launch_bounds__(TPB) void k_pack_wide_x(const float *__restrict__ x, int S, int S_pad,
+                                                     int in, int Kp, char *__restrict__ Xw)
+{
+    const size_t tid = (size_t)blockIdx.x * TPB + threadIdx.x;
+    if (tid >= (size_t)S_pad * Kp) return;
+    const int s = (int)(tid / Kp), k = (int)(tid % Kp);
+    float v = 0.0f;
+    if (s < S) v = k < in ? x[(size_t)s * in + k] : (k == in ? 1.0f : 0.0f);
+    if constexpr (BF) reinterpret_cast<uint16_t *>(Xw)[tid] = __builtin_bit_cast(uint16_t, (__bf16)v);
+    else reinterpret_cast<float *>(Xw)[tid] = v;
+}
+
+__global__ __launch_bounds__(256) void k_wide_finalize(const float *__restrict__ partial, int rows,
+                                                       int ntn, float inv_norm, OutMap map,
+                                                       float *__restrict__ out)
+{
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= rows) return;
+    float t = 0.0f;
+    for (int c = 0; c < ntn; ++c) t += partial[(size_t)r * ntn + c];
+    out[(size_t)(r / map.per) * map.stride + map.offset + r % map.per] = canon_fitness(t * inv_norm);
+}
+
+// One instance per (precision, hidden activation): a run-time activation
+// switch over the 256 accumulators would push them out of registers.
+const void *const kWide[2][4] = {
+    {reinterpret_cast<const void *>(&k_fit_wide<false, 0>), reinterpret_cast<const void *>(&k_fit_wide<false, 1>),
+     reinterpret_cast<const void *>(&k_fit_wide<false, 2>), reinterpret_cast<const void *>(&k_fit_wide<false, 3>)},
+    {reinterpret_cast<const void *>(&k_fit_wide<true, 0>), reinterpret_cast<const void *>(&k_fit_wide<true, 1>),
+     reinterpret_cast<const void *>(&k_fit_wide<true, 2>), reinterpret_cast<const void *>(&k_fit_wide<true, 3>)},
+};
+
+const void *wide_kernel(const Net &net)
+{
+    const int act = net.act[0] >= 0 && net.act[0] <= 3 ? net.act[0] : 0;
+    return kWide[net.bf16 ? 1 : 0][act];
+}
+
+}  // namespace
+
+bool wide_applicable(const Net &net)
+{
+    return net.nl == 2 && net.fo[0] <= WT_M && net.fo[1] <= 16;
+}
+
+// K padded so that a tile's K steps are a whole number of LDS stage rounds
+int wide_kp(const Net &net)
+{
+    const int step = WT_K * (net.bf16 ? WideCfg<true>::STAGES : WideCfg<false>::STAGES);
+    return (net.fi[0] + 1 + step - 1) / step * step;
+}
+
+size_t wide_row_bytes(const Net &net)
+{
+    const size_t es = net.bf16 ? 2 : 4;
+    const size_t b = (size_t)WT_M * wide_kp(net) * es + 16 * WT_M * es + 64;
+    return (b + 255) / 256 * 256;
+}
+
+int wide_lds_bytes(const Net &net) { return net.bf16 ? WideCfg<true>::LDS : WideCfg<false>::LDS; }
+
+hipError_t wide_prepare(const Net &net)
+{
+    return hipFuncSetAttribute(wide_kernel(net), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               wide_lds_bytes(net));
+}
+
+hipError_t launch_pack_wide_x(const Net &net, const float *x, char *Xw, hipStream_t st)
+{
+    const int Kp = wide_kp(net);
+    const size_t n = (size_t)net.S_pad * Kp;
+    const unsigned blocks = (unsigned)((n + TPB - 1) / TPB);
+    if (net.bf16)
+        hipLaunchKernelGGL(k_pack_wide_x<true>, dim3(blocks), dim3(TPB), 0, st, x, net.S, net.S_pad,
+                           net.fi[0], Kp, Xw);
+    else
+        hipLaunchKernelGGL(k_pack_wide_x<false>, dim3(blocks), dim3(TPB), 0, st, x, net.S, net.S_pad,
+                           net.fi[0], Kp, Xw);
+    return hipGetLastError();
+}
+
+hipError_t launch_fitness_wide(const Net &net, const DevState &d, const float *W, size_t ld,
+                               int rows, OutMap map, float *out, hipStream_t st, hipEvent_t mid)
+{
+    if (rows <= 0) return hipSuccess;
+    const int Kp = wide_kp(net);
+    const size_t pr = wide_row_bytes(net);
+    const int es = net.bf16 ? 2 : 4, epc = 16 / es;
+    const int nchunk = WT_M * Kp / epc + 16 * WT_M / epc + 4;
+    dim3 pg((nchunk + TPB - 1) / TPB, rows < MAX_GRID_Y ? rows : MAX_GRID_Y);
+    if (net.bf16)
+        hipLaunchKernelGGL(k_pack_wide_rows<true>, pg, dim3(TPB), 0, st, W, ld, rows, d.Wpack, pr,
+                           net.fi[0], net.fo[0], net.fo[1], Kp, net.woff[0], net.boff[0],
+                           net.woff[1], net.boff[1]);
+    else
+        hipLaunchKernelGGL(k_pack_wide_rows<false>, pg, dim3(TPB), 0, st, W, ld, rows, d.Wpack, pr,
+                           net.fi[0], net.fo[0], net.fo[1], Kp, net.woff[0], net.boff[0],
+                           net.woff[1], net.boff[1]);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    WideArgs a;
+    a.Wp = d.Wpack;
+    a.pr = pr;
+    a.rows = rows;
+    a.Xw = d.Xw;
+    a.Kp = Kp;
+    a.nk = Kp / WT_K;
+    a.S = net.S;
+    a.S_pad = net.S_pad;
+    a.ntn = net.S_pad / WT_N;
+    a.fo1 = net.fo[1];
+    a.loss = net.loss;
+    a.act = net.act[0];
+    a.Y = d.Ypad;
+    a.lab = d.Lpad;
+    a.partial = d.partial;
+    // sparks per XCD group: enough tiles for the XCD's blocks, dividing the rows
+    const int bx = (net.num_cu + 7) / 8;
+    int gs = 1;
+    while (gs * a.ntn < bx && rows % (2 * gs) == 0 && gs < 64) gs *= 2;
+    a.gs = gs;
+    void *args[] = {&a};
+    e = hipLaunchKernel(wide_kernel(net), dim3((unsigned)net.num_cu), dim3(TPB), args,
+                        (size_t)wide_lds_bytes(net), st);
+    if (e != hipSuccess) return e;
+    if (mid) {
+        e = hipEventRecord(mid, st);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_wide_finalize, dim3((rows + 255) / 256), dim3(256), 0, st, d.partial, rows,
+                       a.ntn, net.inv_norm, map, out);
+    return hipGetLastError();
+}
+
+}  // namespace mgfwa

@@ -101,6 +101,18 @@ static int lds_layout(const Net &net, const KernelEntry &e, FitPlan *p)
     return p->lds_bytes;
 }
 
+int resident_lds_bytes(const Net &net)
+{
+    KernelEntry e{};
+    e.bf16 = net.bf16;
+    for (int l = 0; l < MAXL; ++l) {
+        e.R[l] = l < net.nl ? (net.fo[l] + 15) / 16 : 0;
+        if (net.bf16 && l < net.nl - 1 && (e.R[l] & 1)) e.R[l] += 1;
+    }
+    FitPlan p{};
+    return lds_layout(net, e, &p);
+}
+
 bool fit_select(const Net &net, int rows, FitPlan *plan)
 {
     int need[MAXL] = {0, 0, 0, 0};
@@ -110,7 +122,7 @@ bool fit_select(const Net &net, int rows, FitPlan *plan)
         if (net.bf16 && l < net.nl - 1 && (need[l] & 1)) need[l] += 1;
     }
     const char *env = std::getenv("MGFWA_FIT_NW");
-    const int prefer_nw = env ? std::atoi(env) : 8;
+    const int prefer_nw = env ? std::atoi(env) : 0;
     const KernelEntry *best = nullptr;
     double best_cost = 0.0;
     FitPlan tmp{};
@@ -141,7 +153,7 @@ bool fit_select(const Net &net, int rows, FitPlan *plan)
                 cost *= 0.5;                  // staged weights beat global fragment loads
             }
             if (e.act >= 0) cost *= 0.9;      // specialised activation: straight-line epilogue
-            if (e.nw != prefer_nw) cost *= 1.01;
+            if (prefer_nw > 0 && e.nw != prefer_nw) cost *= 1.01;
             if (!best || cost < best_cost) {
                 best = &e;
                 best_cost = cost;

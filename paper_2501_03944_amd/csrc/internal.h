@@ -11,7 +11,7 @@ namespace mgfwa {
 
 constexpr int MAXL = 4;        // Linear layers per MLP
 constexpr int MAXW = 256;      // widest layer output
-constexpr int S_ALIGN = 128;   // sample padding of the packed problem data
+constexpr int S_ALIGN = 256;   // sample padding of the packed problem data
 
 // Where a row's result goes: out[(r / per) * stride + offset + r % per].
 struct OutMap {
@@ -27,6 +27,8 @@ struct DevState {
     uint16_t *Xb;      // [S_pad][in_pad] packed inputs as bf16 bits (BF16 precision)
     float *Ypad;       // [S_pad][out] MSE targets (zero padded)
     int32_t *Lpad;     // [S_pad] CE labels (-1 padded)
+    char *Wpack;       // packed spark rows for the wide-first-layer kernel
+    char *Xw;          // [S_pad][Kp] samples with a ones column (wide kernel)
 };
 
 // Population shape and algorithm constants as the kernels need them.
@@ -52,6 +54,8 @@ struct Net {
     int bf16;                          // precision
     float inv_norm;                    // 1/(S*out) for MSE, 1/S for CE
     int lds_max;                       // LDS bytes a block may use (0: weights stay in global)
+    int wide;                          // first layer streamed through LDS (two-layer nets)
+    int num_cu;                        // compute units (persistent grid size)
 };
 
 // A chosen fitness kernel and its launch geometry for a given row count.
@@ -99,5 +103,18 @@ hipError_t launch_pack_problem(const Net &net, const float *x, const float *y,
                                const int32_t *labels, const DevState &d, hipStream_t st);
 // largest partial-sum count per row any plan may use
 int fit_max_bpr();
+// LDS bytes the resident-weights kernel would need for this network
+int resident_lds_bytes(const Net &net);
+
+// ---- fit_wide.hip
+bool wide_applicable(const Net &net);
+int wide_kp(const Net &net);
+size_t wide_row_bytes(const Net &net);
+int wide_lds_bytes(const Net &net);
+hipError_t wide_prepare(const Net &net);
+hipError_t launch_pack_wide_x(const Net &net, const float *x, char *Xw, hipStream_t st);
+hipError_t launch_fitness_wide(const Net &net, const DevState &d, const float *W, size_t ld,
+                               int rows, OutMap map, float *out, hipStream_t st,
+                               hipEvent_t mid = nullptr);
 
 }  // namespace mgfwa

@@ -55,31 +55,45 @@ __global__ __launch_bounds__(TPB) void k_select(Shape s, float *__restrict__ Yc,
     const int b = blockIdx.x, N = s.N;
     __shared__ int s_fb;
     __shared__ float s_yb;
-    for (int f = threadIdx.x; f < N; f += blockDim.x) {
+    // one wavefront per firework: lanes scan strided candidates, then a
+    // (value, index) butterfly keeps the lowest value and, on ties, the lowest index
+    const int lane = threadIdx.x & 63, nwave = blockDim.x >> 6;
+    for (int f = threadIdx.x >> 6; f < N; f += nwave) {
         const int gf = b * N + f;
         const float *yc = Yc + (size_t)gf * s.C;
-        const float yold = Y[gf];
-        Yprev[gf] = yold;
-        int cs = 0;
-        float ymin = yc[0];
-        for (int c = 1; c < s.C; ++c) {
+        float ymin = __int_as_float(0x7f800000);
+        int cs = 0x7fffffff;
+        for (int c = lane; c < s.C; c += 64) {
             const float v = yc[c];
-            if (v < ymin) {
+            if (v < ymin || (v == ymin && c < cs)) {
                 ymin = v;
                 cs = c;
             }
         }
-        cstar[gf] = cs;
-        reinit[gf] = 0;
-        if (ymin < yold) {
-            Y[gf] = ymin;
-            A[gf] = A[gf] * s.amp_up;
-            improved[gf] = 1;
-            src[gf] = cs;
-        } else {
-            A[gf] = A[gf] * s.amp_down;
-            improved[gf] = 0;
-            src[gf] = SRC_NONE;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const float ov = __shfl_xor(ymin, off);
+            const int oc = __shfl_xor(cs, off);
+            if (ov < ymin || (ov == ymin && oc < cs)) {
+                ymin = ov;
+                cs = oc;
+            }
+        }
+        if (lane == 0) {
+            const float yold = Y[gf];
+            Yprev[gf] = yold;
+            cstar[gf] = cs;
+            reinit[gf] = 0;
+            if (ymin < yold) {
+                Y[gf] = ymin;
+                A[gf] = A[gf] * s.amp_up;
+                improved[gf] = 1;
+                src[gf] = cs;
+            } else {
+                A[gf] = A[gf] * s.amp_down;
+                improved[gf] = 0;
+                src[gf] = SRC_NONE;
+            }
         }
     }
     __syncthreads();
