@@ -237,6 +237,71 @@ MGFWA_API const char *mgfwa_last_error(void);
 /* Library version string. */
 MGFWA_API const char *mgfwa_version(void);
 
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of many optimisation jobs on one device.     */
+/* Each job is an independent run of Alg. 1 (its own population, problem and */
+/* seed).  The server sub-allocates job workspaces from one caller-owned     */
+/* device arena, admits queued jobs in arrival order as soon as their        */
+/* workspace fits (first fit), advances every active job by one generation   */
+/* per tick on a pool of HIP streams so that different jobs' kernels overlap */
+/* on the device, and retires a job when it reaches its generation budget or */
+/* its target loss, freeing its memory for the queue.  A job's state is      */
+/* bit-identical whether it runs alone or in the mix.                        */
+/* ------------------------------------------------------------------------ */
+typedef struct mgfwa_server mgfwa_server;
+
+typedef enum { MGFWA_JOB_QUEUED = 0, MGFWA_JOB_RUNNING = 1, MGFWA_JOB_DONE = 2,
+               MGFWA_JOB_FAILED = 3 } mgfwa_job_state;
+
+typedef struct {
+    int state;              /* mgfwa_job_state */
+    int generations;        /* completed generations */
+    float best_fitness;     /* over the job's populations (valid once RUNNING) */
+    size_t workspace_bytes; /* footprint in the arena */
+    double submit_ms, admit_ms, finish_ms;  /* host clock since server creation */
+} mgfwa_job_info;
+
+typedef struct {
+    int queued, running, done, failed;
+    long generations;                 /* total generations completed */
+    double gen_ms_p50, gen_ms_p99;    /* per-generation device latency of running jobs */
+    double wall_ms;                   /* host clock since server creation */
+    double spark_evals_per_s;         /* completed candidate evaluations / wall time */
+    size_t arena_bytes, arena_used, arena_peak;
+} mgfwa_server_stats;
+
+/* Create a server over arena_dev (256-byte aligned, caller-owned, outlives the
+ * server) with n_streams HIP streams (1..64, created by the server).  */
+MGFWA_API mgfwa_status mgfwa_server_create(mgfwa_server **out, void *arena_dev,
+                                           size_t arena_bytes, int n_streams);
+
+/* Queue a job.  config->max_generations is the job's generation budget (and
+ * the loser-out horizon); use_target/target_loss stop it early.  The problem's
+ * device buffers are read when the job is admitted and must stay valid until
+ * mgfwa_server_job reports it RUNNING or later.  EINVAL on an invalid job,
+ * ENOMEM if its workspace exceeds the whole arena.  *job_id is the handle. */
+MGFWA_API mgfwa_status mgfwa_server_submit(mgfwa_server *s, const mgfwa_config *config,
+                                           const mgfwa_problem *problem, int64_t *job_id);
+
+/* One scheduling tick: collect finished generations, retire finished jobs,
+ * admit queued jobs that fit, enqueue one generation of every running job.
+ * Does not wait for the device. */
+MGFWA_API mgfwa_status mgfwa_server_tick(mgfwa_server *s);
+
+/* Tick until every submitted job is DONE or FAILED (waits for the device). */
+MGFWA_API mgfwa_status mgfwa_server_drain(mgfwa_server *s);
+
+/* Status of a job; x_host (float[D], may be NULL) receives its best position
+ * once DONE (the job's device memory is then already released: the best is
+ * kept on the host when the job retires). */
+MGFWA_API mgfwa_status mgfwa_server_job(mgfwa_server *s, int64_t job_id, mgfwa_job_info *info,
+                                        float *x_host);
+
+MGFWA_API mgfwa_status mgfwa_server_stats_get(mgfwa_server *s, mgfwa_server_stats *stats);
+
+/* Waits for outstanding work, releases every job and the streams. */
+MGFWA_API void mgfwa_server_destroy(mgfwa_server *s);
+
 #ifdef __cplusplus
 }
 #endif

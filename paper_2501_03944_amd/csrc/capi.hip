@@ -22,10 +22,10 @@
 using namespace mgfwa;
 
 namespace {
-
 thread_local char g_err[512] = "";
+}  // namespace
 
-mgfwa_status fail(mgfwa_status code, const char *fmt, ...)
+mgfwa_status mgfwa::fail(mgfwa_status code, const char *fmt, ...)
 {
     va_list ap;
     va_start(ap, fmt);
@@ -33,6 +33,8 @@ mgfwa_status fail(mgfwa_status code, const char *fmt, ...)
     va_end(ap);
     return code;
 }
+
+namespace {
 
 #define HIP_TRY(expr)                                                                    \
     do {                                                                                 \

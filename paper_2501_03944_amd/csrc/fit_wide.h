@@ -84,15 +84,21 @@ __device__ __forceinline__ int wide_swz(int row, int nch)
 // The tile list of a persistent block: groups of gs sparks (gs divides the
 // row count) go to XCD (group % 8); the XCD's bx blocks take the group's
 // gs * ntn tiles round-robin, so block j handles cj tiles of every group.
+// Inside a group, tiles are ordered so that each round of bx consecutive tiles
+// covers gs sparks x (bx / gs) sample tiles when that divides evenly (fewer
+// distinct weight and sample tiles live in the XCD's L2 at once), else spark by
+// spark.
 struct TileIter {
     int xcd, j, bx, gs, ntn, rows;
-    int cj, ngx;               // tiles per group for this block, groups on this XCD
+    int cj, ngx, cw;           // tiles per group for this block, groups here, cols per round
     __device__ __forceinline__ void setup()
     {
         const int t = gs * ntn;
         cj = j < t ? (t - 1 - j) / bx + 1 : 0;
         const int ngroups = rows / gs;
         ngx = xcd < ngroups ? (ngroups - 1 - xcd) / 8 + 1 : 0;
+        cw = bx / gs;
+        if (cw < 1 || bx % gs != 0 || ntn % cw != 0) cw = 0;
     }
     __device__ __forceinline__ int count() const { return cj * ngx; }
     // i-th tile of this block -> (spark row, sample tile)
@@ -101,8 +107,17 @@ struct TileIter {
         const int m = i / cj, ii = i - m * cj;
         const int grp = xcd + 8 * m;
         const int k = j + ii * bx;
-        *r = grp * gs + k / ntn;
-        *col = k % ntn;
+        int sp, c;
+        if (cw) {
+            const int cb = k / (gs * cw), rem = k - cb * gs * cw;
+            sp = rem / cw;
+            c = cb * cw + rem % cw;
+        } else {
+            sp = k / ntn;
+            c = k % ntn;
+        }
+        *r = grp * gs + sp;
+        *col = c;
     }
 };
 

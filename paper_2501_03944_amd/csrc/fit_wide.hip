@@ -2,6 +2,8 @@
 // plan selection and launches (kernel template in fit_wide.h).
 #include "fit_wide.h"
 
+#include <cstdlib>
+
 namespace mgfwa {
 
 using namespace fit;
@@ -122,6 +124,32 @@ const void *wide_kernel(const Net &net)
     return kWide[net.bf16 ? 1 : 0][act];
 }
 
+// Sparks per XCD tile group.  Enough tiles for the XCD's blocks; when the
+// group's rounds can be gs x (bx/gs) rectangles, the gs minimising the distinct
+// weight + sample tiles per round (gs + bx/gs); gs always divides rows.
+int wide_group(const Net &net, int rows, int ntn)
+{
+    const char *env = std::getenv("MGFWA_WIDE_GS");
+    if (env) {
+        const int g = std::atoi(env);
+        if (g >= 1 && rows % g == 0) return g;
+    }
+    const int bx = (net.num_cu + 7) / 8;
+    int gs = 1;
+    while (gs * ntn < bx && rows % (2 * gs) == 0 && gs < 64) gs *= 2;
+    if (gs * ntn < bx) return gs;
+    int best = gs, best_cost = gs + bx;
+    for (int g = gs; g <= 16; g *= 2) {
+        if (rows % g || bx % g || ntn % (bx / g)) continue;
+        const int cost = g + bx / g;
+        if (cost < best_cost) {
+            best = g;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
 }  // namespace
 
 bool wide_applicable(const Net &net)
@@ -200,11 +228,7 @@ hipError_t launch_fitness_wide(const Net &net, const DevState &d, const float *W
     a.Y = d.Ypad;
     a.lab = d.Lpad;
     a.partial = d.partial;
-    // sparks per XCD group: enough tiles for the XCD's blocks, dividing the rows
-    const int bx = (net.num_cu + 7) / 8;
-    int gs = 1;
-    while (gs * a.ntn < bx && rows % (2 * gs) == 0 && gs < 64) gs *= 2;
-    a.gs = gs;
+    a.gs = wide_group(net, rows, a.ntn);
     void *args[] = {&a};
     e = hipLaunchKernel(wide_kernel(net), dim3((unsigned)net.num_cu), dim3(TPB), args,
                         (size_t)wide_lds_bytes(net), st);

@@ -5,6 +5,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/mgfwa.h"
 #include "device_common.h"
 
 namespace mgfwa {
@@ -116,5 +117,8 @@ hipError_t launch_pack_wide_x(const Net &net, const float *x, char *Xw, hipStrea
 hipError_t launch_fitness_wide(const Net &net, const DevState &d, const float *W, size_t ld,
                                int rows, OutMap map, float *out, hipStream_t st,
                                hipEvent_t mid = nullptr);
+
+// Record the message returned by mgfwa_last_error (printf format) and return code.
+mgfwa_status fail(mgfwa_status code, const char *fmt, ...);
 
 }  // namespace mgfwa

@@ -59,6 +59,23 @@ class mgfwa_timing_info(C.Structure):
                 ("fit_kernel_ms", C.c_double), ("generations", C.c_int)]
 
 
+class mgfwa_job_info(C.Structure):
+    _fields_ = [("state", C.c_int), ("generations", C.c_int), ("best_fitness", C.c_float),
+                ("workspace_bytes", C.c_size_t), ("submit_ms", C.c_double),
+                ("admit_ms", C.c_double), ("finish_ms", C.c_double)]
+
+
+class mgfwa_server_stats(C.Structure):
+    _fields_ = [("queued", C.c_int), ("running", C.c_int), ("done", C.c_int), ("failed", C.c_int),
+                ("generations", C.c_long), ("gen_ms_p50", C.c_double), ("gen_ms_p99", C.c_double),
+                ("wall_ms", C.c_double), ("spark_evals_per_s", C.c_double),
+                ("arena_bytes", C.c_size_t), ("arena_used", C.c_size_t),
+                ("arena_peak", C.c_size_t)]
+
+
+JOB_STATE = {0: "queued", 1: "running", 2: "done", 3: "failed"}
+
+
 class MgfwaError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"mgfwa status {status}: {message}")
@@ -95,9 +112,20 @@ def lib() -> C.CDLL:
     L.mgfwa_destroy.restype = None
     L.mgfwa_last_error.restype = C.c_char_p
     L.mgfwa_version.restype = C.c_char_p
+    L.mgfwa_server_create.argtypes = [P(C.c_void_p), C.c_void_p, C.c_size_t, C.c_int]
+    L.mgfwa_server_submit.argtypes = [C.c_void_p, P(mgfwa_config), P(mgfwa_problem),
+                                      P(C.c_int64)]
+    L.mgfwa_server_tick.argtypes = [C.c_void_p]
+    L.mgfwa_server_drain.argtypes = [C.c_void_p]
+    L.mgfwa_server_job.argtypes = [C.c_void_p, C.c_int64, P(mgfwa_job_info), C.c_void_p]
+    L.mgfwa_server_stats_get.argtypes = [C.c_void_p, P(mgfwa_server_stats)]
+    L.mgfwa_server_destroy.argtypes = [C.c_void_p]
+    L.mgfwa_server_destroy.restype = None
     for name in ("mgfwa_init", "mgfwa_step", "mgfwa_best", "mgfwa_best_all", "mgfwa_ask",
                  "mgfwa_tell", "mgfwa_evaluate", "mgfwa_state", "mgfwa_set_timing",
-                 "mgfwa_timing"):
+                 "mgfwa_timing", "mgfwa_server_create", "mgfwa_server_submit",
+                 "mgfwa_server_tick", "mgfwa_server_drain", "mgfwa_server_job",
+                 "mgfwa_server_stats_get"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -139,7 +167,7 @@ def make_problem(widths, acts, loss, n_samples, x_ptr=0, y_ptr=0, labels_ptr=0) 
     return p
 
 
-# ---- C-ABI entry points under their own names ---------------------------------------
+# ---- C-ABI entry points under their own names (serving below) ---------------------------------------
 def mgfwa_workspace_bytes(config: mgfwa_config, problem: mgfwa_problem) -> int:
     return int(lib().mgfwa_workspace_bytes(C.byref(config), C.byref(problem)))
 
@@ -219,6 +247,46 @@ def mgfwa_version() -> str:
 
 
 # ---- convenience wrapper holding the torch-owned device buffers -------------------------
+def mgfwa_server_create(arena_ptr: int, arena_bytes: int, n_streams: int) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(lib().mgfwa_server_create(C.byref(h), C.c_void_p(arena_ptr), arena_bytes, n_streams))
+    return h
+
+
+def mgfwa_server_submit(server, config: mgfwa_config, problem: mgfwa_problem) -> int:
+    jid = C.c_int64()
+    _check(lib().mgfwa_server_submit(server, C.byref(config), C.byref(problem), C.byref(jid)))
+    return jid.value
+
+
+def mgfwa_server_tick(server) -> None:
+    _check(lib().mgfwa_server_tick(server))
+
+
+def mgfwa_server_drain(server) -> None:
+    _check(lib().mgfwa_server_drain(server))
+
+
+def mgfwa_server_job(server, job_id: int, dim: int = 0):
+    info = mgfwa_job_info()
+    x = np.zeros(dim, dtype=np.float32) if dim else None
+    _check(lib().mgfwa_server_job(server, job_id, C.byref(info),
+                                  x.ctypes.data_as(C.c_void_p) if dim else None))
+    d = {name: getattr(info, name) for name, _ in mgfwa_job_info._fields_}
+    d["state"] = JOB_STATE[d["state"]]
+    return d, x
+
+
+def mgfwa_server_stats_get(server) -> dict:
+    st = mgfwa_server_stats()
+    _check(lib().mgfwa_server_stats_get(server, C.byref(st)))
+    return {name: getattr(st, name) for name, _ in mgfwa_server_stats._fields_}
+
+
+def mgfwa_server_destroy(server) -> None:
+    lib().mgfwa_server_destroy(server)
+
+
 class MGFWA:
     """One optimisation job: problem buffers and workspace as torch CUDA tensors."""
 
@@ -339,3 +407,68 @@ class MGFWA:
         """Host copies of the state (synchronises)."""
         self.stream.synchronize()
         return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in self.state().items()}
+
+
+class Server:
+    """Continuous-batching server over one device arena (a torch uint8 tensor)."""
+
+    def __init__(self, arena_bytes: int, n_streams: int = 4, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        self.h = mgfwa_server_create(self.arena.data_ptr(), int(arena_bytes), int(n_streams))
+        self._keep = {}
+        self._dims = {}
+
+    def submit(self, widths, acts, loss, x=None, y=None, labels=None, **config) -> int:
+        """Queue one job; the problem's device copies live until the server is closed."""
+        torch = self.torch
+
+        def dev(a, dtype):
+            if a is None:
+                return None
+            t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a))
+            return t.to(device=self.device, dtype=dtype).contiguous()
+
+        xt = dev(x, torch.float32)
+        yt = dev(y, torch.float32) if loss == "mse" else None
+        lt = dev(labels, torch.int32) if loss == "ce" else None
+        prob = make_problem(widths, acts, loss, 0 if xt is None else xt.shape[0],
+                            0 if xt is None else xt.data_ptr(),
+                            0 if yt is None else yt.data_ptr(),
+                            0 if lt is None else lt.data_ptr())
+        torch.cuda.synchronize(self.device)   # the copies above are complete before admission
+        jid = mgfwa_server_submit(self.h, make_config(**config), prob)
+        self._keep[jid] = (xt, yt, lt)
+        self._dims[jid] = sum((widths[i] + 1) * widths[i + 1] for i in range(len(widths) - 1))
+        return jid
+
+    def submit_workload(self, wl, **config) -> int:
+        kw = dict(n_fireworks=wl.n_fireworks, n_sparks=wl.n_sparks, n_guiding=wl.n_guiding,
+                  lb=wl.lb, ub=wl.ub, max_generations=wl.generations)
+        kw.update(config)
+        return self.submit(wl.widths, wl.acts, wl.loss, wl.x, wl.y, wl.labels, **kw)
+
+    def tick(self):
+        mgfwa_server_tick(self.h)
+
+    def drain(self):
+        mgfwa_server_drain(self.h)
+
+    def job(self, jid: int):
+        return mgfwa_server_job(self.h, jid, self._dims[jid])
+
+    def stats(self) -> dict:
+        return mgfwa_server_stats_get(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            mgfwa_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

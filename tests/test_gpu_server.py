@@ -1,0 +1,125 @@
+"""Serving loop: continuous batching of optimisation jobs on one device.
+
+A job's answer must not depend on what else runs: each served job is compared
+bit for bit with the same configuration run alone through a plain context
+(whose generations are themselves checked against the oracle in the parity
+tests).  Admission is checked against the arena footprint.
+"""
+import numpy as np
+import pytest
+
+from paper_2501_03944_amd import inputs
+from gpu_util import assert_bits, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _alone(wl, **cfg):
+    torch, M = require_gpu()
+    kw = dict(n_fireworks=wl.n_fireworks, n_sparks=wl.n_sparks, n_guiding=wl.n_guiding,
+              lb=wl.lb, ub=wl.ub, max_generations=wl.generations)
+    kw.update(cfg)
+    g = M.MGFWA(wl.widths, wl.acts, wl.loss, wl.x, wl.y, wl.labels, **kw)
+    g.step(kw["max_generations"])
+    x, f, gen = g.best()
+    g.close()
+    return x, f, gen
+
+
+def _mix():
+    teacher = inputs.teacher_regression()
+    gmm = inputs.gaussian_mixture(n_samples=300)
+    small = inputs.teacher_regression(n_samples=96, widths=(5, 7, 2), seed=77)
+    return [
+        (teacher, dict(seed=5, max_generations=40)),
+        (gmm, dict(n_fireworks=2, n_sparks=16, n_guiding=4, max_generations=6, seed=3)),
+        (small, dict(n_fireworks=3, n_sparks=24, n_guiding=3, max_generations=30, seed=11,
+                     n_populations=2)),
+        (teacher, dict(seed=6, max_generations=25, precision="bf16")),
+        (small, dict(n_fireworks=2, n_sparks=8, n_guiding=2, max_generations=50, seed=12,
+                     loser_out=False)),
+    ]
+
+
+def test_served_jobs_equal_jobs_run_alone():
+    torch, M = require_gpu()
+    jobs = _mix()
+    srv = M.Server(256 << 20, n_streams=3)
+    ids = [srv.submit_workload(wl, **cfg) for wl, cfg in jobs]
+    srv.drain()
+    st = srv.stats()
+    assert st["done"] == len(jobs) and st["failed"] == 0 and st["queued"] == 0
+    assert st["arena_used"] == 0
+    assert st["generations"] == sum(cfg["max_generations"] for _, cfg in jobs)
+    assert 0 < st["gen_ms_p50"] <= st["gen_ms_p99"]
+    for jid, (wl, cfg) in zip(ids, jobs):
+        info, x = srv.job(jid)
+        xa, fa, gen = _alone(wl, **cfg)
+        assert info["state"] == "done" and info["generations"] == gen == cfg["max_generations"]
+        assert_bits(np.float32(info["best_fitness"]), np.float32(fa), f"job {jid} best fitness")
+        assert_bits(x, xa, f"job {jid} best position")
+    srv.close()
+
+
+def test_admission_respects_arena_footprint():
+    torch, M = require_gpu()
+    wl = inputs.teacher_regression(n_samples=64)
+    cfg = dict(n_fireworks=3, n_sparks=16, n_guiding=2, max_generations=12)
+    one = M.mgfwa_workspace_bytes(M.make_config(**cfg),
+                                  M.make_problem(wl.widths, wl.acts, wl.loss, 64))
+    one = (one + 255) // 256 * 256
+    srv = M.Server(2 * one + one // 2, n_streams=2)        # room for two jobs at a time
+    ids = [srv.submit_workload(wl, seed=s, **cfg) for s in range(6)]
+    max_running = 0
+    for _ in range(10000):
+        srv.tick()
+        st = srv.stats()
+        max_running = max(max_running, st["running"])
+        assert st["arena_used"] <= st["arena_bytes"]
+        if st["done"] + st["failed"] == len(ids):
+            break
+    srv.drain()
+    st = srv.stats()
+    assert st["done"] == len(ids) and max_running <= 2
+    assert st["arena_peak"] <= 2 * one and st["arena_used"] == 0
+    admits = sorted(srv.job(j)[0]["admit_ms"] for j in ids)
+    assert admits == [srv.job(j)[0]["admit_ms"] for j in ids], "admission in arrival order"
+    for s, jid in enumerate(ids):
+        info, x = srv.job(jid)
+        xa, fa, _ = _alone(wl, seed=s, **cfg)
+        assert_bits(x, xa, f"job seed {s}")
+    srv.close()
+
+
+def test_target_loss_retires_job_early():
+    torch, M = require_gpu()
+    wl = inputs.teacher_regression()
+    srv = M.Server(64 << 20, n_streams=2)
+    fast = srv.submit_workload(wl, seed=0, max_generations=200, target_loss=40.0)
+    slow = srv.submit_workload(wl, seed=1, max_generations=30)
+    srv.drain()
+    info, x = srv.job(fast)
+    xa, fa, gen = _alone(wl, seed=0, max_generations=200, target_loss=40.0)
+    assert info["generations"] == gen < 200
+    assert info["best_fitness"] <= 40.0
+    assert_bits(x, xa, "target job")
+    assert srv.job(slow)[0]["generations"] == 30
+    srv.close()
+
+
+def test_submit_errors():
+    torch, M = require_gpu()
+    wl = inputs.gaussian_mixture(n_samples=300)
+    srv = M.Server(1 << 20, n_streams=1)
+    with pytest.raises(M.MgfwaError) as e:                 # workspace larger than the arena
+        srv.submit_workload(wl)
+    assert e.value.status == M.ENOMEM
+    small = inputs.teacher_regression(n_samples=32)
+    with pytest.raises(M.MgfwaError) as e:
+        srv.submit_workload(small, external_fitness=True)
+    assert e.value.status == M.EINVAL
+    with pytest.raises(M.MgfwaError) as e:
+        srv.submit_workload(small, n_sparks=0)
+    assert e.value.status == M.EINVAL
+    assert srv.stats()["queued"] == 0
+    srv.close()
