@@ -43,8 +43,10 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1, help="1: time the oracle (rank 0)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle sample")
-    ap.add_argument("--precision-study", action="store_true",
-                    help="also run the 784-256-10 workload in BF16 and FP32 and compare")
+    ap.add_argument("--precision-study", type=int, default=1,
+                    help="1: also run the 784-256-10 workload in BF16 and FP32 and compare")
+    ap.add_argument("--batch-study", type=int, default=1,
+                    help="1: also run 64 mixed-shape BF16 jobs as one batched graph per generation")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--calib-copy-mib", type=int, default=256,
                     help="size of a plain device copy run once before the timed region; its "
@@ -132,8 +134,38 @@ def cpu_baseline(wl, seconds, seed):
                        f"initial fireworks), binary64 fitness, {dt:.1f} s")
 
 
-def precision_study(steps, seed):
+def topk_agreement(y_run, y_ref, lam, G, sigma):
+    """Guiding-group decisions (top and bottom k members of each group of m sparks)
+    taken on y_run against those taken on y_ref, both [fireworks, lam] numpy."""
+    import numpy as np
+
+    m = lam // G
+    k = max(1, int(sigma * m))
+    same_sets = overlap = groups = 0
+    for f in range(y_run.shape[0]):
+        for g in range(G):
+            a, b = y_run[f, g * m:(g + 1) * m], y_ref[f, g * m:(g + 1) * m]
+            oa, ob = np.argsort(a, kind="stable"), np.argsort(b, kind="stable")
+            ta, tb = set(oa[:k]), set(ob[:k])
+            ba, bb = set(oa[-k:]), set(ob[-k:])
+            overlap += len(ta & tb) + len(ba & bb)
+            same_sets += (ta == tb) and (ba == bb)
+            groups += 1
+    best_same = float(np.mean(np.argmin(y_run, axis=1) == np.argmin(y_ref, axis=1)))
+    return dict(member_agreement=overlap / (2.0 * k * groups),
+                groups_identical=same_sets / groups, best_spark_agreement=best_same, k=k, m=m)
+
+
+def precision_study(steps, seed, gens=3):
+    """784-256-10 in BF16 and FP32: throughput of each, and for the sparks of the
+    first generations of the BF16 run, the BF16 fitness against the FP32 fitness
+    of the same sparks (relative error, guiding top/bottom-k and best-spark
+    agreement)."""
+    import numpy as np
+    import torch
+
     from paper_2501_03944_amd import inputs
+    from paper_2501_03944_amd import mgfwa as M
 
     wl = inputs.workload("mlp784-256-10")
     out = {}
@@ -143,7 +175,86 @@ def precision_study(steps, seed):
                          ms_per_step=r["ms"] / steps,
                          fit_kernel_tflops=wl.flops_per_eval() * wl.n_fireworks * wl.n_sparks
                          / (r["timing"]["fit_kernel_ms"] / steps / 1e3) / 1e12)
+    g16 = M.MGFWA.from_workload(wl, precision="bf16", seed=seed)
+    g32 = M.MGFWA.from_workload(wl, precision="fp32", seed=seed)
+    lam, N = wl.n_sparks, wl.n_fireworks
+    rel, agree = [], []
+    for _ in range(gens):
+        g16.step(1)
+        st = g16.state()
+        y16 = st["Yc"][:, :lam].float().cpu().numpy()
+        y32 = g32.evaluate(st["SE"]).view(N, lam).cpu().numpy()
+        rel.append(np.abs(y16 - y32) / np.maximum(np.abs(y32), 1e-30))
+        agree.append(topk_agreement(y16, y32, lam, wl.n_guiding, 0.2))
+    torch.cuda.synchronize()
+    g16.close()
+    g32.close()
+    rel = np.concatenate([r.ravel() for r in rel])
+    out["bf16_vs_fp32"] = dict(
+        generations=gens, sparks=int(rel.size),
+        rel_err_max=float(rel.max()), rel_err_median=float(np.median(rel)),
+        topk_member_agreement=float(np.mean([a["member_agreement"] for a in agree])),
+        topk_groups_identical=float(np.mean([a["groups_identical"] for a in agree])),
+        best_spark_agreement=float(np.mean([a["best_spark_agreement"] for a in agree])),
+        k=agree[0]["k"], group_size=agree[0]["m"])
+    out["bf16_speedup"] = out["bf16"]["spark_evals_per_s"] / out["fp32"]["spark_evals_per_s"]
     return out
+
+
+def batch_study(steps, seed, n_jobs=64):
+    """64 independent jobs of uneven shape (D log-uniform in [1k, 50k], 2-3 layers of
+    width 32-256, 64-512 sparks, 1024-4096 samples), BF16 fitness with autotuned
+    launch shapes: one HIP graph launch per generation for all jobs, against the
+    same jobs' own per-job graphs launched one after another."""
+    import torch
+
+    from paper_2501_03944_amd import inputs
+    from paper_2501_03944_amd import mgfwa as M
+
+    wls = inputs.mixed_jobs(n_jobs=n_jobs)
+    gens = 2 * steps + 4
+    jobs = [M.MGFWA.from_workload(wl, precision="bf16", seed=seed + i, max_generations=gens)
+            for i, wl in enumerate(wls)]
+    t0 = time.perf_counter()
+    for g in jobs:
+        g.autotune(3)
+    tune_s = time.perf_counter() - t0
+    C = sum(g.BN * (wl.n_sparks + wl.n_guiding) for g, wl in zip(jobs, wls))
+    flops = sum(wl.flops_per_eval() * g.BN * (wl.n_sparks + wl.n_guiding)
+                for g, wl in zip(jobs, wls))
+    stream = torch.cuda.current_stream()
+    b = M.Batch(jobs, stream=stream)
+    b.step(1)
+    for g in jobs:
+        g.step(1)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    batched_ms = timed(lambda: b.step(steps))
+
+    def one_by_one():
+        for _ in range(steps):
+            for g in jobs:
+                g.step(1)
+
+    sequential_ms = timed(one_by_one)
+    b.close()
+    for g in jobs:
+        g.close()
+    dims = [wl.dim for wl in wls]
+    return dict(jobs=n_jobs, candidates_per_generation=C, D_min=min(dims), D_max=max(dims),
+                autotune_s=tune_s, batched_ms_per_generation=batched_ms,
+                sequential_ms_per_generation=sequential_ms,
+                spark_evals_per_s=C / (batched_ms / 1e3),
+                fitness_tflops_whole_step=flops / (batched_ms / 1e3) / 1e12,
+                speedup_vs_sequential=sequential_ms / batched_ms)
 
 
 def main():
@@ -196,6 +307,8 @@ def main():
     }
     if args.precision_study:
         line["precision_study"] = precision_study(max(2, min(K, 5)), args.seed)
+    if args.batch_study:
+        line["batch_study"] = batch_study(max(2, min(K, 10)), args.seed)
     if args.cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds, args.seed)
     print(json.dumps(line), flush=True)

@@ -238,6 +238,60 @@ MGFWA_API const char *mgfwa_last_error(void);
 MGFWA_API const char *mgfwa_version(void);
 
 /* ------------------------------------------------------------------------ */
+/* Tuning and batched generations.                                          */
+/* ------------------------------------------------------------------------ */
+
+/* The fitness launch shape of a context (the fitness step of Alg. 1 as a grouped
+ * GEMM): which = 0 explosion sparks, 1 guiding sparks. */
+typedef struct {
+    int wide;               /* 1: the K-streamed wide-first-layer kernel (fixed tiles) */
+    int rows;               /* sparks per launch */
+    int wavefronts;         /* per block */
+    int slabs;              /* 16-sample slabs per wavefront in flight */
+    int lds_weights;        /* 1: the spark's weights are staged in LDS */
+    int blocks_per_row;     /* blocks per spark (sample split) */
+    int samples_per_block;
+    int lds_bytes;
+    int row_blocks[4];      /* 16-row MFMA blocks per layer (padded widths / 16) */
+} mgfwa_plan_info;
+
+MGFWA_API mgfwa_status mgfwa_fit_plan(const mgfwa_ctx *ctx, int which, mgfwa_plan_info *info);
+
+/*
+ * Autotune the fitness launches of a context: every compiled kernel variant that
+ * covers the MLP shape, with a few sample splits, is timed on the device (reps
+ * launches each, on the context's stream, over its own spark buffers) and the
+ * fastest is kept.  The choice is cached for the process per (shape, precision,
+ * samples, sparks): any later context of the same shape takes it without timing,
+ * so a job's fitness values (whose summation order follows the launch shape)
+ * depend only on its shape, alone or in a batch.  Call before the first
+ * generation (ESTATE otherwise).  Contexts on the wide kernel keep their fixed
+ * tiles (OK, nothing changes).  Synchronises the stream.
+ */
+MGFWA_API mgfwa_status mgfwa_autotune(mgfwa_ctx *ctx, int reps);
+
+/*
+ * Batched generations: many independent jobs (contexts of any shapes, each its
+ * own run of Alg. 1 over its own workspace) advanced together by one HIP graph
+ * launch per generation.  The graph holds every job's generation as independent
+ * branches, so the kernels of different jobs overlap on the device; each job's
+ * kernels, launch shapes and results are exactly those of stepping it alone.
+ * The contexts stay owned by the caller and must outlive the batch; while they
+ * are in a batch they may still be read (best, state) and stepped alone.
+ * hip_stream: the launch stream (NULL = null stream); mgfwa_batch_step orders
+ * itself after work already queued on each job's stream and before later work
+ * there.  Errors: EINVAL (no jobs, NULL or repeated job), ESTATE (a job uses
+ * external fitness, is in an ask/tell exchange or has timing on), EHIP.
+ */
+typedef struct mgfwa_batch mgfwa_batch;
+MGFWA_API mgfwa_status mgfwa_batch_create(mgfwa_batch **out, mgfwa_ctx *const *ctxs, int n_jobs,
+                                          void *hip_stream);
+/* Enqueue n_generations generations of every job (asynchronous). */
+MGFWA_API mgfwa_status mgfwa_batch_step(mgfwa_batch *batch, int n_generations);
+/* Release the batch (waits for its launch stream); the contexts are untouched. */
+MGFWA_API void mgfwa_batch_destroy(mgfwa_batch *batch);
+
+/* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of many optimisation jobs on one device.     */
 /* Each job is an independent run of Alg. 1 (its own population, problem and */
 /* seed).  The server sub-allocates job workspaces from one caller-owned     */

@@ -14,6 +14,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "../../include/mgfwa.h"
@@ -717,6 +720,260 @@ void mgfwa_destroy(mgfwa_ctx *c)
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
     delete c;
+}
+
+}  // extern "C"
+
+// ---- autotuning ------------------------------------------------------------
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, FitPlan> g_tune;   // shape key -> timed choice, for the process
+
+std::string tune_key(const Net &net, int rows)
+{
+    std::string k = "p" + std::to_string(net.bf16) + " S" + std::to_string(net.S) + " L" +
+                    std::to_string(net.loss) + " r" + std::to_string(rows);
+    for (int l = 0; l < net.nl; ++l)
+        k += " " + std::to_string(net.fi[l]) + "x" + std::to_string(net.fo[l]) + "a" +
+             std::to_string(net.act[l]);
+    return k;
+}
+
+// Time every candidate plan for `rows` sparks of W on the context's stream and
+// keep the fastest; a shape seen before reuses its choice without timing.
+mgfwa_status tune_plan(mgfwa_ctx *c, int rows, const float *W, OutMap map, int reps, FitPlan *out)
+{
+    const std::string key = tune_key(c->net, rows);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            *out = it->second;
+            HIP_TRY(fit_prepare(*out));
+            return MGFWA_OK;
+        }
+    }
+    FitPlan cand[64];
+    const int n = fit_candidates(c->net, rows, cand, 64);
+    if (n == 0) return fail(MGFWA_EUNSUPPORTED, "no compiled fitness kernel covers this MLP shape");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int best = -1;
+    float best_ms = 0.0f;
+    mgfwa_status r = MGFWA_OK;
+    for (int i = 0; i < n && r == MGFWA_OK; ++i) {
+        hipError_t e = fit_prepare(cand[i]);
+        for (int k = 0; k <= reps && e == hipSuccess; ++k) {
+            if (k == 1) e = hipEventRecord(e0, c->stream);
+            if (e == hipSuccess)
+                e = launch_fitness(c->net, cand[i], c->d, W, c->s.Dp, rows, map, c->d.Yc, c->stream);
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            r = fail(MGFWA_EHIP, "autotune: %s", hipGetErrorString(e));
+            break;
+        }
+        if (best < 0 || ms < best_ms) {
+            best = i;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r != MGFWA_OK) return r;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto ins = g_tune.emplace(key, cand[best]);   // a concurrent tuner may have won
+        *out = ins.first->second;
+    }
+    HIP_TRY(fit_prepare(*out));
+    return MGFWA_OK;
+}
+
+}  // namespace
+
+// ---- batched generations -----------------------------------------------------
+struct mgfwa_batch {
+    std::vector<mgfwa_ctx *> jobs;
+    hipStream_t stream = nullptr;            // launch stream (caller's)
+    hipStream_t cap = nullptr;               // capture origin
+    std::vector<hipStream_t> branch;         // capture branches
+    std::vector<hipEvent_t> ev;              // fork and joins of the capture
+    std::vector<hipEvent_t> job_ev;          // per job: its own stream's queued work
+    hipEvent_t done = nullptr;               // end of the last batch step
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+};
+
+namespace {
+
+constexpr int MAX_BRANCHES = 16;
+
+hipEvent_t batch_event(mgfwa_batch *b)
+{
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    b->ev.push_back(e);
+    return e;
+}
+
+mgfwa_status batch_capture(mgfwa_batch *b)
+{
+    const int n = (int)b->jobs.size();
+    const int nb = std::min(n, MAX_BRANCHES);
+    HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    for (int i = 0; i < nb; ++i) {
+        hipStream_t st = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        b->branch.push_back(st);
+    }
+    std::vector<hipEvent_t> join(nb);
+    hipEvent_t fork = batch_event(b);
+    for (auto &e : join) e = batch_event(b);
+    if (!fork || std::find(join.begin(), join.end(), nullptr) != join.end())
+        return fail(MGFWA_EHIP, "hipEventCreate failed");
+    HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    mgfwa_status r = MGFWA_OK;
+    hipError_t e = hipEventRecord(fork, b->cap);
+    for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamWaitEvent(b->branch[i], fork, 0);
+    if (e != hipSuccess) r = fail(MGFWA_EHIP, "batch capture: %s", hipGetErrorString(e));
+    // jobs go round-robin over the branches; a branch runs its jobs in order
+    for (int i = 0; i < n && r == MGFWA_OK; ++i)
+        r = enqueue_generation(b->jobs[i], b->branch[i % nb], nullptr);
+    for (int i = 0; i < nb && r == MGFWA_OK; ++i) {
+        e = hipEventRecord(join[i], b->branch[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, join[i], 0);
+        if (e != hipSuccess) r = fail(MGFWA_EHIP, "batch capture: %s", hipGetErrorString(e));
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->cap, &g);
+    if (r != MGFWA_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return r;
+    }
+    if (e != hipSuccess) return fail(MGFWA_EHIP, "batch capture: %s", hipGetErrorString(e));
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+    return MGFWA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mgfwa_status mgfwa_autotune(mgfwa_ctx *c, int reps)
+{
+    if (!c) return fail(MGFWA_EINVAL, "ctx is NULL");
+    if (reps < 1 || reps > 1000) return fail(MGFWA_EINVAL, "reps must be in [1, 1000]");
+    if (c->cfg.external_fitness || !c->has_data)
+        return fail(MGFWA_ESTATE, "autotuning needs the built-in fitness");
+    if (c->phase != PH_READY || c->gen_host != 0 || c->gexec)
+        return fail(MGFWA_ESTATE, "autotune before the first generation");
+    if (c->net.wide) return MGFWA_OK;   // one fixed tile shape
+    const Shape &s = c->s;
+    mgfwa_status r = tune_plan(c, s.BN * s.lam, c->d.SE, OutMap{s.lam, s.C, 0}, reps, &c->plan_expl);
+    if (r) return r;
+    return tune_plan(c, s.BN * s.G, c->d.SG, OutMap{s.G, s.C, s.lam}, reps, &c->plan_guide);
+}
+
+mgfwa_status mgfwa_fit_plan(const mgfwa_ctx *c, int which, mgfwa_plan_info *info)
+{
+    if (!c || !info) return fail(MGFWA_EINVAL, "NULL argument");
+    if (which < 0 || which > 1) return fail(MGFWA_EINVAL, "which must be 0 or 1");
+    const FitPlan &p = which == 0 ? c->plan_expl : c->plan_guide;
+    std::memset(info, 0, sizeof *info);
+    info->wide = c->net.wide ? 1 : 0;
+    info->rows = which == 0 ? c->s.BN * c->s.lam : c->s.BN * c->s.G;
+    if (!c->net.wide) {
+        info->wavefronts = p.nw;
+        info->slabs = p.P;
+        info->lds_weights = p.wl;
+        info->blocks_per_row = p.bpr;
+        info->samples_per_block = p.spb;
+        info->lds_bytes = p.lds_bytes;
+        for (int l = 0; l < MAXL; ++l) info->row_blocks[l] = p.lrows[l] / 16;
+    }
+    return MGFWA_OK;
+}
+
+mgfwa_status mgfwa_batch_create(mgfwa_batch **out, mgfwa_ctx *const *ctxs, int n_jobs,
+                                void *hip_stream)
+{
+    if (!out) return fail(MGFWA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctxs || n_jobs < 1) return fail(MGFWA_EINVAL, "no jobs");
+    std::vector<mgfwa_ctx *> jobs(ctxs, ctxs + n_jobs);
+    for (int i = 0; i < n_jobs; ++i) {
+        mgfwa_ctx *c = jobs[i];
+        if (!c) return fail(MGFWA_EINVAL, "job %d is NULL", i);
+        if (c->cfg.external_fitness || c->phase != PH_READY || c->timing)
+            return fail(MGFWA_ESTATE, "job %d: needs the built-in fitness, no exchange in "
+                                      "progress and timing off", i);
+        for (int k = 0; k < i; ++k)
+            if (jobs[k] == c) return fail(MGFWA_EINVAL, "job %d appears twice", i);
+    }
+    mgfwa_batch *b = new mgfwa_batch();
+    b->jobs = jobs;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    mgfwa_status r = MGFWA_OK;
+    for (int i = 0; i <= n_jobs && r == MGFWA_OK; ++i) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            r = fail(MGFWA_EHIP, "hipEventCreate failed");
+        else if (i < n_jobs)
+            b->job_ev.push_back(e);
+        else
+            b->done = e;
+    }
+    if (r == MGFWA_OK) r = batch_capture(b);
+    if (r != MGFWA_OK) {
+        mgfwa_batch_destroy(b);
+        return r;
+    }
+    *out = b;
+    return MGFWA_OK;
+}
+
+mgfwa_status mgfwa_batch_step(mgfwa_batch *b, int n)
+{
+    if (!b) return fail(MGFWA_EINVAL, "batch is NULL");
+    if (n < 0) return fail(MGFWA_EINVAL, "n_generations < 0");
+    if (n == 0) return MGFWA_OK;
+    for (mgfwa_ctx *c : b->jobs)
+        if (c->phase != PH_READY || c->timing)
+            return fail(MGFWA_ESTATE, "a job of the batch is in an exchange or timing");
+    // work already queued on the jobs' own streams runs first, and later work
+    // on those streams waits for the batch
+    for (size_t i = 0; i < b->jobs.size(); ++i) {
+        HIP_TRY(hipEventRecord(b->job_ev[i], b->jobs[i]->stream));
+        HIP_TRY(hipStreamWaitEvent(b->stream, b->job_ev[i], 0));
+    }
+    for (int i = 0; i < n; ++i) HIP_TRY(hipGraphLaunch(b->gexec, b->stream));
+    HIP_TRY(hipEventRecord(b->done, b->stream));
+    for (mgfwa_ctx *c : b->jobs) {
+        HIP_TRY(hipStreamWaitEvent(c->stream, b->done, 0));
+        c->gen_host += n;
+    }
+    return MGFWA_OK;
+}
+
+void mgfwa_batch_destroy(mgfwa_batch *b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (hipStream_t st : b->branch) (void)hipStreamDestroy(st);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : b->job_ev) (void)hipEventDestroy(e);
+    if (b->done) (void)hipEventDestroy(b->done);
+    delete b;
 }
 
 const char *mgfwa_last_error(void) { return g_err; }

@@ -72,6 +72,41 @@ __device__ __forceinline__ floatx4 zero4()
     return z;
 }
 
+// Matrix-core multiply-accumulate in place: c += a x b with the result written
+// over the addend (dst = srcC) in accumulation registers.  Written as inline
+// assembly because with the builtin the register allocator is free to give the
+// result another register than the addend, and in a K loop over 64
+// accumulator tiles it then copies accumulators around on every step.  The
+// compiler does not track the matrix-core latency of these instructions:
+// mfma_acc_sync() must separate them from any other write or read of the
+// accumulators (zeroing before, the epilogue after).
+__device__ __forceinline__ void mfma_acc(floatx4 &c, const bf16x8 &a, const bf16x8 &b)
+{
+    asm volatile("v_mfma_f32_16x16x32_bf16 %0, %1, %2, %0" : "+a"(c) : "v"(a), "v"(b));
+}
+
+__device__ __forceinline__ void mfma_acc(floatx4 &c, float a, float b)
+{
+    asm volatile("v_mfma_f32_16x16x4_f32 %0, %1, %2, %0" : "+a"(c) : "v"(a), "v"(b));
+}
+
+// Orders the accumulators against mfma_acc: every earlier write of them is
+// complete and 24 wait states have passed before any later instruction reads or
+// writes them (more than the longest matrix-core result latency).
+template <int RB, int CB>
+__device__ __forceinline__ void mfma_acc_sync(floatx4 (&acc)[RB][CB])
+{
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) asm volatile("" : "+a"(acc[rb][cb]));
+    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7" ::: "memory");
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) asm volatile("" : "+a"(acc[rb][cb]));
+}
+
 // Four consecutive weights W[row][kbase..kbase+3] from global memory; zero
 // outside the layer.
 __device__ __forceinline__ floatx4 ldw4(const float *p, bool row_ok, int kbase, int fi, int vec)
@@ -491,6 +526,10 @@ __global__ __launch_bounds__(NW * 64) void k_fit(FitArgs a)
     const int s_end = min(s_begin + a.spb, a.S_pad);
     float lsum = 0.0f;
     for (int s0 = s_begin + wave * 16 * P; s0 < s_end; s0 += NW * 16 * P) {
+        // The staged weights are re-read from LDS for every slab: without this
+        // fence the compiler hoists those reads out of the loop and, short of
+        // registers, spills the whole weight fragment set to scratch memory.
+        asm volatile("" ::: "memory");
         floatx4 h1[P][R1];
         layer_x<BF, WL, P, R1, SCHED>(a, w0, s0, n, g, h1);
         if constexpr (R2 == 0) {

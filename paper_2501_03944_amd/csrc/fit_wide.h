@@ -98,7 +98,8 @@ struct TileIter {
         const int ngroups = rows / gs;
         ngx = xcd < ngroups ? (ngroups - 1 - xcd) / 8 + 1 : 0;
         cw = bx / gs;
-        if (cw < 1 || bx % gs != 0 || ntn % cw != 0) cw = 0;
+        // spark by spark otherwise: with cw = ntn a round covers one spark
+        if (cw < 1 || bx % gs != 0 || ntn % cw != 0) cw = ntn;
     }
     __device__ __forceinline__ int count() const { return cj * ngx; }
     // i-th tile of this block -> (spark row, sample tile)
@@ -107,17 +108,12 @@ struct TileIter {
         const int m = i / cj, ii = i - m * cj;
         const int grp = xcd + 8 * m;
         const int k = j + ii * bx;
-        int sp, c;
-        if (cw) {
-            const int cb = k / (gs * cw), rem = k - cb * gs * cw;
-            sp = rem / cw;
-            c = cb * cw + rem % cw;
-        } else {
-            sp = k / ntn;
-            c = k % ntn;
-        }
+        // branch-free: control flow here would split the accumulators' live
+        // ranges inside the K loop
+        const int cb = k / (gs * cw), rem = k - cb * gs * cw;
+        const int sp = rem / cw;
         *r = grp * gs + sp;
-        *col = c;
+        *col = cb * cw + (rem - sp * cw);
     }
 };
 
@@ -193,7 +189,7 @@ __device__ __forceinline__ void wide_mma(const char *stage, int nh, int sh, int 
                                                                  ((g ^ wide_swz(row, 4)) << 4));
 #pragma unroll
             for (int cb = 0; cb < 8; ++cb)
-                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[cb], acc[rb][cb], 0, 0, 0);
+                mfma_acc(acc[rb][cb], afr, bfr[cb]);
         }
     } else {
         // lane group g holds k = 16kk + 4g + v of the two 16-column halves kk
@@ -215,7 +211,7 @@ __device__ __forceinline__ void wide_mma(const char *stage, int nh, int sh, int 
                 for (int v = 0; v < 4; ++v)
 #pragma unroll
                     for (int cb = 0; cb < 8; ++cb)
-                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[v], bfr[cb][v], acc[rb][cb], 0, 0, 0);
+                        mfma_acc(acc[rb][cb], afr[v], bfr[cb][v]);
             }
         }
     }
@@ -388,6 +384,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         for (int rb = 0; rb < 8; ++rb)
 #pragma unroll
             for (int cb = 0; cb < 8; ++cb) acc[rb][cb] = zero4();
+        mfma_acc_sync(acc);
         const int qbase = i * a.nk;
         for (int kt0 = 0; kt0 + C::STAGES < a.nk; kt0 += C::STAGES)
             wide_round<BF>(a, smem, it, qbase + kt0, Q, wave, lane, nh, sh, n, g, acc);
@@ -397,6 +394,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         if constexpr (BF) w2_load<BF>(a, r, nh, n, g, w2);
         wide_round<BF>(a, smem, it, qbase + a.nk - C::STAGES, Q, wave, lane, nh, sh, n, g, acc);
         if constexpr (!BF) w2_load<BF>(a, r, nh, n, g, w2);
+        mfma_acc_sync(acc);
         wide_epilogue<BF, ACT>(a, smem, r, col, wave, lane, acc, w2, red);
     }
     __builtin_amdgcn_s_waitcnt(0);

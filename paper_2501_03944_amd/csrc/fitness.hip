@@ -113,7 +113,9 @@ int resident_lds_bytes(const Net &net)
     return lds_layout(net, e, &p);
 }
 
-bool fit_select(const Net &net, int rows, FitPlan *plan)
+// Whether kernel entry e covers the network; *cost is the model cost used to
+// rank the entries that do.
+static bool entry_fits(const Net &net, const KernelEntry &e, double *cost)
 {
     int need[MAXL] = {0, 0, 0, 0};
     for (int l = 0; l < net.nl; ++l) {
@@ -121,71 +123,103 @@ bool fit_select(const Net &net, int rows, FitPlan *plan)
         // BF16 chains need even 16-row blocks for every layer that feeds another
         if (net.bf16 && l < net.nl - 1 && (need[l] & 1)) need[l] += 1;
     }
+    if (e.bf16 != net.bf16) return false;
+    if (e.act >= 0) {
+        for (int l = 0; l < net.nl - 1; ++l)   // a fixed activation must match every hidden layer
+            if (net.act[l] != e.act) return false;
+    }
+    double c = 0.0;
+    for (int l = 0; l < MAXL; ++l) {
+        const bool present = l < net.nl;
+        if (present != (e.R[l] > 0) || (present && e.R[l] < need[l])) return false;
+        if (present) c += (double)e.R[l] * (l == 0 ? net.in_pad : net.fo[l - 1] + 16);
+    }
+    if (e.wl) {
+        FitPlan tmp{};
+        if (lds_layout(net, e, &tmp) > net.lds_max) return false;
+        c *= 0.5;                             // staged weights beat global fragment loads
+    }
+    if (e.act >= 0) c *= 0.9;                 // specialised activation: straight-line epilogue
     const char *env = std::getenv("MGFWA_FIT_NW");
     const int prefer_nw = env ? std::atoi(env) : 0;
+    if (prefer_nw > 0 && e.nw != prefer_nw) c *= 1.01;
+    *cost = c;
+    return true;
+}
+
+// Blocks per spark row by default: enough blocks to fill the chip (about 4 per
+// CU) while keeping at least two slab groups per wavefront.
+static int default_bpr(const Net &net, const KernelEntry &e, int rows)
+{
+    const int group = e.nw * 16 * e.P;                    // samples per block pass
+    const int max_bpr = (net.S_pad + group - 1) / group;
+    int bpr = (1024 + rows - 1) / (rows > 0 ? rows : 1);
+    const int lim = max_bpr / 2 > 0 ? max_bpr / 2 : 1;
+    if (bpr > lim) bpr = lim;
+    if (bpr > MAX_BPR) bpr = MAX_BPR;
+    return bpr < 1 ? 1 : bpr;
+}
+
+// The plan for entry e with about `bpr` blocks per row (rounded to whole block passes).
+static void make_plan(const Net &net, const KernelEntry &e, int rows, int bpr, FitPlan *plan)
+{
+    plan->kernel = e.fn;
+    plan->nw = e.nw;
+    plan->P = e.P;
+    plan->wl = e.wl;
+    plan->rows = rows;
+    lds_layout(net, e, plan);
+    if (!e.wl) plan->lds_bytes = 0;
+    const int group = e.nw * 16 * e.P;
+    int spb = (net.S_pad + bpr - 1) / bpr;
+    spb = (spb + group - 1) / group * group;
+    plan->bpr = (net.S_pad + spb - 1) / spb;
+    plan->spb = spb;
+}
+
+bool fit_select(const Net &net, int rows, FitPlan *plan)
+{
     const KernelEntry *best = nullptr;
     double best_cost = 0.0;
-    FitPlan tmp{};
     for (auto table : kTables) {
         int nent = 0;
         const KernelEntry *ents = table(&nent);
         for (int ie = 0; ie < nent; ++ie) {
-            const KernelEntry &e = ents[ie];
-            if (e.bf16 != net.bf16) continue;
-            if (e.act >= 0) {
-                bool same = true;              // a fixed activation must match every hidden layer
-                for (int l = 0; l < net.nl - 1; ++l) same = same && net.act[l] == e.act;
-                if (!same) continue;
-            }
-            bool ok = true;
             double cost = 0.0;
-            for (int l = 0; l < MAXL; ++l) {
-                const bool present = l < net.nl;
-                if (present != (e.R[l] > 0) || (present && e.R[l] < need[l])) {
-                    ok = false;
-                    break;
-                }
-                if (present) cost += (double)e.R[l] * (l == 0 ? net.in_pad : net.fo[l - 1] + 16);
-            }
-            if (!ok) continue;
-            if (e.wl) {
-                if (lds_layout(net, e, &tmp) > net.lds_max) continue;
-                cost *= 0.5;                  // staged weights beat global fragment loads
-            }
-            if (e.act >= 0) cost *= 0.9;      // specialised activation: straight-line epilogue
-            if (prefer_nw > 0 && e.nw != prefer_nw) cost *= 1.01;
+            if (!entry_fits(net, ents[ie], &cost)) continue;
             if (!best || cost < best_cost) {
-                best = &e;
+                best = &ents[ie];
                 best_cost = cost;
             }
         }
     }
     if (!best) return false;
-    plan->kernel = best->fn;
-    plan->nw = best->nw;
-    plan->P = best->P;
-    plan->wl = best->wl;
-    plan->rows = rows;
-    if (best->wl) lds_layout(net, *best, plan);
-    else {
-        lds_layout(net, *best, plan);
-        plan->lds_bytes = 0;
-    }
-    // Blocks per spark: enough blocks to fill the chip (about 4 per CU) while
-    // keeping at least two slab groups per wavefront.
-    const int group = best->nw * 16 * best->P;               // samples per block pass
-    const int max_bpr = (net.S_pad + group - 1) / group;
-    int bpr = (1024 + rows - 1) / (rows > 0 ? rows : 1);
-    int lim = max_bpr / 2 > 0 ? max_bpr / 2 : 1;
-    if (bpr > lim) bpr = lim;
-    if (bpr > MAX_BPR) bpr = MAX_BPR;
-    if (bpr < 1) bpr = 1;
-    int spb = (net.S_pad + bpr - 1) / bpr;
-    spb = (spb + group - 1) / group * group;
-    bpr = (net.S_pad + spb - 1) / spb;
-    plan->bpr = bpr;
-    plan->spb = spb;
+    make_plan(net, *best, rows, default_bpr(net, *best, rows), plan);
     return true;
+}
+
+int fit_candidates(const Net &net, int rows, FitPlan *out, int max_out)
+{
+    int n = 0;
+    for (auto table : kTables) {
+        int nent = 0;
+        const KernelEntry *ents = table(&nent);
+        for (int ie = 0; ie < nent; ++ie) {
+            double cost = 0.0;
+            if (!entry_fits(net, ents[ie], &cost)) continue;
+            const int b0 = default_bpr(net, ents[ie], rows);
+            for (int b : {b0, 2 * b0, b0 / 2, 4 * b0}) {
+                if (b < 1 || b > MAX_BPR || n >= max_out) continue;
+                FitPlan p{};
+                make_plan(net, ents[ie], rows, b, &p);
+                bool dup = false;
+                for (int i = 0; i < n; ++i)
+                    dup = dup || (out[i].kernel == p.kernel && out[i].bpr == p.bpr);
+                if (!dup) out[n++] = p;
+            }
+        }
+    }
+    return n;
 }
 
 hipError_t fit_prepare(const FitPlan &plan)

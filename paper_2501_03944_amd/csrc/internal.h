@@ -92,6 +92,9 @@ hipError_t launch_store_fitness(const float *src, int rows, OutMap map, float *o
 // ---- fitness.hip
 // Choose the kernel for the network (false if the shape is not compiled in).
 bool fit_select(const Net &net, int rows, FitPlan *plan);
+// Every plan that covers the network for `rows` sparks: each fitting kernel
+// entry with a few blocks-per-row choices; returns the count (at most max_out).
+int fit_candidates(const Net &net, int rows, FitPlan *out, int max_out);
 // Device-side preparation of a chosen plan (dynamic LDS limit); needs a device.
 hipError_t fit_prepare(const FitPlan &plan);
 // Fitness of `rows` sparks into out[map(row)]: the GEMM kernel writes one partial

@@ -17,6 +17,8 @@ provided, each at full size and at any smaller size a test wants:
   means ~ N(0, 4 I_64), unit covariance, balanced labels.
 * ``sparse_prototypes``   784-256-10 ReLU MLP, cross-entropy, inputs in
   [0, 1]^784 built from 10 seeded class prototypes with 20 % support plus noise.
+* ``mixed_jobs``          many Gaussian-mixture jobs of uneven depth, width, sample
+  count and spark count, for batched generations and serving.
 """
 from __future__ import annotations
 
@@ -199,6 +201,39 @@ def random_weights(dim: int, rows: int, seed: int, lo: float = -5.0, hi: float =
     """Uniform random weight vectors (float32 [rows, dim]) for fitness-only tests."""
     rng = np.random.default_rng(seed)
     return rng.uniform(lo, hi, size=(rows, dim)).astype(np.float32)
+
+
+def mixed_jobs(n_jobs: int = 64, seed: int = 1004, d_range=(1000, 50000), width_range=(32, 256),
+               sample_range=(1024, 4096), sparks=(16, 32, 64, 128), n_fireworks: int = 4,
+               inputs=(16, 32, 64), classes: int = 10, generations: int = 300) -> list:
+    """Independent jobs of uneven shape for batched generations: per job a target
+    D log-uniform in d_range, 2 or 3 weight layers, input width from `inputs`, one
+    hidden width (clamped to width_range) that brings D nearest the target, 10-class
+    Gaussian-mixture data with a sample count uniform in sample_range, and
+    n_fireworks x lambda sparks with lambda from `sparks` (4 guiding sparks)."""
+    rng = np.random.default_rng(seed)
+    jobs = []
+    lo_w, hi_w = width_range
+    for j in range(n_jobs):
+        target = float(np.exp(rng.uniform(np.log(d_range[0]), np.log(d_range[1]))))
+        layers = int(rng.integers(2, 4))
+        fin = int(rng.choice(inputs))
+        if layers == 2:    # D = fin*h + h + h*C + C
+            h = (target - classes) / (fin + 1 + classes)
+        else:              # D = fin*h + h + h*h + h + h*C + C
+            b = fin + 2 + classes
+            h = (-b + np.sqrt(b * b + 4.0 * (target - classes))) / 2.0
+        h = int(min(max(round(h), lo_w), hi_w))
+        widths = (fin,) + (h,) * (layers - 1) + (classes,)
+        n_samples = int(rng.integers(sample_range[0], sample_range[1] + 1))
+        lam = int(rng.choice(sparks))
+        wl = gaussian_mixture(n_samples=n_samples, widths=widths, seed=10_000 + j,
+                              n_fireworks=n_fireworks, n_sparks=lam, n_guiding=4,
+                              generations=generations)
+        wl.name = f"job{j}"
+        wl.extra["target_dim"] = target
+        jobs.append(wl)
+    return jobs
 
 
 def _apply_shape(wl: Workload, shape: dict, defaults: dict) -> None:

@@ -76,6 +76,13 @@ class mgfwa_server_stats(C.Structure):
 JOB_STATE = {0: "queued", 1: "running", 2: "done", 3: "failed"}
 
 
+class mgfwa_plan_info(C.Structure):
+    _fields_ = [("wide", C.c_int), ("rows", C.c_int), ("wavefronts", C.c_int), ("slabs", C.c_int),
+                ("lds_weights", C.c_int), ("blocks_per_row", C.c_int),
+                ("samples_per_block", C.c_int), ("lds_bytes", C.c_int),
+                ("row_blocks", C.c_int * 4)]
+
+
 class MgfwaError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"mgfwa status {status}: {message}")
@@ -112,6 +119,12 @@ def lib() -> C.CDLL:
     L.mgfwa_destroy.restype = None
     L.mgfwa_last_error.restype = C.c_char_p
     L.mgfwa_version.restype = C.c_char_p
+    L.mgfwa_autotune.argtypes = [C.c_void_p, C.c_int]
+    L.mgfwa_fit_plan.argtypes = [C.c_void_p, C.c_int, P(mgfwa_plan_info)]
+    L.mgfwa_batch_create.argtypes = [P(C.c_void_p), P(C.c_void_p), C.c_int, C.c_void_p]
+    L.mgfwa_batch_step.argtypes = [C.c_void_p, C.c_int]
+    L.mgfwa_batch_destroy.argtypes = [C.c_void_p]
+    L.mgfwa_batch_destroy.restype = None
     L.mgfwa_server_create.argtypes = [P(C.c_void_p), C.c_void_p, C.c_size_t, C.c_int]
     L.mgfwa_server_submit.argtypes = [C.c_void_p, P(mgfwa_config), P(mgfwa_problem),
                                       P(C.c_int64)]
@@ -123,7 +136,8 @@ def lib() -> C.CDLL:
     L.mgfwa_server_destroy.restype = None
     for name in ("mgfwa_init", "mgfwa_step", "mgfwa_best", "mgfwa_best_all", "mgfwa_ask",
                  "mgfwa_tell", "mgfwa_evaluate", "mgfwa_state", "mgfwa_set_timing",
-                 "mgfwa_timing", "mgfwa_server_create", "mgfwa_server_submit",
+                 "mgfwa_timing", "mgfwa_autotune", "mgfwa_fit_plan", "mgfwa_batch_create",
+                 "mgfwa_batch_step", "mgfwa_server_create", "mgfwa_server_submit",
                  "mgfwa_server_tick", "mgfwa_server_drain", "mgfwa_server_job",
                  "mgfwa_server_stats_get"):
         getattr(L, name).restype = C.c_int
@@ -247,6 +261,33 @@ def mgfwa_version() -> str:
 
 
 # ---- convenience wrapper holding the torch-owned device buffers -------------------------
+def mgfwa_autotune(ctx, reps: int = 3) -> None:
+    _check(lib().mgfwa_autotune(ctx, int(reps)))
+
+
+def mgfwa_fit_plan(ctx, which: int) -> dict:
+    info = mgfwa_plan_info()
+    _check(lib().mgfwa_fit_plan(ctx, int(which), C.byref(info)))
+    d = {name: getattr(info, name) for name, _ in mgfwa_plan_info._fields_}
+    d["row_blocks"] = list(info.row_blocks)
+    return d
+
+
+def mgfwa_batch_create(ctxs, stream: int) -> C.c_void_p:
+    arr = (C.c_void_p * len(ctxs))(*[c.value if isinstance(c, C.c_void_p) else c for c in ctxs])
+    h = C.c_void_p()
+    _check(lib().mgfwa_batch_create(C.byref(h), arr, len(ctxs), C.c_void_p(stream or None)))
+    return h
+
+
+def mgfwa_batch_step(batch, n: int) -> None:
+    _check(lib().mgfwa_batch_step(batch, int(n)))
+
+
+def mgfwa_batch_destroy(batch) -> None:
+    lib().mgfwa_batch_destroy(batch)
+
+
 def mgfwa_server_create(arena_ptr: int, arena_bytes: int, n_streams: int) -> C.c_void_p:
     h = C.c_void_p()
     _check(lib().mgfwa_server_create(C.byref(h), C.c_void_p(arena_ptr), arena_bytes, n_streams))
@@ -376,6 +417,12 @@ class MGFWA:
         mgfwa_evaluate(self.ctx, W.data_ptr(), W.shape[0], W.shape[1], out.data_ptr())
         return out
 
+    def autotune(self, reps: int = 3):
+        mgfwa_autotune(self.ctx, reps)
+
+    def fit_plan(self, which: int = 0) -> dict:
+        return mgfwa_fit_plan(self.ctx, which)
+
     def set_timing(self, on: bool):
         mgfwa_set_timing(self.ctx, on)
 
@@ -407,6 +454,30 @@ class MGFWA:
         """Host copies of the state (synchronises)."""
         self.stream.synchronize()
         return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in self.state().items()}
+
+
+class Batch:
+    """Jobs (MGFWA objects) advanced together: one HIP graph launch per generation."""
+
+    def __init__(self, jobs, stream=None):
+        import torch
+        self.jobs = list(jobs)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.h = mgfwa_batch_create([j.ctx for j in self.jobs], self.stream.cuda_stream)
+
+    def step(self, n: int = 1):
+        mgfwa_batch_step(self.h, n)
+
+    def close(self):
+        if getattr(self, "h", None):
+            mgfwa_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

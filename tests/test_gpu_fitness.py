@@ -193,10 +193,22 @@ def test_wide_bf16_fitness_error_bounded(force_wide, widths, acts, loss, S):
     print(f"wide bf16 {widths}: max abs err {err.max():.3e}, "
           f"max rel err {(err / np.maximum(np.abs(want), 1e-12)).max():.3e}")
     # bf16 operands: relative error for ordinary losses, an absolute floor
-    # (0.05 nats / units) where the exact loss is close to zero
-    assert np.all(err <= 5e-2 * np.abs(want) + 5e-2)
-    # the same sparks through the resident or global kernel agree closely too
+    # (0.05 nats / units) where the exact loss is close to zero.  Cross-entropy
+    # is a difference of logits, and rounding the operands to bf16 perturbs each
+    # logit by a few 2^-8 of its own magnitude, so its loss error scales with the
+    # logits (mean over samples of max |z|), not with the loss itself.
+    bound = 5e-2 * np.abs(want) + 5e-2
+    if loss == "ce":
+        bound = bound + 2.0 ** -6 * _logit_scale(p, W, S)
+    assert np.all(err <= bound)
     g.close()
+
+
+def _logit_scale(p, W, S, max_samples=64):
+    """Mean over (up to max_samples evenly spaced) samples of max_j |z_j|, from
+    the oracle's binary64 forward pass, per weight row."""
+    idx = np.unique(np.linspace(0, S - 1, min(S, max_samples)).astype(int))
+    return np.array([np.mean([np.max(np.abs(p.forward(w, int(s)))) for s in idx]) for w in W])
 
 
 def test_wide_and_resident_paths_agree_on_state(monkeypatch):

@@ -65,9 +65,9 @@ def test_admission_respects_arena_footprint():
     torch, M = require_gpu()
     wl = inputs.teacher_regression(n_samples=64)
     cfg = dict(n_fireworks=3, n_sparks=16, n_guiding=2, max_generations=12)
-    one = M.mgfwa_workspace_bytes(M.make_config(**cfg),
-                                  M.make_problem(wl.widths, wl.acts, wl.loss, 64))
-    one = (one + 255) // 256 * 256
+    probe = M.MGFWA.from_workload(wl, **cfg)          # the job's workspace size
+    one = (probe.nbytes + 255) // 256 * 256
+    probe.close()
     srv = M.Server(2 * one + one // 2, n_streams=2)        # room for two jobs at a time
     ids = [srv.submit_workload(wl, seed=s, **cfg) for s in range(6)]
     max_running = 0
