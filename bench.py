@@ -54,6 +54,34 @@ def parse():
     return ap.parse_args()
 
 
+PROFILE_FOR = {   # (workload, precision) -> committed rocprofv3 traffic summary of its dominant kernel
+    ("mlp64-128-128-10", "fp32"): "k_fit_mlp64-128-128-10_fp32_traffic.json",
+    ("mlp64-128-128-10", "bf16"): "k_fit_mlp64-128-128-10_bf16_traffic.json",
+    ("mlp784-256-10", "bf16"): "k_fit_wide_mlp784-256-10_bf16_traffic.json",
+    ("mlp784-256-10", "fp32"): "k_fit_wide_mlp784-256-10_fp32_traffic.json",
+}
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE /
+    WRITE_SIZE summary, or None when there is none or the kernel's sources changed
+    since the counters were taken."""
+    import hashlib
+
+    name = PROFILE_FOR.get((workload, precision))
+    path = os.path.join(ROOT, "profiles", name) if name else None
+    if not path or not os.path.exists(path):
+        return None, None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for src in sorted(rec["sources"]):
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None, name + " (stale: kernel sources changed)"
+    return rec["hbm_bytes_per_launch"], name
+
+
 def calibration_copy(mib):
     """A plain device-to-device copy of known size (read mib MiB, write mib MiB)."""
     import torch
@@ -277,6 +305,12 @@ def main():
     fit_ms = t["fit_kernel_ms"] / K
     achieved = flops / (fit_ms / 1e3) / 1e12
     peak = PEAK_TFLOPS[precision]
+    traffic, traffic_src = measured_traffic(args.workload, precision)
+    # algorithmic bytes of one launch: every spark's weights once (the wide kernel
+    # reads them packed in its own precision), the samples once
+    es = 4 if precision == "fp32" else 2
+    wide = args.workload == "mlp784-256-10"
+    alg_bytes = rows * wl.dim * (es if wide else 4) + wl.n_samples * wl.widths[0] * es
     line = {
         "metric": METRIC,
         "value": value,
@@ -294,7 +328,8 @@ def main():
                    "sparks": wl.n_sparks, "guiding": wl.n_guiding, "samples": wl.n_samples,
                    "D": wl.dim, "precision": precision, "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": traffic, "traffic_source": traffic_src,
+                     "algorithmic_bytes": alg_bytes,
                      "kernel": "k_fit (explosion-spark fitness)",
                      "flop_per_launch": flops, "avg_launch_ms": fit_ms},
         "mfma_pct_peak": 100.0 * achieved / peak,

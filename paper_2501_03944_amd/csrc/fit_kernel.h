@@ -79,15 +79,18 @@ __device__ __forceinline__ floatx4 zero4()
 // accumulator tiles it then copies accumulators around on every step.  The
 // compiler does not track the matrix-core latency of these instructions:
 // mfma_acc_sync() must separate them from any other write or read of the
-// accumulators (zeroing before, the epilogue after).
+// accumulators (zeroing before, the epilogue after).  Not volatile: a volatile
+// statement is a scheduling barrier, which would keep the LDS reads of the next
+// fragments from being issued ahead of the multiplies; the data dependences on
+// the accumulators and operands fix the order that matters.
 __device__ __forceinline__ void mfma_acc(floatx4 &c, const bf16x8 &a, const bf16x8 &b)
 {
-    asm volatile("v_mfma_f32_16x16x32_bf16 %0, %1, %2, %0" : "+a"(c) : "v"(a), "v"(b));
+    asm("v_mfma_f32_16x16x32_bf16 %0, %1, %2, %0" : "+a"(c) : "v"(a), "v"(b));
 }
 
 __device__ __forceinline__ void mfma_acc(floatx4 &c, float a, float b)
 {
-    asm volatile("v_mfma_f32_16x16x4_f32 %0, %1, %2, %0" : "+a"(c) : "v"(a), "v"(b));
+    asm("v_mfma_f32_16x16x4_f32 %0, %1, %2, %0" : "+a"(c) : "v"(a), "v"(b));
 }
 
 // Orders the accumulators against mfma_acc: every earlier write of them is

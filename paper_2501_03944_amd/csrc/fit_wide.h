@@ -10,19 +10,25 @@
 //             wavefronts owns it, each wavefront a 128 x 128 quarter (16 x 16
 //             MFMA blocks: 8 x 8 accumulator tiles);
 //  * K loop = 32 input columns per step through a ring of LDS stages filled by
-//             direct global->LDS loads (global_load_lds_dwordx4): every step
-//             issues the loads of the step STAGES-1 ahead, waits for the current
-//             one with an explicit vmcnt and a barrier, then runs its MFMAs.  Each
-//             step issues the same number of loads (past the end it re-loads the
-//             last tile into the free stage) so the wait count is a constant;
+//             direct global->LDS loads (global_load_lds_dwordx4).  BF16
+//             (k_fit_wide_pipe): a 4-stage ring and one barrier per step; each
+//             step refills the stage it consumed with the step 4 ahead and reads
+//             the next step's MFMA fragments into the second of two register
+//             sets, one load and two fragment reads interleaved with every 8
+//             multiplies, so loads, LDS reads and matrix work overlap.  FP32
+//             (k_fit_wide): a 2-stage ring, loads issued one step ahead.  Past
+//             the end a step re-loads the last tile, so wait counts are
+//             constants;
 //  * swizzle: a 16-byte chunk c of tile row r lives at chunk c ^ s(r), with
-//             s(r) = (r >> 2) & 3 for 64-byte rows (BF16) and (r >> 1) & 7 for
-//             128-byte rows (FP32), so the 16 rows read by a quarter-wavefront
-//             fall in distinct bank groups;
+//             s(r) = (r >> 1) & 3 for 64-byte rows (BF16) and r & 7 for 128-byte
+//             rows (FP32), so the 8 lanes served together by a 16-byte LDS read
+//             (8 consecutive rows, same chunk) hit 8 distinct 16-byte bank
+//             groups;
 //  * epilogue per tile: activation, layer 2 as MFMAs whose B operand is the
 //             hidden tile straight from the accumulators, the two hidden halves'
-//             logits summed through LDS, then the loss; one partial per
-//             (spark, sample tile), reduced later in a fixed order;
+//             logits summed through LDS and stored sample-major, then every lane
+//             computes one sample's loss on its own; one partial per (spark,
+//             sample tile), reduced later in a fixed order;
 //  * schedule: blocks are persistent (one per CU); tile groups of GS sparks go
 //             to one XCD, whose blocks split the group's sample tiles, so a
 //             spark's weights are fetched from HBM into that XCD's L2 once.
@@ -61,6 +67,8 @@ struct WideArgs {
     int gs;                // sparks per XCD tile group
 };
 
+constexpr int ZP = 20;      // LDS pitch (floats) of a sample's logits in the loss exchange
+
 template <bool BF>
 struct WideCfg {
     static constexpr int ES = BF ? 2 : 4;                  // bytes per element
@@ -72,13 +80,24 @@ struct WideCfg {
     static constexpr int STAGES = BF ? 3 : 2;
     static constexpr int LOADS = STAGEB / 1024 / WT_NW;    // wave loads per wave per step
     static constexpr int ZX = STAGES * STAGEB;             // logits exchange area
-    static constexpr int ZXB = 2 * 64 * 32 * 4;            // two wavefronts x 64 lanes x 32 floats
+    static constexpr int ZXB = WT_N * ZP * 4;              // logits of the tile's samples
     static constexpr int LDS = ZX + ZXB;
+    static constexpr int KMULT = BF ? 2 * WT_K : STAGES * WT_K;   // padded K is a multiple
+};
+
+// BF16 software pipeline: a 4-stage ring; fragments of the next step are read
+// from LDS while the current step multiplies.
+struct PipeCfg {
+    static constexpr int STAGES = 4;
+    static constexpr int STAGEB = WideCfg<true>::STAGEB;          // 32 KiB
+    static constexpr int LOADS = WideCfg<true>::LOADS;            // 8 per wave per step
+    static constexpr int ZX = STAGES * STAGEB;
+    static constexpr int LDS = ZX + WideCfg<true>::ZXB;           // 148 KiB
 };
 
 __device__ __forceinline__ int wide_swz(int row, int nch)
 {
-    return nch == 4 ? ((row >> 2) & 3) : ((row >> 1) & 7);
+    return nch == 4 ? ((row >> 1) & 3) : (row & 7);
 }
 
 // The tile list of a persistent block: groups of gs sparks (gs divides the
@@ -125,16 +144,19 @@ __device__ __forceinline__ void wide_issue(const WideArgs &a, char *stage, int r
     using C = WideCfg<BF>;
     const char *wrow = a.Wp + (size_t)r * a.pr + (size_t)kt * C::ROWB;
     const char *xrow = a.Xw + ((size_t)col * WT_N) * a.Kp * C::ES + (size_t)kt * C::ROWB;
-    const size_t gpitch = (size_t)a.Kp * C::ES;
+    const uint32_t gpitch = (uint32_t)a.Kp * C::ES;
     const int lr = lane / C::NCH, pc = lane % C::NCH;
 #pragma unroll
     for (int t = 0; t < C::LOADS; ++t) {
-        // wave loads alternate between the W tile and the X tile
+        // wave loads alternate between the W tile and the X tile; the base is
+        // uniform and the lane offset 32-bit (a tile spans < 4 GiB), so the
+        // load takes a scalar base plus a vector offset
         const int half = t & 1;
         const int r0 = (wave * (C::LOADS / 2) + (t >> 1)) * C::RPL;
         const int row = r0 + lr;
         const int q = pc ^ wide_swz(row, C::NCH);
-        const char *src = (half ? xrow : wrow) + (size_t)row * gpitch + q * 16;
+        const uint32_t off = (uint32_t)row * gpitch + (uint32_t)q * 16u;
+        const char *src = (half ? xrow : wrow) + off;
         char *dst = stage + half * C::TILEB + r0 * C::ROWB;
         __builtin_amdgcn_global_load_lds(src, (lds_void_t *)dst, 16, 0, 0);
     }
@@ -166,6 +188,96 @@ __device__ __forceinline__ void wait_stage()
     cfence();
 }
 
+// 16-byte LDS read issued as an instruction the compiler does not track; the
+// caller waits for it with lgkm_wait_all before using the value.
+__device__ __forceinline__ bf16x8 lds_read16(const char *p)
+{
+    bf16x8 v;
+    asm volatile("ds_read_b128 %0, %1" : "=v"(v) : "v"((const lds_void_t *)p));
+    return v;
+}
+
+// All of this wave's LDS reads have completed; the fragments passed through are
+// tied to the wait so that nothing uses them earlier.
+__device__ __forceinline__ void lgkm_wait_all(bf16x8 (&a)[8], bf16x8 (&b)[8])
+{
+    asm volatile("s_waitcnt lgkmcnt(0)"
+                 : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]),
+                   "+v"(a[6]), "+v"(a[7]), "+v"(b[0]), "+v"(b[1]), "+v"(b[2]), "+v"(b[3]),
+                   "+v"(b[4]), "+v"(b[5]), "+v"(b[6]), "+v"(b[7]));
+}
+
+// One wave load (t of LOADS) of K step kt of tile (r, col) into an LDS stage.
+__device__ __forceinline__ void pipe_issue_one(const WideArgs &a, char *stage, int r, int col,
+                                               int kt, int wave, int lane, int t)
+{
+    using C = WideCfg<true>;
+    const char *wrow = a.Wp + (size_t)r * a.pr + (size_t)kt * C::ROWB;
+    const char *xrow = a.Xw + ((size_t)col * WT_N) * a.Kp * C::ES + (size_t)kt * C::ROWB;
+    const uint32_t gpitch = (uint32_t)a.Kp * C::ES;
+    const int lr = lane / C::NCH, pc = lane % C::NCH;
+    const int half = t & 1;
+    const int r0 = (wave * (C::LOADS / 2) + (t >> 1)) * C::RPL;
+    const int row = r0 + lr;
+    const int q = pc ^ wide_swz(row, C::NCH);
+    const uint32_t off = (uint32_t)row * gpitch + (uint32_t)q * 16u;
+    const char *src = (half ? xrow : wrow) + off;
+    char *dst = stage + half * C::TILEB + r0 * C::ROWB;
+    __builtin_amdgcn_global_load_lds(src, (lds_void_t *)dst, 16, 0, 0);
+}
+
+// Wait until this wave's loads of the next step's stage have landed (the loads
+// of the two younger steps may still be in flight), then a block barrier: the
+// stage is complete for every wavefront, and every wavefront has finished
+// reading the stage that is refilled during this step.
+__device__ __forceinline__ void pipe_wait()
+{
+    constexpr int n = 2 * PipeCfg::LOADS;
+    static_assert(n < 64, "vmcnt holds at most 63");
+    cfence();
+    __builtin_amdgcn_s_waitcnt((n & 0xF) | ((n >> 4) << 14) | (7 << 4) | (15 << 8));
+    __builtin_amdgcn_s_barrier();
+    cfence();
+}
+
+// One pipelined K step q (register set P holds its fragments): refill the
+// stage of step q with step q+4, read the fragments of step q+1 into set 1-P,
+// and run the 64 multiplies of step q, interleaved one load and two reads per
+// row block of multiplies.
+template <int P>
+__device__ __forceinline__ void pipe_step(const WideArgs &a, char *smem, const TileIter &it, int q,
+                                          int Q, int wave, int lane, int nh, int sh, int n, int g,
+                                          floatx4 (&acc)[8][8], bf16x8 (&fa)[2][8],
+                                          bf16x8 (&fb)[2][8])
+{
+    using C = WideCfg<true>;
+    pipe_wait();
+    int qq = q + PipeCfg::STAGES;
+    qq = qq < Q ? qq : Q - 1;                     // past the end: re-load into the free stage
+    int r, col;
+    it.tile(qq / a.nk, &r, &col);
+    const int kt = qq % a.nk;
+    char *fill = smem + (q & (PipeCfg::STAGES - 1)) * PipeCfg::STAGEB;
+    const int qn = q + 1 < Q ? q + 1 : Q - 1;
+    const char *next = smem + (qn & (PipeCfg::STAGES - 1)) * PipeCfg::STAGEB;
+    const char *wt = next, *xt = next + C::TILEB;
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb) {
+        pipe_issue_one(a, fill, r, col, kt, wave, lane, rb);
+        {
+            const int rowb = 128 * sh + 16 * rb + n;
+            fb[1 - P][rb] = lds_read16(xt + rowb * C::ROWB + ((g ^ wide_swz(rowb, 4)) << 4));
+            const int rowa = 128 * nh + 16 * rb + n;
+            fa[1 - P][rb] = lds_read16(wt + rowa * C::ROWB + ((g ^ wide_swz(rowa, 4)) << 4));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int cb = 0; cb < 8; ++cb) mfma_acc(acc[rb][cb], fa[P][rb], fb[P][cb]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    lgkm_wait_all(fa[1 - P], fb[1 - P]);
+}
+
 // MFMAs of one K step on the stage: acc[rb][cb] over this wave's quarter.
 template <bool BF>
 __device__ __forceinline__ void wide_mma(const char *stage, int nh, int sh, int n, int g,
@@ -175,7 +287,11 @@ __device__ __forceinline__ void wide_mma(const char *stage, int nh, int sh, int 
     const char *wt = stage;
     const char *xt = stage + C::TILEB;
     if constexpr (BF) {
-        bf16x8 bfr[8];
+        // all 16 fragment reads are issued before the first multiply, so the
+        // LDS latency is paid once per step (later reads land while earlier
+        // multiplies run); the scheduling barrier keeps the compiler from
+        // re-serialising them into one register set
+        bf16x8 bfr[8], afr[8];
 #pragma unroll
         for (int cb = 0; cb < 8; ++cb) {
             const int row = 128 * sh + 16 * cb + n;
@@ -185,12 +301,14 @@ __device__ __forceinline__ void wide_mma(const char *stage, int nh, int sh, int 
 #pragma unroll
         for (int rb = 0; rb < 8; ++rb) {
             const int row = 128 * nh + 16 * rb + n;
-            const bf16x8 afr = *reinterpret_cast<const bf16x8 *>(wt + row * C::ROWB +
-                                                                 ((g ^ wide_swz(row, 4)) << 4));
-#pragma unroll
-            for (int cb = 0; cb < 8; ++cb)
-                mfma_acc(acc[rb][cb], afr, bfr[cb]);
+            afr[rb] = *reinterpret_cast<const bf16x8 *>(wt + row * C::ROWB +
+                                                        ((g ^ wide_swz(row, 4)) << 4));
         }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 8; ++cb) mfma_acc(acc[rb][cb], afr[rb], bfr[cb]);
     } else {
         // lane group g holds k = 16kk + 4g + v of the two 16-column halves kk
 #pragma unroll
@@ -244,25 +362,59 @@ __device__ __forceinline__ void w2_load(const WideArgs &a, int r, int nh, int n,
 }
 
 template <int ACT>
-__device__ __forceinline__ void wide_act(floatx4 (&acc)[8][8])
+__device__ __forceinline__ floatx4 act4(floatx4 v)
 {
 #pragma unroll
-    for (int rb = 0; rb < 8; ++rb)
+    for (int e = 0; e < 4; ++e) v[e] = act_c<ACT>(v[e]);
+    return v;
+}
+
+// Loss of one sample from its logits zz[0..fo1): cross-entropy against its
+// label (log1p form when the label holds the maximum), or the squared error
+// summed over the outputs.
+__device__ __forceinline__ float sample_loss(const WideArgs &a, int s, const float (&zz)[16])
+{
+    if (a.loss == 0) {
+        const float *y = a.Y + (size_t)s * a.fo1;
+        float acc = 0.0f;
 #pragma unroll
-        for (int cb = 0; cb < 8; ++cb)
+        for (int o = 0; o < 16; ++o)
+            if (o < a.fo1) {
+                const float e = zz[o] - y[o];
+                acc = __builtin_fmaf(e, e, acc);
+            }
+        return acc;
+    }
+    const int label = a.lab[s];
+    float mx = -__builtin_huge_valf(), zl = 0.0f;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[rb][cb][v] = act_c<ACT>(acc[rb][cb][v]);
+    for (int o = 0; o < 16; ++o)
+        if (o < a.fo1) {
+            mx = fmaxf(mx, zz[o]);
+            if (o == label) zl = zz[o];
+        }
+    float se = 0.0f, rest = 0.0f;
+#pragma unroll
+    for (int o = 0; o < 16; ++o)
+        if (o < a.fo1) {
+            const float e = expf(zz[o] - mx);
+            se += e;
+            if (o != label) rest += e;
+        }
+    return zl == mx ? log1pf(rest) : (mx - zl) + logf(se);
 }
 
 template <bool BF, int ACT>
 __device__ void wide_epilogue(const WideArgs &a, char *smem, int r, int col, int wave, int lane,
-                              floatx4 (&acc)[8][8], const W2Frag<BF> &w2, float *red)
+                              floatx4 (&acc)[8][8], const W2Frag<BF> &w2, float *red,
+                              int zx_off = WideCfg<BF>::ZX)
 {
     using C = WideCfg<BF>;
     const int n = lane & 15, g = lane >> 4, nh = wave & 1, sh = wave >> 1;
-    // activation of the hidden tile (the bias came in through the ones column)
-    wide_act<ACT>(acc);
-    // layer 2: logits of this wave's hidden half
+    // layer 2: logits of this wave's hidden half.  The activation of the hidden
+    // tile (its bias came in through the ones column) is applied as each
+    // accumulator is turned into a layer-2 operand: rewriting all 256
+    // accumulators in place first would need them all in VGPRs at once.
     floatx4 z[8][1];
 #pragma unroll
     for (int cb = 0; cb < 8; ++cb) z[cb][0] = zero4();
@@ -272,7 +424,7 @@ __device__ void wide_epilogue(const WideArgs &a, char *smem, int r, int col, int
             const bf16x8 afr = __builtin_bit_cast(bf16x8, w2.f[kb]);
 #pragma unroll
             for (int cb = 0; cb < 8; ++cb) {
-                const bf16x8 bfr = to_bf16x8(acc[2 * kb][cb], acc[2 * kb + 1][cb]);
+                const bf16x8 bfr = to_bf16x8(act4<ACT>(acc[2 * kb][cb]), act4<ACT>(acc[2 * kb + 1][cb]));
                 z[cb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr, z[cb][0], 0, 0, 0);
             }
         }
@@ -280,41 +432,57 @@ __device__ void wide_epilogue(const WideArgs &a, char *smem, int r, int col, int
 #pragma unroll
         for (int rb = 0; rb < 8; ++rb)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
+            for (int cb = 0; cb < 8; ++cb) {
+                const floatx4 h = act4<ACT>(acc[rb][cb]);
 #pragma unroll
-                for (int cb = 0; cb < 8; ++cb)
-                    z[cb][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(w2.f[rb][v], acc[rb][cb][v], z[cb][0], 0, 0, 0);
+                for (int v = 0; v < 4; ++v)
+                    z[cb][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(w2.f[rb][v], h[v], z[cb][0], 0, 0, 0);
+            }
     }
-    // the upper hidden half hands its logits to the lower half through LDS
-    float *zx = reinterpret_cast<float *>(smem + C::ZX) + (size_t)sh * 64 * 32 + lane * 32;
+    // the upper hidden half hands its partial logits to the lower half
+    float *zx = reinterpret_cast<float *>(smem + zx_off);
+    float *mine = zx + (size_t)sh * 64 * 32 + lane * 32;
     if (nh == 1) {
 #pragma unroll
-        for (int cb = 0; cb < 8; ++cb)
-            *reinterpret_cast<floatx4 *>(zx + 4 * cb) = z[cb][0];
+        for (int cb = 0; cb < 8; ++cb) *reinterpret_cast<floatx4 *>(mine + 4 * cb) = z[cb][0];
     }
     lds_barrier();
-    float lsum = 0.0f;
     if (nh == 0) {
 #pragma unroll
         for (int cb = 0; cb < 8; ++cb) {
-            const floatx4 o = *reinterpret_cast<const floatx4 *>(zx + 4 * cb);
+            const floatx4 o = *reinterpret_cast<const floatx4 *>(mine + 4 * cb);
 #pragma unroll
             for (int v = 0; v < 4; ++v) z[cb][0][v] = z[cb][0][v] + o[v] + w2.b2[v];
         }
-        // slab_loss reads the loss inputs through a FitArgs view
-        FitArgs fa;
-        fa.loss = a.loss;
-        fa.Y = a.Y;
-        fa.lab = a.lab;
-        fa.S = a.S;
-        fa.fo[0] = a.fo1;
-        lsum = slab_loss<8, 1>(fa, 0, col * WT_N + 128 * sh, n, g, z);
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) lsum += __shfl_xor(lsum, off);
-        if (lane == 0) red[sh] = lsum;
     }
     lds_barrier();
-    if (threadIdx.x == 0) a.partial[(size_t)r * a.ntn + col] = red[0] + red[1];
+    // ... which stores them sample-major (lane g of sample n holds outputs 4g..4g+3),
+    // so that afterwards every lane of the block owns one sample's logits
+    if (nh == 0) {
+#pragma unroll
+        for (int cb = 0; cb < 8; ++cb)
+            *reinterpret_cast<floatx4 *>(zx + (size_t)(128 * sh + 16 * cb + n) * ZP + 4 * g) = z[cb][0];
+    }
+    lds_barrier();
+    const int sl = 64 * wave + lane;                // sample within the tile
+    const int s = col * WT_N + sl;
+    float ls = 0.0f;
+    if (s < a.S) {
+        float zz[16];
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+            const floatx4 v = *reinterpret_cast<const floatx4 *>(zx + (size_t)sl * ZP + 4 * q4);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) zz[4 * q4 + e] = v[e];
+        }
+        ls = sample_loss(a, s, zz);
+    }
+    // fixed-order reduction: wavefront butterfly, then the four wavefronts in order
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) ls += __shfl_xor(ls, off);
+    if (lane == 0) red[wave] = ls;
+    lds_barrier();
+    if (threadIdx.x == 0) a.partial[(size_t)r * a.ntn + col] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // One K step: issue the loads STAGES-1 steps ahead, wait for this step's
@@ -354,8 +522,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 {
     using C = WideCfg<BF>;
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    __shared__ float red[2];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ float red[4];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform
     const int n = lane & 15, g = lane >> 4, nh = wave & 1, sh = wave >> 1;
     TileIter it;
     it.xcd = blockIdx.x % 8;
@@ -396,6 +565,79 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         if constexpr (!BF) w2_load<BF>(a, r, nh, n, g, w2);
         mfma_acc_sync(acc);
         wide_epilogue<BF, ACT>(a, smem, r, col, wave, lane, acc, w2, red);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+}
+
+// BF16 variant of k_fit_wide with the software pipeline above (same tiles,
+// layout, epilogue and results; the padded K is a multiple of 64).
+template <int ACT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_fit_wide_pipe(WideArgs a)
+{
+    using C = WideCfg<true>;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    __shared__ float red[4];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform
+    const int n = lane & 15, g = lane >> 4, nh = wave & 1, sh = wave >> 1;
+    TileIter it;
+    it.xcd = blockIdx.x % 8;
+    it.j = blockIdx.x / 8;
+    it.bx = (gridDim.x - it.xcd + 7) / 8;
+    it.gs = a.gs;
+    it.ntn = a.ntn;
+    it.rows = a.rows;
+    it.setup();
+    const int ntiles = it.count();
+    if (ntiles == 0) return;
+    const int Q = ntiles * a.nk;          // K steps of this block; nk is even
+    // prologue: steps 0..3 into stages 0..3, then the fragments of step 0
+#pragma unroll
+    for (int s = 0; s < PipeCfg::STAGES; ++s) {
+        const int qq = s < Q ? s : Q - 1;
+        int r, col;
+        it.tile(qq / a.nk, &r, &col);
+#pragma unroll
+        for (int t = 0; t < C::LOADS; ++t)
+            pipe_issue_one(a, smem + s * PipeCfg::STAGEB, r, col, qq % a.nk, wave, lane, t);
+    }
+    {
+        constexpr int n3 = 3 * PipeCfg::LOADS;
+        cfence();
+        __builtin_amdgcn_s_waitcnt((n3 & 0xF) | ((n3 >> 4) << 14) | (7 << 4) | (15 << 8));
+        __builtin_amdgcn_s_barrier();
+        cfence();
+    }
+    bf16x8 fa[2][8], fb[2][8];
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb) {
+        const int rowb = 128 * sh + 16 * rb + n;
+        fb[0][rb] = lds_read16(smem + C::TILEB + rowb * C::ROWB + ((g ^ wide_swz(rowb, 4)) << 4));
+        const int rowa = 128 * nh + 16 * rb + n;
+        fa[0][rb] = lds_read16(smem + rowa * C::ROWB + ((g ^ wide_swz(rowa, 4)) << 4));
+    }
+    lgkm_wait_all(fa[0], fb[0]);
+    for (int i = 0; i < ntiles; ++i) {
+        int r, col;
+        it.tile(i, &r, &col);
+        floatx4 acc[8][8];
+#pragma unroll
+        for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 8; ++cb) acc[rb][cb] = zero4();
+        mfma_acc_sync(acc);
+        const int qbase = i * a.nk;
+        for (int kt = 0; kt + 2 < a.nk; kt += 2) {
+            pipe_step<0>(a, smem, it, qbase + kt, Q, wave, lane, nh, sh, n, g, acc, fa, fb);
+            pipe_step<1>(a, smem, it, qbase + kt + 1, Q, wave, lane, nh, sh, n, g, acc, fa, fb);
+        }
+        // last two steps; the layer-2 weights are fetched meanwhile
+        W2Frag<true> w2;
+        w2_load<true>(a, r, nh, n, g, w2);
+        pipe_step<0>(a, smem, it, qbase + a.nk - 2, Q, wave, lane, nh, sh, n, g, acc, fa, fb);
+        pipe_step<1>(a, smem, it, qbase + a.nk - 1, Q, wave, lane, nh, sh, n, g, acc, fa, fb);
+        mfma_acc_sync(acc);
+        wide_epilogue<true, ACT>(a, smem, r, col, wave, lane, acc, w2, red, PipeCfg::ZX);
     }
     __builtin_amdgcn_s_waitcnt(0);
 }

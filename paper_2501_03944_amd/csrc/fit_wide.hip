@@ -114,8 +114,8 @@ __global__ __launch_bounds__(256) void k_wide_finalize(const float *__restrict__
 const void *const kWide[2][4] = {
     {reinterpret_cast<const void *>(&k_fit_wide<false, 0>), reinterpret_cast<const void *>(&k_fit_wide<false, 1>),
      reinterpret_cast<const void *>(&k_fit_wide<false, 2>), reinterpret_cast<const void *>(&k_fit_wide<false, 3>)},
-    {reinterpret_cast<const void *>(&k_fit_wide<true, 0>), reinterpret_cast<const void *>(&k_fit_wide<true, 1>),
-     reinterpret_cast<const void *>(&k_fit_wide<true, 2>), reinterpret_cast<const void *>(&k_fit_wide<true, 3>)},
+    {reinterpret_cast<const void *>(&k_fit_wide_pipe<0>), reinterpret_cast<const void *>(&k_fit_wide_pipe<1>),
+     reinterpret_cast<const void *>(&k_fit_wide_pipe<2>), reinterpret_cast<const void *>(&k_fit_wide_pipe<3>)},
 };
 
 const void *wide_kernel(const Net &net)
@@ -157,10 +157,10 @@ bool wide_applicable(const Net &net)
     return net.nl == 2 && net.fo[0] <= WT_M && net.fo[1] <= 16;
 }
 
-// K padded so that a tile's K steps are a whole number of LDS stage rounds
+// K (inputs plus the ones column) padded to the kernels' K-step rounds
 int wide_kp(const Net &net)
 {
-    const int step = WT_K * (net.bf16 ? WideCfg<true>::STAGES : WideCfg<false>::STAGES);
+    const int step = net.bf16 ? WideCfg<true>::KMULT : WideCfg<false>::KMULT;
     return (net.fi[0] + 1 + step - 1) / step * step;
 }
 
@@ -171,7 +171,7 @@ size_t wide_row_bytes(const Net &net)
     return (b + 255) / 256 * 256;
 }
 
-int wide_lds_bytes(const Net &net) { return net.bf16 ? WideCfg<true>::LDS : WideCfg<false>::LDS; }
+int wide_lds_bytes(const Net &net) { return net.bf16 ? PipeCfg::LDS : WideCfg<false>::LDS; }
 
 hipError_t wide_prepare(const Net &net)
 {
