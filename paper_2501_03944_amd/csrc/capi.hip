@@ -260,10 +260,11 @@ mgfwa_status check(mgfwa_ctx *c, hipError_t e, const char *what)
 const OutMap kFlat = {1, 1, 0};
 
 mgfwa_status fit_rows(mgfwa_ctx *c, const FitPlan &plan, const float *W, size_t ld, int rows,
-                      OutMap map, float *out, hipStream_t st, hipEvent_t mid = nullptr)
+                      OutMap map, float *out, hipStream_t st, hipEvent_t mid = nullptr,
+                      hipEvent_t pre = nullptr)
 {
     if (c->net.wide)
-        STEP(launch_fitness_wide(c->net, c->d, W, ld, rows, map, out, st, mid), "fitness_wide");
+        STEP(launch_fitness_wide(c->net, c->d, W, ld, rows, map, out, st, mid, pre), "fitness_wide");
     else
         STEP(launch_fitness(c->net, plan, c->d, W, ld, rows, map, out, st, mid), "fitness");
     return MGFWA_OK;
@@ -282,7 +283,8 @@ hipEvent_t take_event(mgfwa_ctx *c)
 }
 
 // Enqueue one generation on `st`; ev (7 events) brackets the five phases when
-// non-null, ev[6] marks the end of the explosion-fitness GEMM kernel.
+// non-null, ev[6] marks the end of the explosion-fitness GEMM kernel and ev[7]
+// its start (after the wide kernel's packing; ev[1] serves otherwise).
 mgfwa_status enqueue_generation(mgfwa_ctx *c, hipStream_t st, hipEvent_t *ev)
 {
     const Shape &s = c->s;
@@ -290,7 +292,8 @@ mgfwa_status enqueue_generation(mgfwa_ctx *c, hipStream_t st, hipEvent_t *ev)
     STEP(launch_explode(s, c->d, st), "explode");
     if (ev) STEP(hipEventRecord(ev[1], st), "event");
     mgfwa_status r = fit_rows(c, c->plan_expl, c->d.SE, s.Dp, s.BN * s.lam,
-                              OutMap{s.lam, s.C, 0}, c->d.Yc, st, ev ? ev[6] : nullptr);
+                              OutMap{s.lam, s.C, 0}, c->d.Yc, st, ev ? ev[6] : nullptr,
+                              ev && c->net.wide ? ev[7] : nullptr);
     if (r) return r;
     if (ev) STEP(hipEventRecord(ev[2], st), "event");
     STEP(launch_rank(s, c->d, st), "rank");
@@ -479,7 +482,7 @@ mgfwa_status mgfwa_step(mgfwa_ctx *c, int n)
     if (c->phase != PH_READY) return fail(MGFWA_ESTATE, "an ask/tell exchange is in progress");
     for (int i = 0; i < n; ++i) {
         if (c->timing) {
-            std::vector<hipEvent_t> ev(7);
+            std::vector<hipEvent_t> ev(8);
             for (auto &e : ev) {
                 e = take_event(c);
                 if (!e) return fail(MGFWA_EHIP, "hipEventCreate failed");
@@ -682,7 +685,7 @@ mgfwa_status mgfwa_timing(mgfwa_ctx *c, mgfwa_timing_info *info)
             HIP_TRY(hipEventElapsedTime(&ms, ev[p], ev[p + 1]));
             c->phase_ms[p] += ms;
         }
-        HIP_TRY(hipEventElapsedTime(&ms, ev[1], ev[6]));
+        HIP_TRY(hipEventElapsedTime(&ms, c->net.wide ? ev[7] : ev[1], ev[6]));
         c->fit_kernel_ms += ms;
         HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[MGFWA_N_PHASES]));
         c->gen_ms.push_back(ms);

@@ -34,7 +34,9 @@
 //             spark's weights are fetched from HBM into that XCD's L2 once.
 //
 // Packed spark layout (written by k_pack_wide, row pitch PR bytes):
-//   [0, 256*Kp*es)          W1aug[256][Kp]: W1 (zero-padded), b1 in column `in`
+//   [0, 256*Kp*es)          W1aug as [Kp/32][256][32] (K-blocked: the tile of one
+//                           K step is 16 or 32 KiB of contiguous memory): W1
+//                           (zero-padded), b1 in column `in`
 //   [.., + 16*256*es)       W2[16][256]; in BF16 each 32-column block is stored
 //                           in the order the MFMA lanes consume it
 //   [.., + 16*4)            b2[16] (FP32)
@@ -56,7 +58,7 @@ struct WideArgs {
     const char *Wp;        // packed spark rows
     size_t pr;             // packed row pitch (bytes)
     int rows;
-    const char *Xw;        // packed samples [S_pad][Kp] (element type of the kernel)
+    const char *Xw;        // packed samples, K-blocked per 256-sample tile (kernel element type)
     int Kp, nk;            // padded K and K steps
     int S, S_pad, ntn;     // samples, padded samples, sample tiles
     int fo1;               // output width (<= 16)
@@ -142,9 +144,10 @@ __device__ __forceinline__ void wide_issue(const WideArgs &a, char *stage, int r
                                            int wave, int lane)
 {
     using C = WideCfg<BF>;
-    const char *wrow = a.Wp + (size_t)r * a.pr + (size_t)kt * C::ROWB;
-    const char *xrow = a.Xw + ((size_t)col * WT_N) * a.Kp * C::ES + (size_t)kt * C::ROWB;
-    const uint32_t gpitch = (uint32_t)a.Kp * C::ES;
+    // K-blocked operands: step kt of a tile is one contiguous 256-row block
+    const char *wrow = a.Wp + (size_t)r * a.pr + (size_t)kt * C::TILEB;
+    const char *xrow = a.Xw + ((size_t)col * a.nk + kt) * C::TILEB;
+    const uint32_t gpitch = C::ROWB;
     const int lr = lane / C::NCH, pc = lane % C::NCH;
 #pragma unroll
     for (int t = 0; t < C::LOADS; ++t) {
@@ -212,9 +215,10 @@ __device__ __forceinline__ void pipe_issue_one(const WideArgs &a, char *stage, i
                                                int kt, int wave, int lane, int t)
 {
     using C = WideCfg<true>;
-    const char *wrow = a.Wp + (size_t)r * a.pr + (size_t)kt * C::ROWB;
-    const char *xrow = a.Xw + ((size_t)col * WT_N) * a.Kp * C::ES + (size_t)kt * C::ROWB;
-    const uint32_t gpitch = (uint32_t)a.Kp * C::ES;
+    // K-blocked operands: step kt of a tile is one contiguous 256-row block
+    const char *wrow = a.Wp + (size_t)r * a.pr + (size_t)kt * C::TILEB;
+    const char *xrow = a.Xw + ((size_t)col * a.nk + kt) * C::TILEB;
+    const uint32_t gpitch = C::ROWB;
     const int lr = lane / C::NCH, pc = lane % C::NCH;
     const int half = t & 1;
     const int r0 = (wave * (C::LOADS / 2) + (t >> 1)) * C::RPL;
@@ -242,8 +246,8 @@ __device__ __forceinline__ void pipe_wait()
 
 // One pipelined K step q (register set P holds its fragments): refill the
 // stage of step q with step q+4, read the fragments of step q+1 into set 1-P,
-// and run the 64 multiplies of step q, interleaved one load and two reads per
-// row block of multiplies.
+// and run the 64 multiplies of step q; per row block of 8 multiplies, two
+// fragment reads go first and one load in the middle.
 template <int P>
 __device__ __forceinline__ void pipe_step(const WideArgs &a, char *smem, const TileIter &it, int q,
                                           int Q, int wave, int lane, int nh, int sh, int n, int g,
@@ -263,7 +267,6 @@ __device__ __forceinline__ void pipe_step(const WideArgs &a, char *smem, const T
     const char *wt = next, *xt = next + C::TILEB;
 #pragma unroll
     for (int rb = 0; rb < 8; ++rb) {
-        pipe_issue_one(a, fill, r, col, kt, wave, lane, rb);
         {
             const int rowb = 128 * sh + 16 * rb + n;
             fb[1 - P][rb] = lds_read16(xt + rowb * C::ROWB + ((g ^ wide_swz(rowb, 4)) << 4));
@@ -272,7 +275,12 @@ __device__ __forceinline__ void pipe_step(const WideArgs &a, char *smem, const T
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int cb = 0; cb < 8; ++cb) mfma_acc(acc[rb][cb], fa[P][rb], fb[P][cb]);
+        for (int cb = 0; cb < 4; ++cb) mfma_acc(acc[rb][cb], fa[P][rb], fb[P][cb]);
+        __builtin_amdgcn_sched_barrier(0);
+        pipe_issue_one(a, fill, r, col, kt, wave, lane, rb);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int cb = 4; cb < 8; ++cb) mfma_acc(acc[rb][cb], fa[P][rb], fb[P][cb]);
         __builtin_amdgcn_sched_barrier(0);
     }
     lgkm_wait_all(fa[1 - P], fb[1 - P]);

@@ -14,7 +14,8 @@ constexpr int TPB = 256;
 constexpr int MAX_GRID_Y = 65535;
 
 // One 16-byte chunk of a packed spark row per thread.  Chunk ranges:
-//   W1aug  [256][Kp]     value(o, k) = W1[o][k] (k < in), b1[o] (k == in), 0
+//   W1aug  [Kp/32][256][32]  K-blocked: value(o, k) = W1[o][k] (k < in),
+//                        b1[o] (k == in), 0 otherwise, at ((k/32)*256 + o)*32 + k%32
 //   W2     [16][256]     BF16: chunk (i, kb, g) holds W2[i][32kb + p(g, e)], e = 0..7,
 //                        p(g, e) = 4g + e (e < 4) or 16 + 4g + e - 4 (e >= 4);
 //                        FP32: natural order
@@ -35,7 +36,8 @@ __global__ __launch_bounds__(TPB) void k_pack_wide_rows(const float *__restrict_
         const float *w = W + (size_t)r * ld;
         float v[EPC];
         if (chunk < c1) {
-            const int e0 = chunk * EPC, o = e0 / Kp, k0 = e0 % Kp;
+            const int e0 = chunk * EPC, kb = e0 / (WT_M * WT_K), rem = e0 % (WT_M * WT_K);
+            const int o = rem / WT_K, k0 = kb * WT_K + rem % WT_K;
 #pragma unroll
             for (int e = 0; e < EPC; ++e) {
                 const int k = k0 + e;
@@ -84,7 +86,9 @@ __global__ __launch_bounds__(TPB) void k_pack_wide_rows(const float *__restrict_
     }
 }
 
-// Samples for the wide kernel: [S_pad][Kp], column `in` = 1 (the folded bias).
+// Samples for the wide kernel, column `in` = 1 (the folded bias), K-blocked per
+// 256-sample tile: element (s, k) at ((s/256 * Kp/32 + k/32) * 256 + s%256) * 32 + k%32,
+// so one K step of one sample tile is a contiguous 256 x 32 block.
 template <bool BF>
 __global__ __launch_bounds__(TPB) void k_pack_wide_x(const float *__restrict__ x, int S, int S_pad,
                                                      int in, int Kp, char *__restrict__ Xw)
@@ -94,8 +98,10 @@ __global__ __launch_bounds__(TPB) void k_pack_wide_x(const float *__restrict__ x
     const int s = (int)(tid / Kp), k = (int)(tid % Kp);
     float v = 0.0f;
     if (s < S) v = k < in ? x[(size_t)s * in + k] : (k == in ? 1.0f : 0.0f);
-    if constexpr (BF) reinterpret_cast<uint16_t *>(Xw)[tid] = __builtin_bit_cast(uint16_t, (__bf16)v);
-    else reinterpret_cast<float *>(Xw)[tid] = v;
+    const int nk = Kp / WT_K;
+    const size_t dst = (((size_t)(s / WT_N) * nk + k / WT_K) * WT_N + s % WT_N) * WT_K + k % WT_K;
+    if constexpr (BF) reinterpret_cast<uint16_t *>(Xw)[dst] = __builtin_bit_cast(uint16_t, (__bf16)v);
+    else reinterpret_cast<float *>(Xw)[dst] = v;
 }
 
 __global__ __launch_bounds__(256) void k_wide_finalize(const float *__restrict__ partial, int rows,
@@ -194,7 +200,8 @@ hipError_t launch_pack_wide_x(const Net &net, const float *x, char *Xw, hipStrea
 }
 
 hipError_t launch_fitness_wide(const Net &net, const DevState &d, const float *W, size_t ld,
-                               int rows, OutMap map, float *out, hipStream_t st, hipEvent_t mid)
+                               int rows, OutMap map, float *out, hipStream_t st, hipEvent_t mid,
+                               hipEvent_t pre)
 {
     if (rows <= 0) return hipSuccess;
     const int Kp = wide_kp(net);
@@ -212,6 +219,10 @@ hipError_t launch_fitness_wide(const Net &net, const DevState &d, const float *W
                            net.woff[1], net.boff[1]);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (pre) {                          // packing done: the GEMM kernel starts here
+        e = hipEventRecord(pre, st);
+        if (e != hipSuccess) return e;
+    }
     WideArgs a;
     a.Wp = d.Wpack;
     a.pr = pr;

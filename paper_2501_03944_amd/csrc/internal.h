@@ -119,7 +119,7 @@ hipError_t wide_prepare(const Net &net);
 hipError_t launch_pack_wide_x(const Net &net, const float *x, char *Xw, hipStream_t st);
 hipError_t launch_fitness_wide(const Net &net, const DevState &d, const float *W, size_t ld,
                                int rows, OutMap map, float *out, hipStream_t st,
-                               hipEvent_t mid = nullptr);
+                               hipEvent_t mid = nullptr, hipEvent_t pre = nullptr);
 
 // Record the message returned by mgfwa_last_error (printf format) and return code.
 mgfwa_status fail(mgfwa_status code, const char *fmt, ...);
