@@ -434,18 +434,41 @@ __device__ __forceinline__ void bias_act(const FitArgs &a, const float *w, const
     }
 }
 
+// v and its partner in lane l ^ 16 (or l ^ 32), exchanged with gfx950's row-swap
+// instructions (plain VALU work, no LDS round trip).  Each lane gets both values,
+// its own and its partner's in some order; sums and maxima of the pair are then
+// the same in every lane, bit for bit, as v op shfl_xor(v, 16).
+__device__ __forceinline__ void pair16(float v, float &a, float &b)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ void pair32(float v, float &a, float &b)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+
+// Sum / maximum over the four lanes l, l^16, l^32, l^48.
 __device__ __forceinline__ float xor_sum4(float v)
 {
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    return v;
+    float a, b;
+    pair16(v, a, b);
+    v = a + b;
+    pair32(v, a, b);
+    return a + b;
 }
 
 __device__ __forceinline__ float xor_max4(float v)
 {
-    v = fmaxf(v, __shfl_xor(v, 16));
-    v = fmaxf(v, __shfl_xor(v, 32));
-    return v;
+    float a, b;
+    pair16(v, a, b);
+    v = fmaxf(a, b);
+    pair32(v, a, b);
+    return fmaxf(a, b);
 }
 
 // Sum of the per-sample losses of this wavefront's P slabs (valid in lanes g == 0).

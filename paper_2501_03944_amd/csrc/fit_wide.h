@@ -380,7 +380,8 @@ __device__ __forceinline__ floatx4 act4(floatx4 v)
 // Loss of one sample from its logits zz[0..fo1): cross-entropy against its
 // label (log1p form when the label holds the maximum), or the squared error
 // summed over the outputs.
-__device__ __forceinline__ float sample_loss(const WideArgs &a, int s, const float (&zz)[16])
+__device__ __forceinline__ float sample_loss(const WideArgs &a, int s, int label,
+                                             const float (&zz)[16])
 {
     if (a.loss == 0) {
         const float *y = a.Y + (size_t)s * a.fo1;
@@ -393,7 +394,6 @@ __device__ __forceinline__ float sample_loss(const WideArgs &a, int s, const flo
             }
         return acc;
     }
-    const int label = a.lab[s];
     float mx = -__builtin_huge_valf(), zl = 0.0f;
 #pragma unroll
     for (int o = 0; o < 16; ++o)
@@ -412,9 +412,17 @@ __device__ __forceinline__ float sample_loss(const WideArgs &a, int s, const flo
     return zl == mx ? log1pf(rest) : (mx - zl) + logf(se);
 }
 
+// Label of the sample this lane scores in the epilogue of tile column col
+// (fetched early: its load latency would otherwise sit in the epilogue).
+__device__ __forceinline__ int tile_label(const WideArgs &a, int col, int wave, int lane)
+{
+    const int s = col * WT_N + 64 * wave + lane;
+    return (a.loss == 1 && s < a.S) ? a.lab[s] : 0;
+}
+
 template <bool BF, int ACT>
 __device__ void wide_epilogue(const WideArgs &a, char *smem, int r, int col, int wave, int lane,
-                              floatx4 (&acc)[8][8], const W2Frag<BF> &w2, float *red,
+                              floatx4 (&acc)[8][8], const W2Frag<BF> &w2, float *red, int label,
                               int zx_off = WideCfg<BF>::ZX)
 {
     using C = WideCfg<BF>;
@@ -483,7 +491,7 @@ __device__ void wide_epilogue(const WideArgs &a, char *smem, int r, int col, int
 #pragma unroll
             for (int e = 0; e < 4; ++e) zz[4 * q4 + e] = v[e];
         }
-        ls = sample_loss(a, s, zz);
+        ls = sample_loss(a, s, label, zz);
     }
     // fixed-order reduction: wavefront butterfly, then the four wavefronts in order
 #pragma unroll
@@ -572,7 +580,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         wide_round<BF>(a, smem, it, qbase + a.nk - C::STAGES, Q, wave, lane, nh, sh, n, g, acc);
         if constexpr (!BF) w2_load<BF>(a, r, nh, n, g, w2);
         mfma_acc_sync(acc);
-        wide_epilogue<BF, ACT>(a, smem, r, col, wave, lane, acc, w2, red);
+        wide_epilogue<BF, ACT>(a, smem, r, col, wave, lane, acc, w2, red,
+                               tile_label(a, col, wave, lane));
     }
     __builtin_amdgcn_s_waitcnt(0);
 }
@@ -634,18 +643,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
             for (int cb = 0; cb < 8; ++cb) acc[rb][cb] = zero4();
         mfma_acc_sync(acc);
+        // the epilogue's global inputs are fetched at the start of the tile
+        W2Frag<true> w2;
+        w2_load<true>(a, r, nh, n, g, w2);
+        const int label = tile_label(a, col, wave, lane);
         const int qbase = i * a.nk;
-        for (int kt = 0; kt + 2 < a.nk; kt += 2) {
+        for (int kt = 0; kt < a.nk; kt += 2) {
             pipe_step<0>(a, smem, it, qbase + kt, Q, wave, lane, nh, sh, n, g, acc, fa, fb);
             pipe_step<1>(a, smem, it, qbase + kt + 1, Q, wave, lane, nh, sh, n, g, acc, fa, fb);
         }
-        // last two steps; the layer-2 weights are fetched meanwhile
-        W2Frag<true> w2;
-        w2_load<true>(a, r, nh, n, g, w2);
-        pipe_step<0>(a, smem, it, qbase + a.nk - 2, Q, wave, lane, nh, sh, n, g, acc, fa, fb);
-        pipe_step<1>(a, smem, it, qbase + a.nk - 1, Q, wave, lane, nh, sh, n, g, acc, fa, fb);
         mfma_acc_sync(acc);
-        wide_epilogue<true, ACT>(a, smem, r, col, wave, lane, acc, w2, red, PipeCfg::ZX);
+        wide_epilogue<true, ACT>(a, smem, r, col, wave, lane, acc, w2, red, label, PipeCfg::ZX);
     }
     __builtin_amdgcn_s_waitcnt(0);
 }
