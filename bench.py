@@ -47,6 +47,9 @@ def parse():
                     help="1: also run the 784-256-10 workload in BF16 and FP32 and compare")
     ap.add_argument("--batch-study", type=int, default=1,
                     help="1: also run 64 mixed-shape BF16 jobs as one batched graph per generation")
+    ap.add_argument("--serving-study", type=int, default=1,
+                    help="1: also run a Poisson stream of mixed jobs through the serving loop")
+    ap.add_argument("--serve-seconds", type=float, default=8.0, help="arrival window of that study")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--calib-copy-mib", type=int, default=256,
                     help="size of a plain device copy run once before the timed region; its "
@@ -285,6 +288,80 @@ def batch_study(steps, seed, n_jobs=64):
                 speedup_vs_sequential=sequential_ms / batched_ms)
 
 
+# serving mix: (workload, share of arrivals, precision, generation budget, target loss)
+SERVE_MIX = (("mlp8-16-1", 0.70, "fp32", 100, 40.0),
+             ("mlp64-128-128-10", 0.25, "fp32", 30, None),
+             ("mlp784-256-10", 0.05, "bf16", 10, None))
+
+
+def serving_study(seconds, seed, rate=20.0, arena_gib=64, n_streams=4):
+    """Poisson arrivals (rate jobs/s over `seconds`) of the SERVE_MIX shapes into the
+    continuous-batching server; per-generation device latency p50/p99, throughput,
+    and the offered load implied by the single-job generation times."""
+    import numpy as np
+    import torch
+
+    from paper_2501_03944_amd import inputs
+    from paper_2501_03944_amd import mgfwa as M
+
+    rng = np.random.default_rng(1234 + seed)
+    t, arrivals = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > seconds:
+            break
+        arrivals.append(t)
+    shares = np.array([m[1] for m in SERVE_MIX])
+    kinds = rng.choice(len(SERVE_MIX), size=len(arrivals), p=shares / shares.sum())
+    wls = []
+    for name, _, _, _, _ in SERVE_MIX:
+        wl = inputs.workload(name)
+        # device copies once; every job of the kind shares them
+        wl.x = torch.from_numpy(wl.x).cuda()
+        wl.y = None if wl.y is None else torch.from_numpy(wl.y).cuda()
+        wl.labels = None if wl.labels is None else torch.from_numpy(wl.labels).cuda()
+        wls.append(wl)
+    torch.cuda.synchronize()
+    srv = M.Server(arena_gib << 30, n_streams=n_streams)
+    t0 = time.perf_counter()
+    i, ids = 0, []
+    while True:
+        now = time.perf_counter() - t0
+        while i < len(arrivals) and arrivals[i] <= now:
+            name, _, prec, gens, target = SERVE_MIX[kinds[i]]
+            ids.append(srv.submit_workload(wls[kinds[i]], sync=False, precision=prec,
+                                           max_generations=gens, target_loss=target,
+                                           seed=seed + i))
+            i += 1
+        srv.tick()
+        if i == len(arrivals):
+            st = srv.stats()
+            if st["queued"] == 0 and st["running"] == 0:
+                break
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    infos = [srv.job(j)[0] for j in ids]
+    srv.close()
+    waits = [x["admit_ms"] - x["submit_ms"] for x in infos]
+    turn = [x["finish_ms"] - x["submit_ms"] for x in infos]
+    counts = {SERVE_MIX[k][0]: int((kinds == k).sum()) for k in range(len(SERVE_MIX))}
+    # offered matrix work: every arrived job run to its full generation budget
+    offered = sum(counts[m[0]] * m[3] * wl.n_fireworks * (wl.n_sparks + wl.n_guiding)
+                  * wl.flops_per_eval() for m, wl in zip(SERVE_MIX, wls)) / seconds
+    return dict(arrival_rate_jobs_per_s=rate, arrival_window_s=seconds, jobs=len(ids),
+                mix={m[0]: dict(share=m[1], precision=m[2], generations=m[3],
+                                target_loss=m[4], arrived=counts[m[0]]) for m in SERVE_MIX},
+                done=st["done"], failed=st["failed"], generations=st["generations"],
+                gen_latency_ms={"p50": st["gen_ms_p50"], "p99": st["gen_ms_p99"]},
+                spark_evals_per_s=st["spark_evals_per_s"], wall_s=wall,
+                admission_wait_ms={"p50": float(np.percentile(waits, 50)),
+                                   "p99": float(np.percentile(waits, 99))},
+                turnaround_ms={"p50": float(np.percentile(turn, 50)),
+                               "p99": float(np.percentile(turn, 99))},
+                offered_tflops_at_full_budgets=offered / 1e12,
+                arena_gib=arena_gib, arena_peak_gib=st["arena_peak"] / 2**30, streams=n_streams)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -342,6 +419,8 @@ def main():
     }
     if args.precision_study:
         line["precision_study"] = precision_study(max(2, min(K, 5)), args.seed)
+    if args.serving_study:
+        line["serving_study"] = serving_study(args.serve_seconds, args.seed)
     if args.batch_study:
         line["batch_study"] = batch_study(max(2, min(K, 10)), args.seed)
     if args.cpu_baseline:

@@ -492,8 +492,10 @@ class Server:
         self._keep = {}
         self._dims = {}
 
-    def submit(self, widths, acts, loss, x=None, y=None, labels=None, **config) -> int:
-        """Queue one job; the problem's device copies live until the server is closed."""
+    def submit(self, widths, acts, loss, x=None, y=None, labels=None, sync=True, **config) -> int:
+        """Queue one job; the problem's device copies live until the server is closed.
+        sync=False skips the device synchronisation that makes freshly uploaded inputs
+        visible to the job's stream (pass it for inputs already complete on the device)."""
         torch = self.torch
 
         def dev(a, dtype):
@@ -509,17 +511,18 @@ class Server:
                             0 if xt is None else xt.data_ptr(),
                             0 if yt is None else yt.data_ptr(),
                             0 if lt is None else lt.data_ptr())
-        torch.cuda.synchronize(self.device)   # the copies above are complete before admission
+        if sync:
+            torch.cuda.synchronize(self.device)   # the copies above are complete before admission
         jid = mgfwa_server_submit(self.h, make_config(**config), prob)
         self._keep[jid] = (xt, yt, lt)
         self._dims[jid] = sum((widths[i] + 1) * widths[i + 1] for i in range(len(widths) - 1))
         return jid
 
-    def submit_workload(self, wl, **config) -> int:
+    def submit_workload(self, wl, sync=True, **config) -> int:
         kw = dict(n_fireworks=wl.n_fireworks, n_sparks=wl.n_sparks, n_guiding=wl.n_guiding,
                   lb=wl.lb, ub=wl.ub, max_generations=wl.generations)
         kw.update(config)
-        return self.submit(wl.widths, wl.acts, wl.loss, wl.x, wl.y, wl.labels, **kw)
+        return self.submit(wl.widths, wl.acts, wl.loss, wl.x, wl.y, wl.labels, sync=sync, **kw)
 
     def tick(self):
         mgfwa_server_tick(self.h)
