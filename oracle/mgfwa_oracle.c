@@ -249,10 +249,31 @@ struct orc_state {
     int32_t *cstar, *improved, *reinit;
     int32_t *best_f, *best_gen;
     float *best_x, *best_y;
+    float *lo, *hi;          /* [B][D] population ranges (map_range) */
 };
 
 enum { PH_NEW = 0, PH_NEED_INIT_FIT, PH_READY, PH_NEED_EXPL_FIT, PH_EXPL_DONE, PH_NEED_GUIDE_FIT,
-       PH_GUIDE_DONE };
+       PH_GUIDE_DONE, PH_LAG_GUIDED };
+
+/* The ranges of every population from the current fireworks (map_range). */
+static void update_ranges(orc_state *st)
+{
+    if (!st->c.map_range) return;
+    const size_t D = (size_t)st->D;
+    for (int b = 0; b < st->c.B; ++b)
+        orc_population_range(st->c.N, st->D, st->F + (size_t)b * st->c.N * D, st->lo + b * D,
+                             st->hi + b * D);
+}
+
+static const float *range_lo(const orc_state *st, int gf)
+{
+    return st->c.map_range ? st->lo + (size_t)(gf / st->c.N) * st->D : NULL;
+}
+
+static const float *range_hi(const orc_state *st, int gf)
+{
+    return st->c.map_range ? st->hi + (size_t)(gf / st->c.N) * st->D : NULL;
+}
 
 /* A fitness value as the state path stores it: NaN becomes +inf. */
 static float canon(float y) { return isnan(y) ? INFINITY : y; }
@@ -265,11 +286,35 @@ void orc_init_row(const orc_config *c, int dim, uint32_t row, uint32_t t, int ta
         x[d] = uniform_in_box(c, orc_u01(orc_word(c->seed, tag, row, t, (uint32_t)d)));
 }
 
+/* Random mapping of one out-of-box coordinate from its draw u2: uniform in the
+ * box, or (map_range) uniform in the population's range lo..hi of that
+ * dimension, fma(u2, hi - lo, lo), clamped into the box. */
+static float map_coordinate(const orc_config *c, float u2, const float *lo, const float *hi, int d)
+{
+    if (!lo) return uniform_in_box(c, u2);
+    float width = hi[d] - lo[d];
+    return clampf(fmaf(u2, width, lo[d]), c->lb, c->ub);
+}
+
+void orc_population_range(int n, int dim, const float *F, float *lo, float *hi)
+{
+    for (int d = 0; d < dim; ++d) {
+        float a = F[d], b = F[d];
+        for (int f = 1; f < n; ++f) {
+            float v = F[(size_t)f * dim + d];
+            if (v < a) a = v;
+            if (v > b) b = v;
+        }
+        lo[d] = a;
+        hi[d] = b;
+    }
+}
+
 /* Explosion spark: every coordinate moves by A*(2u-1), u uniform; a coordinate
- * that leaves [lb, ub] is mapped to a fresh uniform position in the box drawn
- * from its own stream (the reading of the random mapping). */
+ * that leaves [lb, ub] is mapped to a fresh uniform position drawn from its own
+ * stream (the reading of the random mapping; lo/hi select the range variant). */
 void orc_explosion_row(const orc_config *c, int dim, const float *x, float amp, uint32_t row,
-                       uint32_t t, float *s)
+                       uint32_t t, const float *lo, const float *hi, float *s)
 {
     for (int d = 0; d < dim; ++d) {
         float u = orc_u01(orc_word(c->seed, ORC_TAG_EXPL, row, t, (uint32_t)d));
@@ -277,7 +322,7 @@ void orc_explosion_row(const orc_config *c, int dim, const float *x, float amp, 
         float sv = fmaf(amp, v, x[d]);
         if (sv < c->lb || sv > c->ub) {
             float u2 = orc_u01(orc_word(c->seed, ORC_TAG_EXPL_MAP, row, t, (uint32_t)d));
-            sv = uniform_in_box(c, u2);
+            sv = map_coordinate(c, u2, lo, hi, d);
         }
         s[d] = sv;
     }
@@ -327,6 +372,8 @@ orc_state *orc_create(const orc_config *c, const orc_problem *p)
     st->best_gen = xcalloc(c->B, sizeof(int32_t));
     st->best_x = xcalloc((size_t)c->B * D, sizeof(float));
     st->best_y = xcalloc(c->B, sizeof(float));
+    st->lo = xcalloc((size_t)c->B * st->D, sizeof(float));
+    st->hi = xcalloc((size_t)c->B * st->D, sizeof(float));
     st->phase = PH_NEW;
     return st;
 }
@@ -339,6 +386,7 @@ void orc_destroy(orc_state *st)
     free(st->top); free(st->bottom); free(st->tie);
     free(st->cstar); free(st->improved); free(st->reinit);
     free(st->best_f); free(st->best_gen); free(st->best_x); free(st->best_y);
+    free(st->lo); free(st->hi);
     free(st);
 }
 
@@ -430,14 +478,15 @@ int orc_eval_init(orc_state *st)
 /* Alg. 1, explosion sparks of every firework plus their random mapping. */
 int orc_explode(orc_state *st)
 {
-    if (!want(st, PH_READY, "explode")) return -1;
+    if (!want(st, st->c.lag_guiding ? PH_LAG_GUIDED : PH_READY, "explode")) return -1;
     const uint32_t tn = (uint32_t)(st->t + 1);
     const int lam = st->c.lambda;
+    update_ranges(st);
     for (int gf = 0; gf < st->BN; ++gf)
         for (int j = 0; j < lam; ++j) {
             uint32_t row = (uint32_t)(gf * lam + j);
             orc_explosion_row(&st->c, st->D, st->F + (size_t)gf * st->D, st->A[gf], row, tn,
-                              st->SE + (size_t)row * st->D);
+                              range_lo(st, gf), range_hi(st, gf), st->SE + (size_t)row * st->D);
         }
     st->phase = PH_NEED_EXPL_FIT;
     return 0;
@@ -532,19 +581,34 @@ void orc_guide_group(int m, int k, int dim, const float *sparks, const float *y,
 
 int orc_guide(orc_state *st)
 {
-    if (!want(st, PH_EXPL_DONE, "guide")) return -1;
+    const int lag = st->c.lag_guiding;
+    if (!want(st, lag ? PH_READY : PH_EXPL_DONE, "guide")) return -1;
     const int G = st->c.G, m = st->m, k = st->k, lam = st->c.lambda;
     const size_t D = (size_t)st->D;
     const uint32_t tn = (uint32_t)(st->t + 1);
+    update_ranges(st);
+    /* lag: the explosion sparks and fitness in SE / Yc are the previous
+     * generation's; before the first generation there are none, and every
+     * guiding vector is zero (the group counts as tied) */
+    const int none_yet = lag && st->t == 0;
     for (int gf = 0; gf < st->BN; ++gf) {
         for (int g = 0; g < G; ++g) {
             const size_t gidx = (size_t)gf * G + g;
             const size_t first = (size_t)gf * lam + (size_t)g * m;
             int32_t *top = st->top + gidx * k, *bot = st->bottom + gidx * k;
             float *gs = st->SG + gidx * D;
-            orc_guide_group(m, k, st->D, st->SE + first * D, st->Yc + (size_t)gf * st->C + g * m,
-                            st->F + (size_t)gf * D, st->c.boost, st->inv_k, top, bot,
-                            st->tie + gidx, gs);
+            if (none_yet) {
+                for (int i = 0; i < k; ++i) {
+                    top[i] = i;
+                    bot[i] = m - k + i;
+                }
+                st->tie[gidx] = 1;
+                memcpy(gs, st->F + (size_t)gf * D, D * sizeof(float));
+            } else {
+                orc_guide_group(m, k, st->D, st->SE + first * D,
+                                st->Yc + (size_t)gf * st->C + g * m, st->F + (size_t)gf * D,
+                                st->c.boost, st->inv_k, top, bot, st->tie + gidx, gs);
+            }
             for (int i = 0; i < k; ++i) {   /* report spark indices within the firework */
                 top[i] += g * m;
                 bot[i] += g * m;
@@ -554,18 +618,18 @@ int orc_guide(orc_state *st)
                 if (v < st->c.lb || v > st->c.ub) {
                     float u2 = orc_u01(orc_word(st->c.seed, ORC_TAG_GUIDE_MAP, (uint32_t)gidx, tn,
                                                 (uint32_t)d));
-                    gs[d] = uniform_in_box(&st->c, u2);
+                    gs[d] = map_coordinate(&st->c, u2, range_lo(st, gf), range_hi(st, gf), (int)d);
                 }
             }
         }
     }
-    st->phase = PH_NEED_GUIDE_FIT;
+    st->phase = lag ? PH_LAG_GUIDED : PH_NEED_GUIDE_FIT;
     return 0;
 }
 
 int orc_eval_guiding(orc_state *st)
 {
-    if (!want(st, PH_NEED_GUIDE_FIT, "eval_guiding")) return -1;
+    if (!want(st, st->c.lag_guiding ? PH_EXPL_DONE : PH_NEED_GUIDE_FIT, "eval_guiding")) return -1;
     if (!st->has_problem) { set_err("no problem to evaluate"); return -1; }
     int rows = st->BN * st->c.G;
     double *y = malloc(sizeof(double) * rows);
@@ -578,7 +642,7 @@ int orc_eval_guiding(orc_state *st)
 
 int orc_tell_guiding(orc_state *st, const float *y)
 {
-    if (!want(st, PH_NEED_GUIDE_FIT, "tell_guiding")) return -1;
+    if (!want(st, st->c.lag_guiding ? PH_EXPL_DONE : PH_NEED_GUIDE_FIT, "tell_guiding")) return -1;
     store_fitness(st, st->c.lambda, st->c.G, NULL, y);
     st->phase = PH_GUIDE_DONE;
     return 0;
@@ -653,9 +717,14 @@ int orc_run(orc_state *st, int n)
         if (orc_init_positions(st) || orc_eval_init(st)) return -1;
     }
     for (int i = 0; i < n && !st->done; ++i) {
-        if (orc_explode(st) || orc_eval_explosion(st) || orc_guide(st) || orc_eval_guiding(st) ||
-            orc_select(st))
+        if (st->c.lag_guiding) {
+            if (orc_guide(st) || orc_explode(st) || orc_eval_explosion(st) ||
+                orc_eval_guiding(st) || orc_select(st))
+                return -1;
+        } else if (orc_explode(st) || orc_eval_explosion(st) || orc_guide(st) ||
+                   orc_eval_guiding(st) || orc_select(st)) {
             return -1;
+        }
     }
     return 0;
 }

@@ -49,6 +49,16 @@ typedef struct {
     int loser_out;
     int use_target;
     float target_loss;
+    /* Variants of Alg. 1 (0 = the default readings):
+     *  lag_guiding: guiding sparks of generation t come from generation t-1's
+     *    explosion sparks and fitness (Alg. 1 taken literally: guide, explode,
+     *    then one evaluation of both), the first generation's guiding vectors
+     *    being zero;
+     *  map_range: an out-of-box coordinate is mapped uniformly into the
+     *    population's current range in that dimension (min..max over its
+     *    fireworks) instead of the whole box. */
+    int lag_guiding;
+    int map_range;
 } orc_config;
 
 typedef struct orc_state orc_state;
@@ -70,8 +80,11 @@ void orc_forward(const orc_problem *p, const float *w, int sample, double *out);
 
 /* Single-row helpers of the state path (all binary32). */
 void orc_init_row(const orc_config *c, int dim, uint32_t row, uint32_t t, int tag, float *x);
+/* lo, hi: the population's per-dimension range for map_range (NULL: the box). */
 void orc_explosion_row(const orc_config *c, int dim, const float *x, float amp,
-                       uint32_t row, uint32_t t, float *s);
+                       uint32_t row, uint32_t t, const float *lo, const float *hi, float *s);
+/* Per-dimension minimum and maximum over the n rows of F ([n][dim]). */
+void orc_population_range(int n, int dim, const float *F, float *lo, float *hi);
 
 /* One guiding group of m explosion sparks ([m][dim], fitness y[m]) around the
  * firework x: writes the top and bottom member lists (ascending index), the
@@ -85,7 +98,9 @@ void orc_destroy(orc_state *st);
 const char *orc_error(void);
 
 /* Phases of one generation.  Fitness comes from the problem (orc_eval_*) or from
- * the caller (orc_tell_*).  Return 0 on success, -1 on misuse. */
+ * the caller (orc_tell_*).  Return 0 on success, -1 on misuse.  Default order:
+ * explode, explosion fitness, guide, guiding fitness, select.  With lag_guiding:
+ * guide, explode, explosion fitness, guiding fitness, select. */
 int orc_init_positions(orc_state *st);
 int orc_eval_init(orc_state *st);
 int orc_tell_init(orc_state *st, const float *y);

@@ -41,7 +41,9 @@ def lib():
         L.orc_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
         L.orc_init_row.argtypes = [C.c_void_p, C.c_int, C.c_uint32, C.c_uint32, C.c_int, C.c_void_p]
         L.orc_explosion_row.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_float, C.c_uint32,
-                                        C.c_uint32, C.c_void_p]
+                                        C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_population_range.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_population_range.restype = None
         L.orc_guide_group.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_float, C.c_float, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_void_p]
@@ -71,7 +73,8 @@ class _Config(C.Structure):
                 ("sigma", C.c_float), ("boost", C.c_float), ("amp_up", C.c_float),
                 ("amp_down", C.c_float), ("amp_init", C.c_float), ("lb", C.c_float),
                 ("ub", C.c_float), ("T", C.c_int), ("seed", C.c_uint64),
-                ("loser_out", C.c_int), ("use_target", C.c_int), ("target_loss", C.c_float)]
+                ("loser_out", C.c_int), ("use_target", C.c_int), ("target_loss", C.c_float),
+                ("lag_guiding", C.c_int), ("map_range", C.c_int)]
 
 
 class _View(C.Structure):
@@ -157,7 +160,7 @@ def u01(r):
 
 DEFAULTS = dict(B=1, N=4, lam=32, G=4, sigma=0.2, boost=1.0, amp_up=1.2, amp_down=0.9,
                 amp_init=None, lb=-5.0, ub=5.0, T=100, seed=0, loser_out=1, use_target=0,
-                target_loss=0.0)
+                target_loss=0.0, lag_guiding=0, map_range=0)
 
 
 def make_config(**kw) -> _Config:
@@ -180,12 +183,24 @@ def init_row(cfg: _Config, dim, row, t, tag="init"):
     return out
 
 
-def explosion_row(cfg: _Config, x, amp, row, t):
+def explosion_row(cfg: _Config, x, amp, row, t, lo=None, hi=None):
+    """Explosion spark; lo/hi: the population range for range mapping (None: the box)."""
     x = np.ascontiguousarray(x, dtype=np.float32)
     out = np.zeros_like(x)
+    lo = None if lo is None else np.ascontiguousarray(lo, dtype=np.float32)
+    hi = None if hi is None else np.ascontiguousarray(hi, dtype=np.float32)
     lib().orc_explosion_row(C.byref(cfg), x.shape[0], _ptr(x), float(amp), int(row), int(t),
-                            _ptr(out))
+                            _ptr(lo), _ptr(hi), _ptr(out))
     return out
+
+
+def population_range(F):
+    """Per-dimension (min, max) over the rows of F, as the oracle computes them."""
+    F = np.ascontiguousarray(F, dtype=np.float32)
+    lo = np.zeros(F.shape[1], dtype=np.float32)
+    hi = np.zeros(F.shape[1], dtype=np.float32)
+    lib().orc_population_range(F.shape[0], F.shape[1], _ptr(F), _ptr(lo), _ptr(hi))
+    return lo, hi
 
 
 def guide_group(sparks, y, x, k, boost=1.0):
@@ -248,10 +263,16 @@ class Oracle:
         self.eval_init()
 
     def generation(self):
-        self.explode()
-        self.eval_explosion()
-        self.guide()
-        self.eval_guiding()
+        if self.cfg.lag_guiding:   # Alg. 1 literally: guide from the previous sparks first
+            self.guide()
+            self.explode()
+            self.eval_explosion()
+            self.eval_guiding()
+        else:
+            self.explode()
+            self.eval_explosion()
+            self.guide()
+            self.eval_guiding()
         self.select()
 
     def run(self, n):
