@@ -96,6 +96,17 @@ typedef struct {
  *   external_fitness  1: no fitness kernels, the caller tells every fitness
  *   use_target, target_loss  stop once a population's best <= target_loss
  *   seed      key of the counter-based generator
+ *   lag_guiding  1: Alg. 1's own order -- each generation first builds its
+ *             guiding sparks from the PREVIOUS generation's explosion sparks
+ *             and their fitness (around the current fireworks; zero guiding
+ *             vectors in the first generation), then explodes, then evaluates
+ *             the explosion and guiding sparks in one fitness launch.  0 (the
+ *             default) builds them from the current generation's sparks as
+ *             Sec. 3.2 describes.  Not available with external_fitness.
+ *   map_range 1: a coordinate that leaves [lb, ub] lands uniformly in the
+ *             population's current range min..max of that dimension over its
+ *             fireworks (the mapping rule of the FWA family, Sec. 2) instead
+ *             of uniformly in [lb, ub]
  */
 typedef struct {
     int n_populations;      /* B >= 1 */
@@ -116,6 +127,8 @@ typedef struct {
     int use_target;
     float target_loss;
     uint64_t seed;
+    int lag_guiding;
+    int map_range;
 } mgfwa_config;
 
 /* Layout of the device state inside the workspace, for inspection: byte
@@ -242,7 +255,8 @@ MGFWA_API const char *mgfwa_version(void);
 /* ------------------------------------------------------------------------ */
 
 /* The fitness launch shape of a context (the fitness step of Alg. 1 as a grouped
- * GEMM): which = 0 explosion sparks, 1 guiding sparks. */
+ * GEMM): which = 0 explosion sparks (with lag_guiding: the explosion and the
+ * guiding sparks, one launch), 1 guiding sparks (unused with lag_guiding). */
 typedef struct {
     int wide;               /* 1: the K-streamed wide-first-layer kernel (fixed tiles) */
     int rows;               /* sparks per launch */

@@ -54,7 +54,7 @@ int round_up(int v, int a) { return (v + a - 1) / a * a; }
 struct Layout {
     size_t F, SE, SG, A, Y, Yprev, fresh, Yc, top, bottom, tie, cstar, improved, reinit, src;
     size_t best_x, best_y, best_f, best_gen, best_upd, ctrl, partial, Xp, Xb, Ypad, Lpad;
-    size_t Wpack, Xw, total;
+    size_t Wpack, Xw, lo, hi, total;
     int partial_rows;
 };
 
@@ -67,6 +67,9 @@ struct Derived {
 };
 
 bool finite(float v) { return std::isfinite(v); }
+
+// rows per firework of the explosion-fitness launch
+int expl_rows(const Shape &s) { return s.lag ? s.C : s.lam; }
 
 mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
 {
@@ -82,6 +85,8 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
         c->amp_up <= 0.0f || c->amp_down <= 0.0f)
         return fail(MGFWA_EINVAL, "boost/amplitude parameters must be finite, factors > 0");
     if (c->max_generations < 1) return fail(MGFWA_EINVAL, "max_generations must be >= 1");
+    if (c->lag_guiding && c->external_fitness)
+        return fail(MGFWA_EUNSUPPORTED, "lag_guiding needs the built-in fitness");
     if (c->precision != MGFWA_FP32 && c->precision != MGFWA_BF16)
         return fail(MGFWA_EINVAL, "unknown precision %d", c->precision);
     if (p->n_layers < 1 || p->n_layers > MGFWA_MAX_LAYERS)
@@ -148,6 +153,8 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
     s.use_target = c->use_target ? 1 : 0;
     s.target = c->target_loss;
     s.key = make_uint2((uint32_t)c->seed, (uint32_t)(c->seed >> 32));
+    s.lag = c->lag_guiding ? 1 : 0;
+    s.map_range = c->map_range ? 1 : 0;
 
     net.loss = p->loss;
     net.bf16 = c->precision == MGFWA_BF16;
@@ -195,7 +202,9 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
     L.best_gen = take((size_t)s.B * 4);
     L.best_upd = take((size_t)s.B * 4);
     L.ctrl = take(CTRL_WORDS * 4);
-    L.partial_rows = (int)std::max<size_t>(BN * s.lam, 1024);
+    // the lag order evaluates the explosion and guiding sparks (adjacent
+    // buffers) in one launch
+    L.partial_rows = (int)std::max<size_t>(BN * (s.lag ? s.C : s.lam), 1024);
     L.partial = take((size_t)L.partial_rows * fit_max_bpr() * 4);
     const size_t nx = (size_t)net.S_pad * net.in_pad;
     L.Xp = take(net.bf16 ? 0 : nx * 4);
@@ -204,7 +213,11 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
     L.Lpad = take(net.loss == MGFWA_LOSS_CE ? (size_t)net.S_pad * 4 : 0);
     L.Wpack = take(net.wide ? (size_t)L.partial_rows * wide_row_bytes(net) : 0);
     L.Xw = take(net.wide ? (size_t)net.S_pad * wide_kp(net) * (net.bf16 ? 2 : 4) : 0);
+    L.lo = take(s.map_range ? (size_t)s.B * Dp * 4 : 0);
+    L.hi = take(s.map_range ? (size_t)s.B * Dp * 4 : 0);
     L.total = off;
+    if (s.lag && L.SG != L.SE + BN * s.lam * Dp * 4)
+        return fail(MGFWA_EINVAL, "internal: guiding sparks must follow the explosion sparks");
     return MGFWA_OK;
 }
 
@@ -259,6 +272,20 @@ mgfwa_status check(mgfwa_ctx *c, hipError_t e, const char *what)
 
 const OutMap kFlat = {1, 1, 0};
 
+// The explosion-fitness launch: BN*lambda explosion sparks into the first
+// lambda candidate slots or, in the lag order, those followed by the BN*G
+// guiding sparks into the last G slots.
+OutMap expl_map(const Shape &s)
+{
+    OutMap m{s.lam, s.C, 0};
+    if (s.lag) {
+        m.split = s.BN * s.lam;
+        m.per2 = s.G;
+        m.offset2 = s.lam;
+    }
+    return m;
+}
+
 mgfwa_status fit_rows(mgfwa_ctx *c, const FitPlan &plan, const float *W, size_t ld, int rows,
                       OutMap map, float *out, hipStream_t st, hipEvent_t mid = nullptr,
                       hipEvent_t pre = nullptr)
@@ -285,22 +312,37 @@ hipEvent_t take_event(mgfwa_ctx *c)
 // Enqueue one generation on `st`; ev (7 events) brackets the five phases when
 // non-null, ev[6] marks the end of the explosion-fitness GEMM kernel and ev[7]
 // its start (after the wide kernel's packing; ev[1] serves otherwise).
+//
+// The lag order (Alg. 1 as printed) builds the guiding sparks from the sparks
+// and fitness the previous generation left in SE and Yc before exploding, then
+// evaluates both kinds of spark in one launch; its explosion phase also holds
+// the rank and guide kernels and its guiding-fitness phase is empty.
 mgfwa_status enqueue_generation(mgfwa_ctx *c, hipStream_t st, hipEvent_t *ev)
 {
     const Shape &s = c->s;
     if (ev) STEP(hipEventRecord(ev[0], st), "event");
+    if (s.map_range) STEP(launch_pop_range(s, c->d, st), "pop_range");
+    if (s.lag) {
+        STEP(launch_rank(s, c->d, st), "rank");
+        STEP(launch_guide(s, c->d, st), "guide");
+    }
     STEP(launch_explode(s, c->d, st), "explode");
     if (ev) STEP(hipEventRecord(ev[1], st), "event");
-    mgfwa_status r = fit_rows(c, c->plan_expl, c->d.SE, s.Dp, s.BN * s.lam,
-                              OutMap{s.lam, s.C, 0}, c->d.Yc, st, ev ? ev[6] : nullptr,
+    mgfwa_status r = fit_rows(c, c->plan_expl, c->d.SE, s.Dp, s.BN * expl_rows(s), expl_map(s),
+                              c->d.Yc, st, ev ? ev[6] : nullptr,
                               ev && c->net.wide ? ev[7] : nullptr);
     if (r) return r;
     if (ev) STEP(hipEventRecord(ev[2], st), "event");
-    STEP(launch_rank(s, c->d, st), "rank");
-    STEP(launch_guide(s, c->d, st), "guide");
+    if (!s.lag) {
+        STEP(launch_rank(s, c->d, st), "rank");
+        STEP(launch_guide(s, c->d, st), "guide");
+    }
     if (ev) STEP(hipEventRecord(ev[3], st), "event");
-    r = fit_rows(c, c->plan_guide, c->d.SG, s.Dp, s.BN * s.G, OutMap{s.G, s.C, s.lam}, c->d.Yc, st);
-    if (r) return r;
+    if (!s.lag) {
+        r = fit_rows(c, c->plan_guide, c->d.SG, s.Dp, s.BN * s.G, OutMap{s.G, s.C, s.lam},
+                     c->d.Yc, st);
+        if (r) return r;
+    }
     if (ev) STEP(hipEventRecord(ev[4], st), "event");
     STEP(launch_select(s, c->d, st), "select");
     STEP(launch_apply(s, c->d, st), "apply");
@@ -371,7 +413,7 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
     const bool has_data = !config->external_fitness || problem->x_dev;
     FitPlan pi{}, pe{}, pg{}, pv{};
     if (has_data && !dv.net.wide) {
-        if (!fit_select(dv.net, dv.s.BN, &pi) || !fit_select(dv.net, dv.s.BN * dv.s.lam, &pe) ||
+        if (!fit_select(dv.net, dv.s.BN, &pi) || !fit_select(dv.net, dv.s.BN * expl_rows(dv.s), &pe) ||
             !fit_select(dv.net, dv.s.BN * dv.s.G, &pg) ||
             !fit_select(dv.net, dv.lay.partial_rows, &pv))
             return fail(MGFWA_EUNSUPPORTED, "no compiled fitness kernel covers this MLP shape");
@@ -389,7 +431,7 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
             return fail(MGFWA_EUNSUPPORTED, "device LDS too small for the wide fitness kernel");
         HIP_TRY(wide_prepare(dv.net));
     } else if (has_data) {
-        if (!fit_select(dv.net, dv.s.BN, &pi) || !fit_select(dv.net, dv.s.BN * dv.s.lam, &pe) ||
+        if (!fit_select(dv.net, dv.s.BN, &pi) || !fit_select(dv.net, dv.s.BN * expl_rows(dv.s), &pe) ||
             !fit_select(dv.net, dv.s.BN * dv.s.G, &pg) ||
             !fit_select(dv.net, dv.lay.partial_rows, &pv))
             return fail(MGFWA_EUNSUPPORTED, "no compiled fitness kernel covers this MLP shape");
@@ -443,6 +485,8 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
     d.Lpad = c->net.loss == MGFWA_LOSS_CE ? at<int32_t>(b, L.Lpad) : nullptr;
     d.Wpack = c->net.wide ? at<char>(b, L.Wpack) : nullptr;
     d.Xw = c->net.wide ? at<char>(b, L.Xw) : nullptr;
+    d.lo = c->s.map_range ? at<float>(b, L.lo) : nullptr;
+    d.hi = c->s.map_range ? at<float>(b, L.hi) : nullptr;
 
     auto bail = [&](mgfwa_status st) {
         mgfwa_destroy(c);
@@ -554,6 +598,7 @@ mgfwa_status mgfwa_ask(mgfwa_ctx *c, const float **sparks, int *rows, int *ld)
         c->phase = PH_INIT_TELL;
         break;
     case PH_READY:
+        if (s.map_range) STEP(launch_pop_range(s, c->d, c->stream), "pop_range");
         STEP(launch_explode(s, c->d, c->stream), "explode");
         *sparks = c->d.SE;
         if (rows) *rows = s.BN * s.lam;
@@ -879,7 +924,7 @@ mgfwa_status mgfwa_autotune(mgfwa_ctx *c, int reps)
         return fail(MGFWA_ESTATE, "autotune before the first generation");
     if (c->net.wide) return MGFWA_OK;   // one fixed tile shape
     const Shape &s = c->s;
-    mgfwa_status r = tune_plan(c, s.BN * s.lam, c->d.SE, OutMap{s.lam, s.C, 0}, reps, &c->plan_expl);
+    mgfwa_status r = tune_plan(c, s.BN * expl_rows(s), c->d.SE, expl_map(s), reps, &c->plan_expl);
     if (r) return r;
     return tune_plan(c, s.BN * s.G, c->d.SG, OutMap{s.G, s.C, s.lam}, reps, &c->plan_guide);
 }
@@ -891,7 +936,7 @@ mgfwa_status mgfwa_fit_plan(const mgfwa_ctx *c, int which, mgfwa_plan_info *info
     const FitPlan &p = which == 0 ? c->plan_expl : c->plan_guide;
     std::memset(info, 0, sizeof *info);
     info->wide = c->net.wide ? 1 : 0;
-    info->rows = which == 0 ? c->s.BN * c->s.lam : c->s.BN * c->s.G;
+    info->rows = which == 0 ? c->s.BN * expl_rows(c->s) : c->s.BN * c->s.G;
     if (!c->net.wide) {
         info->wavefronts = p.nw;
         info->slabs = p.P;

@@ -57,6 +57,19 @@ __device__ __forceinline__ float box_uniform(const Box &b, float u)
     return v > b.ub ? b.ub : v;
 }
 
+// Random mapping of an out-of-box coordinate from its draw u: uniform in the box,
+// or (lo non-null) uniform in the population's range lo..hi of that dimension,
+// fma(u, hi - lo, lo), clamped into the box.
+__device__ __forceinline__ float map_uniform(const Box &b, float u, const float *lo,
+                                             const float *hi, int d)
+{
+    if (!lo) return box_uniform(b, u);
+    const float width = hi[d] - lo[d];
+    float v = __builtin_fmaf(u, width, lo[d]);
+    v = v < b.lb ? b.lb : v;
+    return v > b.ub ? b.ub : v;
+}
+
 __device__ __forceinline__ bool outside(const Box &b, float v)
 {
     return v < b.lb || v > b.ub;

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) void k_wide_finalize(const float *__restrict__
     if (r >= rows) return;
     float t = 0.0f;
     for (int c = 0; c < ntn; ++c) t += partial[(size_t)r * ntn + c];
-    out[(size_t)(r / map.per) * map.stride + map.offset + r % map.per] = canon_fitness(t * inv_norm);
+    out[map.index(r)] = canon_fitness(t * inv_norm);
 }
 
 // One instance per (precision, hidden activation): a run-time activation

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void k_fit_finalize(const float *__restrict__ 
     if (r >= rows) return;
     float t = 0.0f;
     for (int c = 0; c < bpr; ++c) t += partial[(size_t)r * bpr + c];
-    out[(size_t)(r / map.per) * map.stride + map.offset + r % map.per] = canon_fitness(t * inv_norm);
+    out[map.index(r)] = canon_fitness(t * inv_norm);
 }
 
 // Pack the problem data: X zero-padded to [S_pad][in_pad] (FP32 or bf16 RNE),

@@ -22,9 +22,20 @@ __global__ __launch_bounds__(TPB) void k_rank(const float *__restrict__ Yc, int 
                                               int m, int k, int32_t *__restrict__ top,
                                               int32_t *__restrict__ bottom,
                                               int32_t *__restrict__ tie,
-                                              const int32_t *__restrict__ ctrl)
+                                              const int32_t *__restrict__ ctrl, int lag)
 {
     if (ctrl[CTRL_DONE]) return;
+    if (lag && ctrl[CTRL_GEN] == 0) {
+        // lagged guiding before any explosion: every guiding vector is zero
+        const int gf = blockIdx.x;
+        for (int i = threadIdx.x; i < G * k; i += blockDim.x) {
+            const int g = i / k, j = i % k;
+            top[((size_t)gf * G + g) * k + j] = g * m + j;
+            bottom[((size_t)gf * G + g) * k + j] = g * m + m - k + j;
+        }
+        for (int g = threadIdx.x; g < G; g += blockDim.x) tie[(size_t)gf * G + g] = 1;
+        return;
+    }
     extern __shared__ uint32_t sh[];
     uint32_t *key = sh;               // [lam]
     int32_t *rank = (int32_t *)(sh + lam);  // [lam]
@@ -73,7 +84,9 @@ __global__ __launch_bounds__(TPB) void k_guide(const float *__restrict__ F,
                                                const int32_t *__restrict__ tie, int G, int lam,
                                                int k, float inv_k, float boost, int groups, int D,
                                                int Dp, uint2 key, Box box,
-                                               const int32_t *__restrict__ ctrl)
+                                               const int32_t *__restrict__ ctrl, int N,
+                                               const float *__restrict__ lo,
+                                               const float *__restrict__ hi)
 {
     if (ctrl[CTRL_DONE]) return;
     const uint32_t tn = (uint32_t)ctrl[CTRL_GEN] + 1u;
@@ -108,9 +121,11 @@ __global__ __launch_bounds__(TPB) void k_guide(const float *__restrict__ F,
         if (any_out) {
             const uint4 r2 = draw4(key, (uint32_t)chunk, (uint32_t)gi, tn, TAG_GUIDE_MAP);
             const uint32_t w2[4] = {r2.x, r2.y, r2.z, r2.w};
+            const size_t pb = (size_t)(gf / N) * Dp;
+            const float *plo = lo ? lo + pb : nullptr, *phi = hi ? hi + pb : nullptr;
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                if (outside(box, v[e])) v[e] = box_uniform(box, u01(w2[e]));
+                if (outside(box, v[e])) v[e] = map_uniform(box, u01(w2[e]), plo, phi, 4 * chunk + e);
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e)
@@ -125,7 +140,7 @@ hipError_t launch_rank(const Shape &s, const DevState &d, hipStream_t st)
 {
     const size_t shmem = (size_t)s.lam * 8;
     hipLaunchKernelGGL(k_rank, dim3(s.BN), dim3(TPB), shmem, st, d.Yc, s.C, s.lam, s.G, s.m, s.k,
-                       d.top, d.bottom, d.tie, d.ctrl);
+                       d.top, d.bottom, d.tie, d.ctrl, s.lag);
     return hipGetLastError();
 }
 
@@ -135,7 +150,8 @@ hipError_t launch_guide(const Shape &s, const DevState &d, hipStream_t st)
     const int nchunk = s.Dp >> 2;
     dim3 grid((nchunk + TPB - 1) / TPB, groups < MAX_GRID_Y ? groups : MAX_GRID_Y);
     hipLaunchKernelGGL(k_guide, grid, dim3(TPB), 0, st, d.F, d.SE, d.SG, d.top, d.bottom, d.tie,
-                       s.G, s.lam, s.k, s.inv_k, s.boost, groups, s.D, s.Dp, s.key, s.box, d.ctrl);
+                       s.G, s.lam, s.k, s.inv_k, s.boost, groups, s.D, s.Dp, s.key, s.box, d.ctrl,
+                       s.N, s.map_range ? d.lo : nullptr, s.map_range ? d.hi : nullptr);
     return hipGetLastError();
 }
 

@@ -17,6 +17,14 @@ constexpr int S_ALIGN = 256;   // sample padding of the packed problem data
 // Where a row's result goes: out[(r / per) * stride + offset + r % per].
 struct OutMap {
     int per, stride, offset;
+    // rows from `split` on form a second segment: (r' / per2) * stride + offset2 + r' % per2
+    int split = 0x7fffffff, per2 = 1, offset2 = 0;
+    __host__ __device__ size_t index(int r) const
+    {
+        if (r < split) return (size_t)(r / per) * stride + offset + r % per;
+        const int q = r - split;
+        return (size_t)(q / per2) * stride + offset2 + q % per2;
+    }
 };
 
 // Device pointers carved out of the caller's workspace.
@@ -30,6 +38,7 @@ struct DevState {
     int32_t *Lpad;     // [S_pad] CE labels (-1 padded)
     char *Wpack;       // packed spark rows for the wide-first-layer kernel
     char *Xw;          // [S_pad][Kp] samples with a ones column (wide kernel)
+    float *lo, *hi;    // [B][Dp] population ranges (range mapping)
 };
 
 // Population shape and algorithm constants as the kernels need them.
@@ -41,6 +50,8 @@ struct Shape {
     float target;
     Box box;
     uint2 key;
+    int lag;                           // guiding from the previous generation's sparks
+    int map_range;                     // random mapping into the population's range
 };
 
 // MLP problem as the fitness kernels need it.
@@ -75,6 +86,7 @@ struct FitPlan {
 
 // ---- spark.hip
 hipError_t launch_init_positions(const Shape &s, const DevState &d, hipStream_t st);
+hipError_t launch_pop_range(const Shape &s, const DevState &d, hipStream_t st);
 hipError_t launch_explode(const Shape &s, const DevState &d, hipStream_t st);
 
 // ---- guide.hip

@@ -220,7 +220,7 @@ __global__ __launch_bounds__(TPB) void k_store_fitness(const float *__restrict__
     if (ctrl && ctrl[CTRL_DONE]) return;
     const int r = blockIdx.x * TPB + threadIdx.x;
     if (r >= rows) return;
-    out[(size_t)(r / map.per) * map.stride + map.offset + r % map.per] = canon_fitness(in[r]);
+    out[map.index(r)] = canon_fitness(in[r]);
 }
 
 }  // namespace

@@ -34,6 +34,29 @@ __global__ __launch_bounds__(TPB) void k_init_positions(float *__restrict__ F,
     }
 }
 
+// Per-dimension minimum and maximum over the N fireworks of every population
+// (the range the range-mapping variant draws into), fireworks in index order.
+__global__ __launch_bounds__(TPB) void k_pop_range(const float *__restrict__ F, int N, int B,
+                                                   int Dp, float *__restrict__ lo,
+                                                   float *__restrict__ hi,
+                                                   const int32_t *__restrict__ ctrl)
+{
+    if (ctrl[CTRL_DONE]) return;
+    const int d = blockIdx.x * TPB + threadIdx.x;
+    if (d >= Dp) return;
+    for (int b = blockIdx.y; b < B; b += gridDim.y) {
+        const float *f0 = F + (size_t)b * N * Dp;
+        float a = f0[d], c = f0[d];
+        for (int f = 1; f < N; ++f) {
+            const float v = f0[(size_t)f * Dp + d];
+            if (v < a) a = v;
+            if (v > c) c = v;
+        }
+        lo[(size_t)b * Dp + d] = a;
+        hi[(size_t)b * Dp + d] = c;
+    }
+}
+
 // Explosion spark j of firework f (row = f*lambda + j) for generation t+1:
 // s = fma(A_f, 2u - 1, x_f); out-of-box coordinates take a uniform draw from
 // the mapping stream of the same (chunk, row, generation).
@@ -41,7 +64,9 @@ __global__ __launch_bounds__(TPB) void k_explode(const float *__restrict__ F,
                                                  const float *__restrict__ A,
                                                  float *__restrict__ SE, int lam, int rows, int D,
                                                  int Dp, uint2 key, Box box,
-                                                 const int32_t *__restrict__ ctrl)
+                                                 const int32_t *__restrict__ ctrl, int N,
+                                                 const float *__restrict__ lo,
+                                                 const float *__restrict__ hi)
 {
     if (ctrl[CTRL_DONE]) return;
     const uint32_t tn = (uint32_t)ctrl[CTRL_GEN] + 1u;
@@ -65,9 +90,11 @@ __global__ __launch_bounds__(TPB) void k_explode(const float *__restrict__ F,
         if (any_out) {
             const uint4 r2 = draw4(key, (uint32_t)chunk, (uint32_t)row, tn, TAG_EXPL_MAP);
             const uint32_t w2[4] = {r2.x, r2.y, r2.z, r2.w};
+            const size_t pb = (size_t)(gf / N) * Dp;
+            const float *plo = lo ? lo + pb : nullptr, *phi = hi ? hi + pb : nullptr;
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                if (outside(box, s[e])) s[e] = box_uniform(box, u01(w2[e]));
+                if (outside(box, s[e])) s[e] = map_uniform(box, u01(w2[e]), plo, phi, 4 * chunk + e);
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e)
@@ -91,11 +118,20 @@ hipError_t launch_init_positions(const Shape &s, const DevState &d, hipStream_t 
     return hipGetLastError();
 }
 
+hipError_t launch_pop_range(const Shape &s, const DevState &d, hipStream_t st)
+{
+    const dim3 grid((s.Dp + TPB - 1) / TPB, s.B < MAX_GRID_Y ? s.B : MAX_GRID_Y);
+    hipLaunchKernelGGL(k_pop_range, grid, dim3(TPB), 0, st, d.F, s.N,
+                       s.B, s.Dp, d.lo, d.hi, d.ctrl);
+    return hipGetLastError();
+}
+
 hipError_t launch_explode(const Shape &s, const DevState &d, hipStream_t st)
 {
     const int rows = s.BN * s.lam;
     hipLaunchKernelGGL(k_explode, row_grid(s.Dp, rows), dim3(TPB), 0, st, d.F, d.A, d.SE, s.lam,
-                       rows, s.D, s.Dp, s.key, s.box, d.ctrl);
+                       rows, s.D, s.Dp, s.key, s.box, d.ctrl, s.N, s.map_range ? d.lo : nullptr,
+                       s.map_range ? d.hi : nullptr);
     return hipGetLastError();
 }
 

@@ -39,7 +39,8 @@ class mgfwa_config(C.Structure):
                 ("amp_up", C.c_float), ("amp_down", C.c_float), ("amp_init", C.c_float),
                 ("lb", C.c_float), ("ub", C.c_float), ("max_generations", C.c_int),
                 ("loser_out", C.c_int), ("precision", C.c_int), ("external_fitness", C.c_int),
-                ("use_target", C.c_int), ("target_loss", C.c_float), ("seed", C.c_uint64)]
+                ("use_target", C.c_int), ("target_loss", C.c_float), ("seed", C.c_uint64),
+                ("lag_guiding", C.c_int), ("map_range", C.c_int)]
 
 
 _STATE_ARRAYS = ("F", "A", "Y", "Yprev", "fresh", "SE", "SG", "Yc", "top", "bottom", "tie",
@@ -153,7 +154,7 @@ def _check(status: int) -> None:
 def make_config(n_fireworks=4, n_sparks=32, n_guiding=4, n_populations=1, sigma=0.2, boost=1.0,
                 amp_up=1.2, amp_down=0.9, amp_init=0.0, lb=-5.0, ub=5.0, max_generations=100,
                 loser_out=True, precision="fp32", external_fitness=False, target_loss=None,
-                seed=0) -> mgfwa_config:
+                seed=0, lag_guiding=False, map_range=False) -> mgfwa_config:
     c = mgfwa_config()
     c.n_populations, c.n_fireworks, c.n_sparks, c.n_guiding = (
         n_populations, n_fireworks, n_sparks, n_guiding)
@@ -165,6 +166,8 @@ def make_config(n_fireworks=4, n_sparks=32, n_guiding=4, n_populations=1, sigma=
     c.use_target = int(target_loss is not None)
     c.target_loss = 0.0 if target_loss is None else float(target_loss)
     c.seed = int(seed)
+    c.lag_guiding = int(bool(lag_guiding))
+    c.map_range = int(bool(map_range))
     return c
 
 

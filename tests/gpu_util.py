@@ -24,7 +24,8 @@ def require_gpu():
 
 def make_pair(wl, n_populations=1, n_fireworks=None, n_sparks=None, n_guiding=None, sigma=0.2,
               boost=1.0, amp_up=1.2, amp_down=0.9, T=None, seed=0, loser_out=True, target=None,
-              external=False, precision="fp32", with_oracle=True):
+              external=False, precision="fp32", with_oracle=True, lag_guiding=False,
+              map_range=False):
     torch, M = require_gpu()
     N = n_fireworks or wl.n_fireworks
     lam = n_sparks or wl.n_sparks
@@ -36,12 +37,13 @@ def make_pair(wl, n_populations=1, n_fireworks=None, n_sparks=None, n_guiding=No
         o = O.Oracle(p, B=n_populations, N=N, lam=lam, G=G, sigma=sigma, boost=boost,
                      amp_up=amp_up, amp_down=amp_down, lb=wl.lb, ub=wl.ub, T=T, seed=seed,
                      loser_out=int(loser_out), use_target=int(target is not None),
-                     target_loss=0.0 if target is None else target)
+                     target_loss=0.0 if target is None else target,
+                     lag_guiding=int(lag_guiding), map_range=int(map_range))
     g = M.MGFWA(wl.widths, wl.acts, wl.loss, wl.x, wl.y, wl.labels, n_populations=n_populations,
                 n_fireworks=N, n_sparks=lam, n_guiding=G, sigma=sigma, boost=boost,
                 amp_up=amp_up, amp_down=amp_down, lb=wl.lb, ub=wl.ub, max_generations=T,
                 loser_out=loser_out, precision=precision, external_fitness=external,
-                target_loss=target, seed=seed)
+                target_loss=target, seed=seed, lag_guiding=lag_guiding, map_range=map_range)
     return o, g
 
 
@@ -70,9 +72,10 @@ def assert_bits(a, b, what):
 def assert_fitness_close(got, want64, what, rtol=FIT_RTOL, atol=FIT_ATOL):
     got = np.asarray(got, dtype=np.float64)
     want = np.asarray(want64, dtype=np.float64)
-    err = np.abs(got - want)
+    with np.errstate(invalid="ignore"):         # inf - inf where both are infinite
+        err = np.abs(got - want)
     bound = rtol * np.abs(want) + atol
-    bad = ~(err <= bound)
+    bad = ~(err <= bound) & ~(got == want)      # equal infinities (reinitialised) agree
     if np.any(bad):
         i = np.argwhere(bad)[:5]
         raise AssertionError(f"{what}: {int(bad.sum())}/{bad.size} outside tolerance; "
@@ -98,9 +101,12 @@ def compare_state(ov, gs, D, B, what, with_sparks=True):
         assert_bits(gs["SG"][:, :D], ov["SG"], f"{what} SG")
 
 
-def near_tie_present(prev, cur, lam, G, m, k, rel=2 * FIT_RTOL):
+def near_tie_present(prev, cur, lam, G, m, k, rel=2 * FIT_RTOL, guide_yc=None, check_guide=True):
     """True when some decision of the oracle's last generation compared two
-    fitness values within `rel` of each other (either branch is then valid)."""
+    fitness values within `rel` of each other (either branch is then valid).
+    guide_yc: the candidate fitness the guiding cut ranked (the previous
+    generation's in the lag order; the current one by default); check_guide
+    False when no guiding cut was made (the lag order's first generation)."""
     def close(a, b):
         a, b = float(a), float(b)
         if not (np.isfinite(a) and np.isfinite(b)):
@@ -108,12 +114,13 @@ def near_tie_present(prev, cur, lam, G, m, k, rel=2 * FIT_RTOL):
         return abs(a - b) <= rel * max(abs(a), abs(b)) + 1e-30
 
     Yc = cur["Yc"]
+    Yg = Yc if guide_yc is None else guide_yc
     BN = Yc.shape[0]
     for gf in range(BN):
         row = Yc[gf]
         # guiding cut: ranks k-1 / k and m-k-1 / m-k inside each group
-        for g in range(G):
-            grp = np.sort(row[g * m:(g + 1) * m].astype(np.float64))
+        for g in range(G if check_guide else 0):
+            grp = np.sort(Yg[gf, g * m:(g + 1) * m].astype(np.float64))
             if close(grp[k - 1], grp[k]) or close(grp[m - k - 1], grp[m - k]):
                 return True
         srt = np.sort(row.astype(np.float64))

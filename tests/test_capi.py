@@ -88,3 +88,20 @@ def test_init_rejects_before_touching_the_device():
     with pytest.raises(M.MgfwaError) as e:
         M.mgfwa_init(c, wide, 4096, 1 << 30, 0)
     assert e.value.status == M.EUNSUPPORTED
+
+
+def test_variant_configs():
+    p = _cfg2_problem()
+    base = dict(n_fireworks=8, n_sparks=256)
+    nb = M.mgfwa_workspace_bytes(M.make_config(**base), p)
+    Dp = (26122 + 63) // 64 * 64
+    # the range variant keeps a min and a max row per population
+    nr = M.mgfwa_workspace_bytes(M.make_config(map_range=True, n_populations=1, **base), p)
+    assert nr >= nb + 2 * Dp * 4
+    assert M.mgfwa_workspace_bytes(M.make_config(lag_guiding=True, **base), p) >= nb
+    with pytest.raises(M.MgfwaError) as e:
+        M.mgfwa_init(M.make_config(lag_guiding=True, external_fitness=True, **base), p, 4096,
+                     1 << 30, 0)
+    assert e.value.status == M.EUNSUPPORTED and "lag_guiding" in str(e.value)
+    assert M.mgfwa_workspace_bytes(M.make_config(map_range=True, external_fitness=True, **base),
+                                   p) > 0
