@@ -92,16 +92,23 @@ static float uniform_in_box(const orc_config *c, float u)
 }
 
 /* ------------------------------------------------------------------------- */
-/* Fitness: loss of the MLP whose weights are the spark (binary64).           */
+/* Fitness (binary64): the loss of the MLP whose weights are the spark, or,   */
+/* for the paper's testbed (Sec. 4.1, eq. (1)), the scalar output of a fixed  */
+/* MLP whose input is the spark.                                              */
 /* Weight layout: for every layer l in order, W_l (out x in, row-major) then  */
 /* b_l (out), i.e. the nn.Linear convention.                                  */
 /* ------------------------------------------------------------------------- */
-int orc_dim(const orc_problem *p)
+int orc_n_params(const orc_problem *p)
 {
     int D = 0;
     for (int l = 0; l < p->n_layers; ++l)
         D += p->widths[l] * p->widths[l + 1] + p->widths[l + 1];
     return D;
+}
+
+int orc_dim(const orc_problem *p)
+{
+    return p->kind == ORC_PROBLEM_INPUT ? p->widths[0] : orc_n_params(p);
 }
 
 static double act_apply(int act, double z)
@@ -122,12 +129,13 @@ static int max_width(const orc_problem *p)
     return w;
 }
 
-/* Forward pass of one sample into out[widths[L]]; a and b are scratch rows. */
-static void forward_one(const orc_problem *p, const float *w, int s, double *a, double *b,
-                        double *out)
+/* Forward pass of the network with parameters w at input `in` into
+ * out[widths[L]]; a and b are scratch rows. */
+static void forward_vec(const orc_problem *p, const float *w, const float *in, double *a,
+                        double *b, double *out)
 {
     const int in0 = p->widths[0];
-    for (int k = 0; k < in0; ++k) a[k] = (double)p->x[(size_t)s * in0 + k];
+    for (int k = 0; k < in0; ++k) a[k] = (double)in[k];
     size_t off = 0;
     for (int l = 0; l < p->n_layers; ++l) {
         const int fi = p->widths[l], fo = p->widths[l + 1];
@@ -143,6 +151,26 @@ static void forward_one(const orc_problem *p, const float *w, int s, double *a, 
         double *tmp = a; a = b; b = tmp;
     }
     for (int o = 0; o < p->widths[p->n_layers]; ++o) out[o] = a[o];
+}
+
+/* Forward pass of sample s of the problem's data. */
+static void forward_one(const orc_problem *p, const float *w, int s, double *a, double *b,
+                        double *out)
+{
+    forward_vec(p, w, p->x + (size_t)s * p->widths[0], a, b, out);
+}
+
+double orc_net_output(const orc_problem *p, const float *x)
+{
+    const int mw = max_width(p);
+    double *a = malloc(sizeof(double) * mw), *b = malloc(sizeof(double) * mw);
+    double *z = malloc(sizeof(double) * mw);
+    forward_vec(p, p->net, x, a, b, z);
+    const double y = z[0];
+    free(a);
+    free(b);
+    free(z);
+    return y;
 }
 
 void orc_forward(const orc_problem *p, const float *w, int sample, double *out)
@@ -219,6 +247,11 @@ double orc_loss(const orc_problem *p, const float *w, double *per_sample)
 
 void orc_loss_rows(const orc_problem *p, const float *w, int rows, int ld, double *out)
 {
+    if (p->kind == ORC_PROBLEM_INPUT) {
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int r = 0; r < rows; ++r) out[r] = orc_net_output(p, w + (size_t)r * ld);
+        return;
+    }
     int nthreads = 1;
 #ifdef _OPENMP
     nthreads = omp_get_max_threads();
@@ -344,7 +377,12 @@ orc_state *orc_create(const orc_config *c, const orc_problem *p)
     orc_state *st = calloc(1, sizeof *st);
     st->c = *c;
     st->p = *p;
-    st->has_problem = (p->x != NULL);
+    st->has_problem = p->kind == ORC_PROBLEM_INPUT ? p->net != NULL : p->x != NULL;
+    if (p->kind == ORC_PROBLEM_INPUT && p->widths[p->n_layers] != 1) {
+        set_err("the fixed network of an input problem has one output");
+        free(st);
+        return NULL;
+    }
     st->D = orc_dim(p);
     st->m = m;
     int k = (int)floor((double)c->sigma * (double)m);

@@ -3,7 +3,8 @@
  *
  * A plain, slow, single-file CPU implementation of one MGFWA run (multi-guiding
  * spark fireworks algorithm, GPU-MGFWA paper Alg. 1) applied to MLP weight
- * optimisation.  It exists to check the HIP library; only the test-suite, the
+ * optimisation, or to the paper's own testbed (Sec. 4.1, eq. (1)): the input
+ * of a fixed MLP that minimises the network's scalar output.  It exists to check the HIP library; only the test-suite, the
  * smoke check and the benchmark's CPU-baseline leg may load it.  It shares no
  * code, header, table or constant with the HIP library.
  *
@@ -22,10 +23,13 @@
 extern "C" {
 #endif
 
-#define ORC_MAX_LAYERS 8
+#define ORC_MAX_LAYERS 12
 
 enum { ORC_ACT_IDENTITY = 0, ORC_ACT_RELU = 1, ORC_ACT_TANH = 2, ORC_ACT_GELU = 3 };
 enum { ORC_LOSS_MSE = 0, ORC_LOSS_CE = 1 };
+/* What a spark is: the MLP's parameters (fitness = loss over the samples), or
+ * the input of a fixed MLP (Sec. 4.1, eq. (1); fitness = its output). */
+enum { ORC_PROBLEM_TRAIN = 0, ORC_PROBLEM_INPUT = 1 };
 /* Philox counter word 3: which random stream a draw belongs to. */
 enum { ORC_TAG_INIT = 0, ORC_TAG_EXPL = 1, ORC_TAG_EXPL_MAP = 2, ORC_TAG_GUIDE_MAP = 3,
        ORC_TAG_REINIT = 4 };
@@ -39,6 +43,9 @@ typedef struct {
     const float *x;          /* [S][widths[0]] */
     const float *y;          /* MSE: [S][widths[n_layers]] */
     const int32_t *labels;   /* CE: [S] */
+    int kind;                /* ORC_PROBLEM_*; INPUT ignores loss and the samples */
+    const float *net;        /* INPUT: the fixed parameters, in the weight layout below,
+                                with widths[n_layers] == 1 */
 } orc_problem;
 
 typedef struct {
@@ -70,10 +77,16 @@ uint32_t orc_word(uint64_t seed, int tag, uint32_t row, uint32_t t, uint32_t d);
 /* Top 24 bits of r scaled by 2^-24: a float in [0, 1 - 2^-24]. */
 float orc_u01(uint32_t r);
 
+/* Spark dimension: the parameter count (TRAIN) or the input width (INPUT). */
 int orc_dim(const orc_problem *p);
-/* Fitness of one weight vector (binary64).  per_sample may be NULL. */
+/* Parameter count of the problem's network, sum of fi*fo + fo over layers. */
+int orc_n_params(const orc_problem *p);
+/* Fitness of one weight vector (binary64, TRAIN).  per_sample may be NULL. */
 double orc_loss(const orc_problem *p, const float *w, double *per_sample);
-/* Fitness of rows weight vectors with leading dimension ld (binary64 results). */
+/* Output of the fixed network at input x (binary64, INPUT, eq. (1)). */
+double orc_net_output(const orc_problem *p, const float *x);
+/* Fitness of rows sparks with leading dimension ld (binary64 results): the loss
+ * (TRAIN) or the fixed network's output (INPUT). */
 void orc_loss_rows(const orc_problem *p, const float *w, int rows, int ld, double *out);
 /* Forward pass of one sample: writes the widths[n_layers] outputs (binary64). */
 void orc_forward(const orc_problem *p, const float *w, int sample, double *out);

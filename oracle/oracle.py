@@ -17,7 +17,8 @@ from . import build as _build
 ACT = {"identity": 0, "relu": 1, "tanh": 2, "gelu": 3}
 LOSS = {"mse": 0, "ce": 1}
 TAG = {"init": 0, "expl": 1, "expl_map": 2, "guide_map": 3, "reinit": 4}
-MAX_LAYERS = 8
+MAX_LAYERS = 12
+KIND = {"train": 0, "input": 1}
 
 _lib = None
 
@@ -35,6 +36,9 @@ def lib():
         L.orc_u01.argtypes = [C.c_uint32]
         L.orc_u01.restype = C.c_float
         L.orc_dim.argtypes = [C.c_void_p]
+        L.orc_n_params.argtypes = [C.c_void_p]
+        L.orc_net_output.argtypes = [C.c_void_p, C.c_void_p]
+        L.orc_net_output.restype = C.c_double
         L.orc_loss.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_loss.restype = C.c_double
         L.orc_loss_rows.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p]
@@ -65,7 +69,8 @@ def lib():
 class _Problem(C.Structure):
     _fields_ = [("n_layers", C.c_int), ("widths", C.c_int * (MAX_LAYERS + 1)),
                 ("acts", C.c_int * MAX_LAYERS), ("loss", C.c_int), ("n_samples", C.c_int),
-                ("x", C.c_void_p), ("y", C.c_void_p), ("labels", C.c_void_p)]
+                ("x", C.c_void_p), ("y", C.c_void_p), ("labels", C.c_void_p),
+                ("kind", C.c_int), ("net", C.c_void_p)]
 
 
 class _Config(C.Structure):
@@ -90,9 +95,12 @@ def _ptr(a):
 
 
 class Problem:
-    """MLP loss problem.  Holds references to the arrays it points at."""
+    """MLP loss problem (the spark is the MLP's parameters), or with net= the
+    paper's testbed (the spark is the input of the fixed MLP whose parameters
+    are `net`; the fitness is its scalar output).  Holds references to the
+    arrays it points at."""
 
-    def __init__(self, widths, acts, loss, x=None, y=None, labels=None):
+    def __init__(self, widths, acts, loss="mse", x=None, y=None, labels=None, net=None):
         widths = [int(w) for w in widths]
         L = len(widths) - 1
         if not 1 <= L <= MAX_LAYERS:
@@ -110,11 +118,27 @@ class Problem:
         s.loss = LOSS[loss]
         s.n_samples = 0 if self.x is None else self.x.shape[0]
         s.x, s.y, s.labels = _ptr(self.x), _ptr(self.y), _ptr(self.labels)
+        self.net = None if net is None else np.ascontiguousarray(net, dtype=np.float32)
+        s.kind = KIND["input" if net is not None else "train"]
+        s.net = _ptr(self.net)
+        if net is not None and self.net.size != lib().orc_n_params(C.byref(s)):
+            raise ValueError("net parameter count does not match the widths")
         self.s = s
 
     @classmethod
     def from_workload(cls, wl):
+        if getattr(wl, "net", None) is not None:
+            return cls(wl.widths, wl.acts, net=wl.net)
         return cls(wl.widths, wl.acts, wl.loss, wl.x, wl.y, wl.labels)
+
+    @property
+    def n_params(self) -> int:
+        return lib().orc_n_params(C.byref(self.s))
+
+    def output(self, x) -> float:
+        """The fixed network's output at input x (input problems)."""
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        return lib().orc_net_output(C.byref(self.s), _ptr(x))
 
     @property
     def dim(self) -> int:

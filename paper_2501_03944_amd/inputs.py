@@ -19,6 +19,10 @@ provided, each at full size and at any smaller size a test wants:
   [0, 1]^784 built from 10 seeded class prototypes with 20 % support plus noise.
 * ``mixed_jobs``          many Gaussian-mixture jobs of uneven depth, width, sample
   count and spark count, for batched generations and serving.
+* ``testbed_net``         the paper's own testbed (Sec. 4.1, eq. (1), Table 2): a
+  fixed MLP d -> h -> (k hidden h -> h layers) -> 1 whose parameters are drawn
+  once, per layer from U(-1/sqrt(fan_in), +1/sqrt(fan_in)) (the paper says only
+  that they are random and fixed); the spark is the network's input.
 """
 from __future__ import annotations
 
@@ -257,3 +261,81 @@ def workload(name: str, **overrides) -> Workload:
 
 
 WORKLOAD_NAMES = ("mlp8-16-1", "mlp64-128-128-10", "mlp784-256-10")
+
+
+# The paper's testbed networks (Table 2): id -> (scale, activation, input dim d,
+# hidden width h, "Layer num" k).  The network is Linear(d, h), k hidden
+# Linear(h, h) layers, and Linear(h, 1), with the activation after every layer
+# but the last, so it has d*h + h + k*(h*h + h) + h + 1 parameters.
+TESTBED_NETS = {
+    1: ("small", "relu", 10, 16, 4),
+    2: ("small", "gelu", 10, 32, 4),
+    3: ("small", "relu", 20, 16, 4),
+    4: ("small", "gelu", 20, 32, 4),
+    5: ("medium", "relu", 100, 64, 7),
+    6: ("medium", "gelu", 100, 128, 7),
+    7: ("medium", "relu", 200, 64, 7),
+    8: ("medium", "gelu", 200, 128, 7),
+    9: ("large", "relu", 1000, 256, 10),
+    10: ("large", "gelu", 1000, 512, 10),
+    11: ("large", "relu", 2000, 256, 10),
+    12: ("large", "gelu", 2000, 512, 10),
+}
+
+
+@dataclasses.dataclass
+class NetInputWorkload:
+    """Input optimisation of a fixed MLP (the spark is the input, the fitness
+    the network's scalar output) plus the MGFWA shape it is run with."""
+
+    name: str
+    widths: tuple            # (d, h, ..., h, 1)
+    acts: tuple              # activation after every layer but the last
+    net: np.ndarray          # float32 parameters, nn.Linear layout (W_l row-major, then b_l)
+    n_fireworks: int = 8
+    n_sparks: int = 512
+    n_guiding: int = 8
+    generations: int = 100
+    lb: float = -5.0
+    ub: float = 5.0
+    extra: dict = dataclasses.field(default_factory=dict)
+    loss = None
+    x = y = labels = None
+
+    @property
+    def dim(self) -> int:
+        """Spark dimension: the input width d."""
+        return int(self.widths[0])
+
+    @property
+    def n_params(self) -> int:
+        w = self.widths
+        return int(sum(w[i] * w[i + 1] + w[i + 1] for i in range(len(w) - 1)))
+
+    def flops_per_eval(self) -> int:
+        """Algorithmic matmul work of one spark evaluation: 2 sum_l in_l out_l."""
+        w = self.widths
+        return int(2 * sum(w[i] * w[i + 1] for i in range(len(w) - 1)))
+
+
+def net_input_problem(widths, acts, seed: int, **shape) -> NetInputWorkload:
+    """A fixed MLP of any shape (widths[-1] must be 1) with seeded parameters."""
+    widths = tuple(int(v) for v in widths)
+    if widths[-1] != 1:
+        raise ValueError("the fixed network has one output")
+    wl = NetInputWorkload(name="net_input", widths=widths, acts=tuple(acts),
+                          net=teacher_weights(widths, seed))
+    _apply_shape(wl, shape, {})
+    return wl
+
+
+def testbed_net(net_id: int, seed: Optional[int] = None, **shape) -> NetInputWorkload:
+    """Table 2 network `net_id` with parameters drawn from seed (default
+    3000 + net_id)."""
+    scale, act, d, h, k = TESTBED_NETS[int(net_id)]
+    widths = (d,) + (h,) * (k + 1) + (1,)
+    wl = net_input_problem(widths, (act,) * (k + 1),
+                           seed=3000 + int(net_id) if seed is None else seed, **shape)
+    wl.name = f"net{int(net_id)}"
+    wl.extra.update(scale=scale, layer_num=k)
+    return wl
