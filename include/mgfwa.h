@@ -36,8 +36,10 @@ extern "C" {
 
 #define MGFWA_API __attribute__((visibility("default")))
 
-#define MGFWA_MAX_LAYERS 4  /* Linear layers per MLP */
-#define MGFWA_MAX_WIDTH 256 /* largest layer output width */
+#define MGFWA_MAX_LAYERS 12       /* Linear layers of a problem's MLP */
+#define MGFWA_MAX_TRAIN_LAYERS 4  /* ... when the spark is the MLP's weights */
+#define MGFWA_MAX_WIDTH 256       /* largest layer output width (weights problems) */
+#define MGFWA_MAX_NET_WIDTH 512   /* largest hidden width of a fixed network (input problems) */
 
 typedef struct mgfwa_ctx mgfwa_ctx;
 
@@ -54,9 +56,12 @@ typedef enum { MGFWA_ACT_IDENTITY = 0, MGFWA_ACT_RELU = 1, MGFWA_ACT_TANH = 2,
                MGFWA_ACT_GELU = 3 } mgfwa_act;
 typedef enum { MGFWA_LOSS_MSE = 0, MGFWA_LOSS_CE = 1 } mgfwa_loss;
 typedef enum { MGFWA_FP32 = 0, MGFWA_BF16 = 1 } mgfwa_precision;
+typedef enum { MGFWA_PROBLEM_WEIGHTS = 0, MGFWA_PROBLEM_INPUT = 1 } mgfwa_problem_kind;
 
 /*
- * The black box f of Alg. 1: the loss of an MLP whose weights are the spark.
+ * The black box f of Alg. 1, one of two kinds.
+ *
+ * kind = MGFWA_PROBLEM_WEIGHTS (0): the loss of an MLP whose weights are the spark.
  * Weight layout inside a spark (length D = sum_l in_l*out_l + out_l): for each
  * layer l in order, W_l as out_l x in_l row-major, then b_l (the nn.Linear
  * convention).  Hidden layers apply hidden_act[l]; the output layer is linear.
@@ -65,6 +70,14 @@ typedef enum { MGFWA_FP32 = 0, MGFWA_BF16 = 1 } mgfwa_precision;
  * x_dev    float32 [n_samples][widths[0]], row-major, device.
  * y_dev    float32 [n_samples][widths[n_layers]] (MSE only), device.
  * labels_dev int32 [n_samples], each in [0, widths[n_layers]) (CE only), device.
+ * At most MGFWA_MAX_TRAIN_LAYERS layers, output widths <= MGFWA_MAX_WIDTH.
+ *
+ * kind = MGFWA_PROBLEM_INPUT (1): the paper's testbed (Sec. 4.1, eq. (1)): the
+ * spark is the input x (D = widths[0]) of a fixed MLP and the fitness is its
+ * scalar output f(x) (widths[n_layers] = 1).  net_dev holds the network's
+ * float32 parameters in the weight layout above; hidden widths <= 512; loss,
+ * n_samples, x_dev, y_dev and labels_dev are ignored.  FP32 only.
+ *
  * The buffers are borrowed: mgfwa_init copies them into the workspace on the
  * stream, so they must stay valid until that work has run; afterwards the
  * library no longer reads them.
@@ -78,6 +91,8 @@ typedef struct {
     const float *x_dev;
     const float *y_dev;
     const int32_t *labels_dev;
+    int kind;                            /* mgfwa_problem_kind */
+    const float *net_dev;                /* INPUT: the fixed network's parameters, device */
 } mgfwa_problem;
 
 /*

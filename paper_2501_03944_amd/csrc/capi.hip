@@ -54,7 +54,7 @@ int round_up(int v, int a) { return (v + a - 1) / a * a; }
 struct Layout {
     size_t F, SE, SG, A, Y, Yprev, fresh, Yc, top, bottom, tie, cstar, improved, reinit, src;
     size_t best_x, best_y, best_f, best_gen, best_upd, ctrl, partial, Xp, Xb, Ypad, Lpad;
-    size_t Wpack, Xw, lo, hi, total;
+    size_t Wpack, Xw, lo, hi, Pnet, total;
     int partial_rows;
 };
 
@@ -63,6 +63,8 @@ enum Phase { PH_READY, PH_INIT_ASK, PH_INIT_TELL, PH_EXPL_TELL, PH_GUIDE_ASK, PH
 struct Derived {
     Shape s;
     Net net;
+    InNet in;        // input problems: the fixed network
+    bool input;
     Layout lay;
 };
 
@@ -89,23 +91,41 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
         return fail(MGFWA_EUNSUPPORTED, "lag_guiding needs the built-in fitness");
     if (c->precision != MGFWA_FP32 && c->precision != MGFWA_BF16)
         return fail(MGFWA_EINVAL, "unknown precision %d", c->precision);
-    if (p->n_layers < 1 || p->n_layers > MGFWA_MAX_LAYERS)
-        return fail(MGFWA_EINVAL, "n_layers must be in [1, %d]", MGFWA_MAX_LAYERS);
+    if (p->kind != MGFWA_PROBLEM_WEIGHTS && p->kind != MGFWA_PROBLEM_INPUT)
+        return fail(MGFWA_EINVAL, "unknown problem kind %d", p->kind);
+    const bool input = p->kind == MGFWA_PROBLEM_INPUT;
+    const int max_layers = input ? MGFWA_MAX_LAYERS : MGFWA_MAX_TRAIN_LAYERS;
+    if (p->n_layers < 1 || p->n_layers > max_layers)
+        return fail(MGFWA_EINVAL, "n_layers must be in [1, %d]", max_layers);
     for (int l = 0; l <= p->n_layers; ++l)
         if (p->widths[l] < 1) return fail(MGFWA_EINVAL, "width %d must be >= 1", l);
     if (p->widths[0] > 65536) return fail(MGFWA_EINVAL, "input width > 65536");
-    for (int l = 1; l <= p->n_layers; ++l)
-        if (p->widths[l] > MGFWA_MAX_WIDTH)
-            return fail(MGFWA_EUNSUPPORTED, "layer width %d > %d", p->widths[l], MGFWA_MAX_WIDTH);
     for (int l = 0; l < p->n_layers - 1; ++l)
         if (p->hidden_act[l] < 0 || p->hidden_act[l] > MGFWA_ACT_GELU)
             return fail(MGFWA_EINVAL, "unknown activation %d", p->hidden_act[l]);
-    if (p->loss != MGFWA_LOSS_MSE && p->loss != MGFWA_LOSS_CE)
-        return fail(MGFWA_EINVAL, "unknown loss %d", p->loss);
-    if (p->loss == MGFWA_LOSS_CE && p->widths[p->n_layers] < 2)
-        return fail(MGFWA_EINVAL, "cross-entropy needs >= 2 outputs");
-    const bool need_data = !c->external_fitness || p->x_dev;
-    if (need_data) {
+    if (input) {
+        if (p->widths[p->n_layers] != 1)
+            return fail(MGFWA_EINVAL, "the fixed network of an input problem has one output");
+        for (int l = 1; l < p->n_layers; ++l)
+            if (p->widths[l] > MGFWA_MAX_NET_WIDTH)
+                return fail(MGFWA_EUNSUPPORTED, "hidden width %d > %d", p->widths[l],
+                            MGFWA_MAX_NET_WIDTH);
+        if (c->precision != MGFWA_FP32)
+            return fail(MGFWA_EUNSUPPORTED, "input problems run in FP32");
+    } else {
+        for (int l = 1; l <= p->n_layers; ++l)
+            if (p->widths[l] > MGFWA_MAX_WIDTH)
+                return fail(MGFWA_EUNSUPPORTED, "layer width %d > %d", p->widths[l],
+                            MGFWA_MAX_WIDTH);
+        if (p->loss != MGFWA_LOSS_MSE && p->loss != MGFWA_LOSS_CE)
+            return fail(MGFWA_EINVAL, "unknown loss %d", p->loss);
+        if (p->loss == MGFWA_LOSS_CE && p->widths[p->n_layers] < 2)
+            return fail(MGFWA_EINVAL, "cross-entropy needs >= 2 outputs");
+    }
+    const bool need_data = !c->external_fitness || (input ? p->net_dev : p->x_dev);
+    if (need_data && input) {
+        if (!p->net_dev) return fail(MGFWA_EINVAL, "net_dev is NULL");
+    } else if (need_data) {
         if (p->n_samples < 1 || p->n_samples > (1 << 24))
             return fail(MGFWA_EINVAL, "n_samples must be in [1, 2^24]");
         if (!p->x_dev) return fail(MGFWA_EINVAL, "x_dev is NULL");
@@ -125,16 +145,40 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
     long D = 0;
     Net &net = out->net;
     std::memset(&net, 0, sizeof net);
-    net.nl = p->n_layers;
-    for (int l = 0; l < p->n_layers; ++l) {
-        net.fi[l] = p->widths[l];
-        net.fo[l] = p->widths[l + 1];
-        net.woff[l] = (int)D;
-        D += (long)net.fi[l] * net.fo[l];
-        net.boff[l] = (int)D;
-        D += net.fo[l];
-        net.act[l] = l < p->n_layers - 1 ? p->hidden_act[l] : MGFWA_ACT_IDENTITY;
-        net.vec[l] = (net.woff[l] % 4 == 0) && (net.fi[l] % 4 == 0);
+    InNet &in = out->in;
+    std::memset(&in, 0, sizeof in);
+    out->input = input;
+    if (input) {
+        // the spark is the network's input; the parameters are packed once
+        in.nl = p->n_layers;
+        int off = 0, hmax = 0;
+        for (int l = 0; l < p->n_layers; ++l) {
+            in.fi[l] = p->widths[l];
+            in.fo[l] = p->widths[l + 1];
+            in.kp[l] = round_up(in.fi[l], 16);
+            in.np[l] = round_up(in.fo[l], 16);
+            in.act[l] = l < p->n_layers - 1 ? p->hidden_act[l] : MGFWA_ACT_IDENTITY;
+            in.woff[l] = off;
+            off += in.np[l] * in.kp[l];
+            in.boff[l] = off;
+            off += in.np[l];
+            if (l > 0) hmax = std::max(hmax, in.kp[l]);
+        }
+        in.n_packed = off;
+        in.hs = hmax + 4;   // 16-byte skew between the rows of the activation tile
+        D = p->widths[0];
+    } else {
+        net.nl = p->n_layers;
+        for (int l = 0; l < p->n_layers; ++l) {
+            net.fi[l] = p->widths[l];
+            net.fo[l] = p->widths[l + 1];
+            net.woff[l] = (int)D;
+            D += (long)net.fi[l] * net.fo[l];
+            net.boff[l] = (int)D;
+            D += net.fo[l];
+            net.act[l] = l < p->n_layers - 1 ? p->hidden_act[l] : MGFWA_ACT_IDENTITY;
+            net.vec[l] = (net.woff[l] % 4 == 0) && (net.fi[l] % 4 == 0);
+        }
     }
     if (D > (1L << 26)) return fail(MGFWA_EINVAL, "spark dimension %ld too large", D);
     s.D = (int)D;
@@ -156,22 +200,27 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
     s.lag = c->lag_guiding ? 1 : 0;
     s.map_range = c->map_range ? 1 : 0;
 
-    net.loss = p->loss;
-    net.bf16 = c->precision == MGFWA_BF16;
-    net.S = need_data ? p->n_samples : 0;
-    net.S_pad = need_data ? round_up(p->n_samples, S_ALIGN) : 0;
-    net.in_pad = round_up(net.fi[0], net.bf16 ? 32 : 16);
-    const int outw = net.fo[net.nl - 1];
-    net.inv_norm = net.loss == MGFWA_LOSS_MSE ? (float)(1.0 / ((double)net.S * outw))
-                                              : (float)(1.0 / (double)net.S);
-    // Two-layer networks whose staged weights exceed the LDS stream their first
-    // layer through LDS instead (MGFWA_FORCE_WIDE=1 forces it, for tests).
-    const char *fw = std::getenv("MGFWA_FORCE_WIDE");
-    const bool force_wide = fw && fw[0] == '1';
-    net.wide = need_data && wide_applicable(net) &&
-               (force_wide || resident_lds_bytes(net) > 160 * 1024 - 512);
-    if (net.wide && net.S_pad / 256 > fit_max_bpr())
-        return fail(MGFWA_EUNSUPPORTED, "too many samples for the wide fitness kernel");
+    int outw = 1;
+    if (input) {
+        net.loss = -1;   // no sample data, no targets
+    } else {
+        net.loss = p->loss;
+        net.bf16 = c->precision == MGFWA_BF16;
+        net.S = need_data ? p->n_samples : 0;
+        net.S_pad = need_data ? round_up(p->n_samples, S_ALIGN) : 0;
+        net.in_pad = round_up(net.fi[0], net.bf16 ? 32 : 16);
+        outw = net.fo[net.nl - 1];
+        net.inv_norm = net.loss == MGFWA_LOSS_MSE ? (float)(1.0 / ((double)net.S * outw))
+                                                  : (float)(1.0 / (double)net.S);
+        // Two-layer networks whose staged weights exceed the LDS stream their first
+        // layer through LDS instead (MGFWA_FORCE_WIDE=1 forces it, for tests).
+        const char *fw = std::getenv("MGFWA_FORCE_WIDE");
+        const bool force_wide = fw && fw[0] == '1';
+        net.wide = need_data && wide_applicable(net) &&
+                   (force_wide || resident_lds_bytes(net) > 160 * 1024 - 512);
+        if (net.wide && net.S_pad / 256 > fit_max_bpr())
+            return fail(MGFWA_EUNSUPPORTED, "too many samples for the wide fitness kernel");
+    }
 
     Layout &L = out->lay;
     size_t off = 0;
@@ -215,6 +264,7 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
     L.Xw = take(net.wide ? (size_t)net.S_pad * wide_kp(net) * (net.bf16 ? 2 : 4) : 0);
     L.lo = take(s.map_range ? (size_t)s.B * Dp * 4 : 0);
     L.hi = take(s.map_range ? (size_t)s.B * Dp * 4 : 0);
+    L.Pnet = take(input && need_data ? (size_t)in.n_packed * 4 : 0);
     L.total = off;
     if (s.lag && L.SG != L.SE + BN * s.lam * Dp * 4)
         return fail(MGFWA_EINVAL, "internal: guiding sparks must follow the explosion sparks");
@@ -227,6 +277,8 @@ struct mgfwa_ctx {
     mgfwa_config cfg;
     Shape s;
     Net net;
+    InNet in;
+    bool input = false;
     Layout lay;
     DevState d;
     bool has_data;
@@ -290,7 +342,10 @@ mgfwa_status fit_rows(mgfwa_ctx *c, const FitPlan &plan, const float *W, size_t 
                       OutMap map, float *out, hipStream_t st, hipEvent_t mid = nullptr,
                       hipEvent_t pre = nullptr)
 {
-    if (c->net.wide)
+    if (c->input) {
+        STEP(launch_net_input(c->in, c->d.Pnet, W, ld, rows, map, out, st), "fitness_input");
+        if (mid) STEP(hipEventRecord(mid, st), "event");
+    } else if (c->net.wide)
         STEP(launch_fitness_wide(c->net, c->d, W, ld, rows, map, out, st, mid, pre), "fitness_wide");
     else
         STEP(launch_fitness(c->net, plan, c->d, W, ld, rows, map, out, st, mid), "fitness");
@@ -410,9 +465,10 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
     if (workspace_bytes < dv.lay.total)
         return fail(MGFWA_ENOMEM, "workspace too small: %zu < %zu bytes", workspace_bytes,
                     dv.lay.total);
-    const bool has_data = !config->external_fitness || problem->x_dev;
+    const bool has_data = !config->external_fitness ||
+                          (dv.input ? (const void *)problem->net_dev : (const void *)problem->x_dev);
     FitPlan pi{}, pe{}, pg{}, pv{};
-    if (has_data && !dv.net.wide) {
+    if (has_data && !dv.input && !dv.net.wide) {
         if (!fit_select(dv.net, dv.s.BN, &pi) || !fit_select(dv.net, dv.s.BN * expl_rows(dv.s), &pe) ||
             !fit_select(dv.net, dv.s.BN * dv.s.G, &pg) ||
             !fit_select(dv.net, dv.lay.partial_rows, &pv))
@@ -426,7 +482,12 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
     int num_cu = 0;
     HIP_TRY(hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev));
     dv.net.num_cu = num_cu > 0 ? num_cu : 1;
-    if (has_data && dv.net.wide) {
+    dv.in.num_cu = dv.net.num_cu;
+    if (has_data && dv.input) {
+        if (net_input_lds_bytes(dv.in) > (size_t)lds_max)
+            return fail(MGFWA_EUNSUPPORTED, "device LDS too small for the network's activations");
+        HIP_TRY(net_input_prepare(dv.in));
+    } else if (has_data && dv.net.wide) {
         if (wide_lds_bytes(dv.net) > lds_max - 64)
             return fail(MGFWA_EUNSUPPORTED, "device LDS too small for the wide fitness kernel");
         HIP_TRY(wide_prepare(dv.net));
@@ -442,6 +503,8 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
     c->cfg = *config;
     c->s = dv.s;
     c->net = dv.net;
+    c->in = dv.in;
+    c->input = dv.input;
     c->lay = dv.lay;
     c->has_data = has_data;
     c->ws = static_cast<char *>(workspace_dev);
@@ -487,6 +550,7 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
     d.Xw = c->net.wide ? at<char>(b, L.Xw) : nullptr;
     d.lo = c->s.map_range ? at<float>(b, L.lo) : nullptr;
     d.hi = c->s.map_range ? at<float>(b, L.hi) : nullptr;
+    d.Pnet = c->input && has_data ? at<float>(b, L.Pnet) : nullptr;
 
     auto bail = [&](mgfwa_status st) {
         mgfwa_destroy(c);
@@ -494,7 +558,10 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
     };
     r = reset_ctrl(c);
     if (r) return bail(r);
-    if (has_data) {
+    if (has_data && c->input) {
+        r = check(c, launch_pack_net(c->in, problem->net_dev, d.Pnet, c->stream), "pack_net");
+        if (r) return bail(r);
+    } else if (has_data) {
         r = check(c, launch_pack_problem(c->net, problem->x_dev, problem->y_dev,
                                          problem->labels_dev, d, c->stream), "pack");
         if (r) return bail(r);
@@ -657,11 +724,13 @@ mgfwa_status mgfwa_evaluate(mgfwa_ctx *c, const float *w, int rows, int ld, floa
     if (rows < 0 || (rows > 0 && (!w || !out))) return fail(MGFWA_EINVAL, "bad rows/buffers");
     if (ld < c->s.D || ld % 4 != 0 || reinterpret_cast<uintptr_t>(w) % 16 != 0)
         return fail(MGFWA_EINVAL, "ld must be >= D and a multiple of 4; w 16-byte aligned");
-    const int chunk = c->lay.partial_rows;
+    // the weights-problem kernels stage per-row partial sums in a buffer of
+    // partial_rows rows; the input-problem kernel needs none
+    const int chunk = c->input ? std::max(rows, 1) : c->lay.partial_rows;
     for (int r0 = 0; r0 < rows; r0 += chunk) {
         const int nr = std::min(chunk, rows - r0);
         FitPlan plan{};
-        if (!c->net.wide) {
+        if (!c->net.wide && !c->input) {
             if (!fit_select(c->net, nr, &plan))
                 return fail(MGFWA_EUNSUPPORTED, "no compiled fitness kernel covers this MLP shape");
             HIP_TRY(fit_prepare(plan));
@@ -922,7 +991,7 @@ mgfwa_status mgfwa_autotune(mgfwa_ctx *c, int reps)
         return fail(MGFWA_ESTATE, "autotuning needs the built-in fitness");
     if (c->phase != PH_READY || c->gen_host != 0 || c->gexec)
         return fail(MGFWA_ESTATE, "autotune before the first generation");
-    if (c->net.wide) return MGFWA_OK;   // one fixed tile shape
+    if (c->net.wide || c->input) return MGFWA_OK;   // one fixed tile shape
     const Shape &s = c->s;
     mgfwa_status r = tune_plan(c, s.BN * expl_rows(s), c->d.SE, expl_map(s), reps, &c->plan_expl);
     if (r) return r;
@@ -937,7 +1006,7 @@ mgfwa_status mgfwa_fit_plan(const mgfwa_ctx *c, int which, mgfwa_plan_info *info
     std::memset(info, 0, sizeof *info);
     info->wide = c->net.wide ? 1 : 0;
     info->rows = which == 0 ? c->s.BN * expl_rows(c->s) : c->s.BN * c->s.G;
-    if (!c->net.wide) {
+    if (!c->net.wide && !c->input) {
         info->wavefronts = p.nw;
         info->slabs = p.P;
         info->lds_weights = p.wl;

@@ -39,6 +39,7 @@ struct DevState {
     char *Wpack;       // packed spark rows for the wide-first-layer kernel
     char *Xw;          // [S_pad][Kp] samples with a ones column (wide kernel)
     float *lo, *hi;    // [B][Dp] population ranges (range mapping)
+    float *Pnet;       // packed parameters of a fixed network (input problems)
 };
 
 // Population shape and algorithm constants as the kernels need them.
@@ -68,6 +69,23 @@ struct Net {
     int lds_max;                       // LDS bytes a block may use (0: weights stay in global)
     int wide;                          // first layer streamed through LDS (two-layer nets)
     int num_cu;                        // compute units (persistent grid size)
+};
+
+// A fixed MLP whose input is the spark (the paper's testbed, eq. (1)), as its
+// fitness kernel needs it.  Packed parameters: per layer W_l zero-padded to
+// np[l] x kp[l] (row-major, output-major like nn.Linear), then b_l padded to
+// np[l]; kp of a hidden layer is np of the layer before it.
+constexpr int NET_MAXL = 12;
+constexpr int NET_MAXW = 512;
+struct InNet {
+    int nl;                            // layers (the last has one output)
+    int fi[NET_MAXL], fo[NET_MAXL];    // true widths
+    int kp[NET_MAXL], np[NET_MAXL];    // K and N padded to 16
+    int act[NET_MAXL];                 // activation after layer l (identity for the last)
+    int woff[NET_MAXL], boff[NET_MAXL];// float offsets into the packed parameters
+    int n_packed;                      // floats of the packed parameters
+    int hs;                            // LDS row pitch (floats) of the activation tile
+    int num_cu;                        // compute units (rows per block choice)
 };
 
 // A chosen fitness kernel and its launch geometry for a given row count.
@@ -121,6 +139,15 @@ hipError_t launch_pack_problem(const Net &net, const float *x, const float *y,
 int fit_max_bpr();
 // LDS bytes the resident-weights kernel would need for this network
 int resident_lds_bytes(const Net &net);
+
+// ---- net_input.hip (input problems)
+// Pack the caller's nn.Linear-layout parameters into the padded blocks.
+hipError_t launch_pack_net(const InNet &net, const float *params, float *packed, hipStream_t st);
+// out[map.index(r)] = f(x_r) for the rows of X (leading dimension ld >= fi[0]).
+hipError_t launch_net_input(const InNet &net, const float *packed, const float *X, size_t ld,
+                            int rows, OutMap map, float *out, hipStream_t st);
+size_t net_input_lds_bytes(const InNet &net);
+hipError_t net_input_prepare(const InNet &net);   // raises the kernels' LDS limit
 
 // ---- fit_wide.hip
 bool wide_applicable(const Net &net);

@@ -1,0 +1,214 @@
+// Fitness of input problems, the paper's own testbed (Sec. 4.1, eq. (1),
+// Table 2): every spark row x is the input of one fixed MLP and its fitness is
+// the network's scalar output f(x).
+//
+// Shape of the work: one shared set of weights against many rows -- a chain of
+// GEMMs [rows x fi] * [fi x fo] with bias and activation between them.  One
+// block carries 16*RB rows through every layer:
+//   * the activations of its rows stay in LDS from layer to layer (the layer
+//     reads them as the A operand, then, after a barrier, overwrites them with
+//     its own outputs), so nothing but the spark rows and the final outputs
+//     touches HBM;
+//   * the weights are read straight from global memory as B fragments; every
+//     block reads the same parameters at about the same time, layer by layer,
+//     so they are served by L2;
+//   * the products run on v_mfma_f32_16x16x4_f32 (FP32 in, FP32 accumulate):
+//     each wave owns the 16-column blocks j = wave, wave + 8, ... of a layer's
+//     output and all 16*RB rows.
+// Fragment layout (one 16-wide K chunk, lane = 16 q + c): the lane holds rows
+// (or output columns) c and the K range 4q..4q+3 of the chunk as one float4;
+// MFMA e of the chunk takes element e, so the four MFMAs together cover the 16
+// K values and the output element (row 4q + v, column c) lands in accumulator
+// lane 16 q + c, slot v.
+#include "internal.h"
+
+namespace mgfwa {
+namespace {
+
+constexpr int NI_NW = 8;                      // waves per block
+constexpr int NI_CB = NET_MAXW / 16 / NI_NW;  // output column blocks per wave at most
+constexpr int TPB = 256;
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float ni_act(int act, float z)
+{
+    switch (act) {
+    case MGFWA_ACT_RELU: return z > 0.0f ? z : 0.0f;
+    case MGFWA_ACT_TANH: return tanhf(z);
+    case MGFWA_ACT_GELU: return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+    default: return z;
+    }
+}
+
+__device__ __forceinline__ void mfma4(floatx4 &acc, const float4 &a, const float4 &b)
+{
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
+}
+
+template <int RB>
+__global__ __launch_bounds__(NI_NW * 64) void k_net_input(InNet net, const float *__restrict__ P,
+                                                          const float *__restrict__ X, size_t ld,
+                                                          int rows, OutMap map,
+                                                          float *__restrict__ out)
+{
+    extern __shared__ float act[];   // [16*RB][hs]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = lane & 15, q = lane >> 4;
+    const int r0 = blockIdx.x * 16 * RB;
+    const int hs = net.hs;
+    const int d = net.fi[0];
+    const float *xr[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        const int r = r0 + 16 * rb + c;   // rows past the end repeat the last row
+        xr[rb] = X + (size_t)(r < rows ? r : rows - 1) * ld;
+    }
+    for (int l = 0; l < net.nl; ++l) {
+        const int K = net.kp[l], nb = net.np[l] >> 4;
+        const float *W = P + net.woff[l];
+        floatx4 acc[RB][NI_CB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int jb = 0; jb < NI_CB; ++jb) acc[rb][jb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int kc = 0; kc < K; kc += 16) {
+            float4 a[RB];
+            if (l == 0) {
+                if (kc + 16 <= d) {
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+                        a[rb] = *reinterpret_cast<const float4 *>(xr[rb] + kc + 4 * q);
+                } else {   // the last chunk of the input: elements past d read as zero
+                    const int k = kc + 4 * q;
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+                        a[rb] = make_float4(k < d ? xr[rb][k] : 0.0f, k + 1 < d ? xr[rb][k + 1] : 0.0f,
+                                            k + 2 < d ? xr[rb][k + 2] : 0.0f,
+                                            k + 3 < d ? xr[rb][k + 3] : 0.0f);
+                }
+            } else {
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+                    a[rb] = *reinterpret_cast<const float4 *>(act + (16 * rb + c) * hs + kc + 4 * q);
+            }
+#pragma unroll
+            for (int jb = 0; jb < NI_CB; ++jb) {
+                const int j = wave + NI_NW * jb;
+                if (j < nb) {
+                    const float4 b =
+                        *reinterpret_cast<const float4 *>(W + (size_t)(16 * j + c) * K + kc + 4 * q);
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) mfma4(acc[rb][jb], a[rb], b);
+                }
+            }
+        }
+        __syncthreads();   // every wave has read this layer's input tile
+        const float *bias = P + net.boff[l];
+        const bool last = l == net.nl - 1;
+#pragma unroll
+        for (int jb = 0; jb < NI_CB; ++jb) {
+            const int j = wave + NI_NW * jb;
+            if (j >= nb) continue;
+            const int col = 16 * j + c;
+            const float bv = bias[col];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * rb + 4 * q + v;
+                    const float z = acc[rb][jb][v] + bv;
+                    if (!last) {
+                        act[row * hs + col] = z;
+                    } else if (col == 0 && r0 + row < rows) {
+                        out[map.index(r0 + row)] = canon_fitness(z);
+                    }
+                }
+        }
+        if (last) break;
+        __syncthreads();   // the pre-activations of the tile are in place
+        // the activation as an elementwise pass over the tile, once the
+        // accumulators are dead (keeps the product loop's registers free)
+        const int fn = net.act[l], np = net.np[l];
+        if (fn != MGFWA_ACT_IDENTITY) {
+            for (int i = threadIdx.x; i < 16 * RB * np; i += NI_NW * 64) {
+                float *e = act + (i / np) * hs + i % np;
+                *e = ni_act(fn, *e);
+            }
+            __syncthreads();   // the next layer reads the whole output tile
+        }
+    }
+}
+
+// Packed parameter i of layer l: W block [np][kp] then the bias [np], zeros
+// outside the true fo x fi (and fo) extents.
+__global__ __launch_bounds__(TPB) void k_pack_net(InNet net, const float *__restrict__ src,
+                                                  float *__restrict__ dst)
+{
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    if (i >= net.n_packed) return;
+    int l = 0;
+    size_t soff = 0;
+    while (l + 1 < net.nl && i >= net.woff[l + 1]) {
+        soff += (size_t)net.fi[l] * net.fo[l] + net.fo[l];
+        ++l;
+    }
+    const int fi = net.fi[l], fo = net.fo[l], kp = net.kp[l];
+    const int o = i - net.woff[l];
+    float v = 0.0f;
+    if (i < net.boff[l]) {
+        const int n = o / kp, k = o % kp;
+        if (n < fo && k < fi) v = src[soff + (size_t)n * fi + k];
+    } else {
+        const int n = i - net.boff[l];
+        if (n < fo) v = src[soff + (size_t)fi * fo + n];
+    }
+    dst[i] = v;
+}
+
+template <int RB>
+size_t lds_bytes_rb(const InNet &net) { return (size_t)16 * RB * net.hs * sizeof(float); }
+
+}  // namespace
+
+size_t net_input_lds_bytes(const InNet &net) { return lds_bytes_rb<2>(net); }
+
+hipError_t launch_pack_net(const InNet &net, const float *params, float *packed, hipStream_t st)
+{
+    const unsigned blocks = (unsigned)((net.n_packed + TPB - 1) / TPB);
+    hipLaunchKernelGGL(k_pack_net, dim3(blocks), dim3(TPB), 0, st, net, params, packed);
+    return hipGetLastError();
+}
+
+hipError_t net_input_prepare(const InNet &net)
+{
+    hipError_t e = hipFuncSetAttribute((const void *)k_net_input<1>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds_bytes_rb<1>(net));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_net_input<2>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes_rb<2>(net));
+    return e;
+}
+
+hipError_t launch_net_input(const InNet &net, const float *packed, const float *X, size_t ld,
+                            int rows, OutMap map, float *out, hipStream_t st)
+{
+    if (rows <= 0) return hipSuccess;
+    // the most rows per block that still gives every compute unit a block
+    const long cu = net.num_cu > 0 ? net.num_cu : 256;
+    const dim3 block(NI_NW * 64);
+    if (rows >= 32 * cu) {
+        hipLaunchKernelGGL(k_net_input<2>, dim3((rows + 31) / 32), block, lds_bytes_rb<2>(net), st,
+                           net, packed, X, ld, rows, map, out);
+    } else {
+        hipLaunchKernelGGL(k_net_input<1>, dim3((rows + 15) / 16), block, lds_bytes_rb<1>(net), st,
+                           net, packed, X, ld, rows, map, out);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mgfwa

@@ -16,8 +16,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmgfwa.so")
 
-MAX_LAYERS = 4
+MAX_LAYERS = 12         # Linear layers of a problem's MLP
+MAX_TRAIN_LAYERS = 4    # ... when the spark is the MLP's weights
 MAX_WIDTH = 256
+KIND = {"weights": 0, "input": 1}
 N_PHASES = 5
 PHASES = ("explosion", "fitness_explosion", "guiding", "fitness_guiding", "selection")
 
@@ -30,7 +32,8 @@ PRECISION = {"fp32": 0, "bf16": 1}
 class mgfwa_problem(C.Structure):
     _fields_ = [("n_layers", C.c_int), ("widths", C.c_int * (MAX_LAYERS + 1)),
                 ("hidden_act", C.c_int * MAX_LAYERS), ("loss", C.c_int), ("n_samples", C.c_int),
-                ("x_dev", C.c_void_p), ("y_dev", C.c_void_p), ("labels_dev", C.c_void_p)]
+                ("x_dev", C.c_void_p), ("y_dev", C.c_void_p), ("labels_dev", C.c_void_p),
+                ("kind", C.c_int), ("net_dev", C.c_void_p)]
 
 
 class mgfwa_config(C.Structure):
@@ -171,16 +174,21 @@ def make_config(n_fireworks=4, n_sparks=32, n_guiding=4, n_populations=1, sigma=
     return c
 
 
-def make_problem(widths, acts, loss, n_samples, x_ptr=0, y_ptr=0, labels_ptr=0) -> mgfwa_problem:
+def make_problem(widths, acts, loss, n_samples, x_ptr=0, y_ptr=0, labels_ptr=0,
+                 net_ptr=None) -> mgfwa_problem:
+    """A weights problem, or with net_ptr (0 for external fitness) an input
+    problem: the spark is the input of the fixed network at net_ptr."""
     p = mgfwa_problem()
     p.n_layers = len(widths) - 1
     for i, w in enumerate(widths):
         p.widths[i] = int(w)
     for i, a in enumerate(acts):
         p.hidden_act[i] = ACT[a] if isinstance(a, str) else int(a)
-    p.loss = LOSS[loss] if isinstance(loss, str) else int(loss)
+    p.loss = LOSS[loss] if isinstance(loss, str) else int(loss or 0)
     p.n_samples = int(n_samples)
     p.x_dev, p.y_dev, p.labels_dev = x_ptr or None, y_ptr or None, labels_ptr or None
+    p.kind = KIND["weights" if net_ptr is None else "input"]
+    p.net_dev = net_ptr or None
     return p
 
 
@@ -332,10 +340,13 @@ def mgfwa_server_destroy(server) -> None:
 
 
 class MGFWA:
-    """One optimisation job: problem buffers and workspace as torch CUDA tensors."""
+    """One optimisation job: problem buffers and workspace as torch CUDA tensors.
+    With net= (the fixed network's parameters) the spark is that network's input
+    and the fitness its output (the paper's testbed); loss and samples are then
+    unused."""
 
-    def __init__(self, widths, acts, loss, x=None, y=None, labels=None, device="cuda",
-                 stream=None, **config):
+    def __init__(self, widths, acts, loss=None, x=None, y=None, labels=None, device="cuda",
+                 stream=None, net=None, **config):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -356,10 +367,14 @@ class MGFWA:
         yt = dev(y, torch.float32) if loss == "mse" else None
         lt = dev(labels, torch.int32) if loss == "ce" else None
         n_samples = 0 if xt is None else xt.shape[0]
+        # net=True: an input problem without parameters (external fitness)
+        nt = dev(net, torch.float32) if net is not None and not isinstance(net, bool) else None
         self.problem = make_problem(self.widths, self.acts, loss, n_samples,
                                     0 if xt is None else xt.data_ptr(),
                                     0 if yt is None else yt.data_ptr(),
-                                    0 if lt is None else lt.data_ptr())
+                                    0 if lt is None else lt.data_ptr(),
+                                    None if net is None else
+                                    (0 if isinstance(net, bool) else nt.data_ptr()))
         self.config = make_config(**config)
         self.nbytes = mgfwa_workspace_bytes(self.config, self.problem)
         if self.nbytes == 0:
@@ -379,6 +394,10 @@ class MGFWA:
         kw = dict(n_fireworks=wl.n_fireworks, n_sparks=wl.n_sparks, n_guiding=wl.n_guiding,
                   lb=wl.lb, ub=wl.ub, max_generations=wl.generations)
         kw.update(config)
+        if getattr(wl, "net", None) is not None:
+            if kw.get("external_fitness"):
+                return cls(wl.widths, wl.acts, net=True, **kw)
+            return cls(wl.widths, wl.acts, net=wl.net, **kw)
         return cls(wl.widths, wl.acts, wl.loss, wl.x, wl.y, wl.labels, **kw)
 
     def close(self):

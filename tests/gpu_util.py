@@ -39,7 +39,9 @@ def make_pair(wl, n_populations=1, n_fireworks=None, n_sparks=None, n_guiding=No
                      loser_out=int(loser_out), use_target=int(target is not None),
                      target_loss=0.0 if target is None else target,
                      lag_guiding=int(lag_guiding), map_range=int(map_range))
-    g = M.MGFWA(wl.widths, wl.acts, wl.loss, wl.x, wl.y, wl.labels, n_populations=n_populations,
+    prob = (dict(net=wl.net) if getattr(wl, "net", None) is not None else
+            dict(loss=wl.loss, x=wl.x, y=wl.y, labels=wl.labels))
+    g = M.MGFWA(wl.widths, wl.acts, **prob, n_populations=n_populations,
                 n_fireworks=N, n_sparks=lam, n_guiding=G, sigma=sigma, boost=boost,
                 amp_up=amp_up, amp_down=amp_down, lb=wl.lb, ub=wl.ub, max_generations=T,
                 loser_out=loser_out, precision=precision, external_fitness=external,
@@ -101,17 +103,19 @@ def compare_state(ov, gs, D, B, what, with_sparks=True):
         assert_bits(gs["SG"][:, :D], ov["SG"], f"{what} SG")
 
 
-def near_tie_present(prev, cur, lam, G, m, k, rel=2 * FIT_RTOL, guide_yc=None, check_guide=True):
+def near_tie_present(prev, cur, lam, G, m, k, rel=2 * FIT_RTOL, guide_yc=None, check_guide=True,
+                     atol=1e-30):
     """True when some decision of the oracle's last generation compared two
     fitness values within `rel` of each other (either branch is then valid).
     guide_yc: the candidate fitness the guiding cut ranked (the previous
     generation's in the lag order; the current one by default); check_guide
-    False when no guiding cut was made (the lag order's first generation)."""
+    False when no guiding cut was made (the lag order's first generation);
+    atol: an absolute closeness floor (fitness bounds that are not relative)."""
     def close(a, b):
         a, b = float(a), float(b)
         if not (np.isfinite(a) and np.isfinite(b)):
             return False
-        return abs(a - b) <= rel * max(abs(a), abs(b)) + 1e-30
+        return abs(a - b) <= rel * max(abs(a), abs(b)) + atol
 
     Yc = cur["Yc"]
     Yg = Yc if guide_yc is None else guide_yc

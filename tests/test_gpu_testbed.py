@@ -1,0 +1,198 @@
+"""The paper's testbed on the HIP path (Sec. 4.1, eq. (1), Table 2; needs an
+MI355X): the spark is the input of a fixed MLP and its fitness the network's
+output, computed by the fused MFMA kernel that carries a tile of sparks through
+every layer.
+
+Fitness tolerance (FP32 products, FP32 accumulation, against the binary64
+oracle): |got - f(x)| <= 1e-6 |f(x)| + (sum_l K_l) 2^-22 S(x), where K_l is the
+padded reduction length of layer l and S(x) the output of the same network run
+on |x| with |W| and |b| and no activation (the magnitude of everything summed
+along the way): a rounding error of at most 4 units of 2^-24 per term summed,
+with room for the activations' slope above one.  State: bit-exact with the
+oracle, as for weight problems, until a near-tie.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import assert_bits, make_pair, near_tie_present, require_gpu
+from oracle import oracle as O
+from paper_2501_03944_amd import inputs
+from test_gpu_parity import _lockstep
+
+pytestmark = pytest.mark.gpu
+
+
+def _abs_scale(wl, X):
+    """S(x) per row: the network on |x| with |W|, |b| and no activation."""
+    H, off = np.abs(X.astype(np.float64)), 0
+    for fi, fo in zip(wl.widths[:-1], wl.widths[1:]):
+        W = np.abs(wl.net[off:off + fi * fo].astype(np.float64).reshape(fo, fi))
+        b = np.abs(wl.net[off + fi * fo:off + fi * fo + fo].astype(np.float64))
+        H = H @ W.T + b
+        off += fi * fo + fo
+    return H[:, 0]
+
+
+def _k_total(wl):
+    return sum((fi + 15) // 16 * 16 for fi in wl.widths[:-1])
+
+
+def assert_net_close(wl, X, got, want, what):
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    bound = 1e-6 * np.abs(want) + _k_total(wl) * 2.0 ** -22 * _abs_scale(wl, X)
+    err = np.abs(got - want)
+    bad = ~(err <= bound)
+    if np.any(bad):
+        i = int(np.argwhere(bad)[0, 0])
+        raise AssertionError(f"{what}: {int(bad.sum())}/{bad.size} outside the bound; first row {i}: "
+                             f"{got[i]} vs {want[i]} (bound {bound[i]:.3e})")
+    return float((err / np.maximum(bound, 1e-300)).max())
+
+
+def _eval(torch, g, X, ld=None):
+    rows, d = X.shape
+    ld = ld or g.Dp
+    Xd = torch.zeros((rows, ld), dtype=torch.float32, device="cuda")
+    Xd[:, :d] = torch.from_numpy(X)
+    return g.evaluate(Xd).cpu().numpy(), Xd
+
+
+@pytest.mark.parametrize("net_id", list(range(1, 13)))
+def test_fitness_matches_oracle_every_table2_net(net_id):
+    torch, M = require_gpu()
+    wl = inputs.testbed_net(net_id)
+    g = M.MGFWA.from_workload(wl, n_fireworks=2, n_sparks=16, n_guiding=4)
+    p = O.Problem.from_workload(wl)
+    rng = np.random.default_rng(net_id)
+    for rows, lo, hi in ((37, -5.0, 5.0), (100, -0.5, 0.5)):
+        X = rng.uniform(lo, hi, (rows, wl.dim)).astype(np.float32)
+        got, _ = _eval(torch, g, X)
+        r = assert_net_close(wl, X, got, p.loss_rows(X), f"net {net_id} U({lo},{hi})")
+        print(f"net {net_id} rows {rows}: worst error / bound = {r:.2e}")
+    g.close()
+
+
+def test_unpadded_rows_ignore_what_follows_the_input():
+    """ld = d rounded up to 4 with NaN in the gap: the kernel reads exactly d
+    inputs per row, also in the last partial chunk."""
+    torch, M = require_gpu()
+    for widths, acts in (((10, 32, 32, 1), ("gelu", "gelu")), ((100, 64, 1), ("relu",)),
+                         ((3, 16, 1), ("tanh",))):
+        wl = inputs.net_input_problem(widths, acts, seed=sum(widths))
+        g = M.MGFWA.from_workload(wl, n_fireworks=2, n_sparks=16, n_guiding=4)
+        p = O.Problem.from_workload(wl)
+        d = widths[0]
+        ld = (d + 3) // 4 * 4
+        X = np.random.default_rng(d).uniform(-3, 3, (53, d)).astype(np.float32)
+        Xd = torch.full((53, ld), float("nan"), dtype=torch.float32, device="cuda")
+        Xd[:, :d] = torch.from_numpy(X)
+        got = g.evaluate(Xd).cpu().numpy()
+        assert np.all(np.isfinite(got))
+        assert_net_close(wl, X, got, p.loss_rows(X), f"{widths} ld={ld}")
+        g.close()
+
+
+def test_many_rows_sampled_against_oracle():
+    """Enough rows for the 32-row tiles (>= 32 per compute unit): sampled rows,
+    the first and the ragged last tile included."""
+    torch, M = require_gpu()
+    wl = inputs.testbed_net(12)
+    g = M.MGFWA.from_workload(wl, n_fireworks=2, n_sparks=16, n_guiding=4)
+    p = O.Problem.from_workload(wl)
+    rows = 32 * 256 * 2 + 13
+    X = np.random.default_rng(5).uniform(-5, 5, (rows, wl.dim)).astype(np.float32)
+    got, _ = _eval(torch, g, X)
+    idx = np.unique(np.concatenate([np.arange(40), np.arange(rows - 45, rows),
+                                    np.random.default_rng(6).integers(0, rows, 48)]))
+    assert_net_close(wl, X[idx], got[idx], p.loss_rows(X[idx]), "net 12 sampled rows")
+    g.close()
+
+
+def _free_run(wl, gens, **cfg):
+    torch, M = require_gpu()
+    o, g = make_pair(wl, **cfg)
+    D = g.D
+    o.init()
+    gs, ov = g.state_numpy(), o.view()
+    assert_bits(gs["F"][:, :D], ov["F"], "init F")
+    lam, G = o.cfg.lam, o.cfg.G
+    try:
+        for gen in range(1, gens + 1):
+            prev = o.view()
+            o.generation()
+            g.step(1)
+            ov, gs = o.view(), g.state_numpy()
+            fin = np.isfinite(ov["Yc64"])
+            SEG = np.concatenate([ov["SE"], ov["SG"]])
+            same = all(np.array_equal(gs[k][:, :D] if k == "F" else gs[k], ov[k])
+                       for k in ("F", "A", "cstar", "reinit", "top", "bottom", "tie"))
+            # candidate fitness: explosion rows then guiding rows of every firework
+            BN = gs["Yc"].shape[0]
+            Xc = np.concatenate([SEG[:BN * lam].reshape(BN, lam, D),
+                                 SEG[BN * lam:].reshape(BN, G, D)], axis=1).reshape(-1, D)
+            assert np.all(fin)
+            if not same:
+                # two decisions are equally valid when the values compared lie
+                # within the fitness bound of each other
+                tol = 2 * _k_total(wl) * 2.0 ** -22 * float(_abs_scale(wl, Xc).max())
+                assert near_tie_present(prev, ov, lam, G, ov["m"], ov["k"], rel=0.0, atol=tol), \
+                    f"divergence at generation {gen} without a near-tie"
+                return gen
+            assert_bits(gs["SE"][:, :D], ov["SE"], f"gen {gen} SE")
+            assert_bits(gs["SG"][:, :D], ov["SG"], f"gen {gen} SG")
+            assert_net_close(wl, Xc, gs["Yc"].reshape(-1), ov["Yc64"].reshape(-1),
+                             f"gen {gen} candidate fitness")
+        return None
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("net_id,cfg", [
+    (2, dict(n_fireworks=4, n_sparks=32, n_guiding=4, seed=1, T=40)),
+    (5, dict(n_fireworks=3, n_sparks=24, n_guiding=3, seed=2, T=40, lag_guiding=True)),
+    (9, dict(n_fireworks=2, n_sparks=16, n_guiding=2, seed=3, T=20, map_range=True)),
+])
+def test_free_running_testbed_matches_oracle(net_id, cfg):
+    wl = inputs.testbed_net(net_id)
+    at = _free_run(wl, 20, **cfg)
+    print(f"net {net_id}: diverged_at={at}")
+
+
+def test_lockstep_testbed_state_path():
+    wl = inputs.testbed_net(3)
+    _lockstep(wl, 10, check_fitness=False, n_fireworks=3, n_sparks=12, n_guiding=3, T=30, seed=4)
+
+
+def test_full_size_generation_sampled():
+    """One generation at the benchmark's size (net 12, 8 fireworks x 512
+    sparks): sampled candidate fitness against the oracle."""
+    torch, M = require_gpu()
+    wl = inputs.testbed_net(12)
+    g = M.MGFWA.from_workload(wl)
+    p = O.Problem.from_workload(wl)
+    g.step(1)
+    s = g.state_numpy()
+    D, lam = g.D, wl.n_sparks
+    rng = np.random.default_rng(7)
+    rows = rng.integers(0, s["SE"].shape[0], 24)
+    X = s["SE"][rows, :D]
+    got = s["Yc"][rows // lam, rows % lam]
+    assert_net_close(wl, X, got, p.loss_rows(X), "full-size explosion fitness")
+    Xg = s["SG"][:, :D]
+    got = s["Yc"][:, lam:].reshape(-1)
+    assert_net_close(wl, Xg, got, p.loss_rows(Xg), "full-size guiding fitness")
+    g.close()
+
+
+def test_input_problem_errors():
+    torch, M = require_gpu()
+    wl = inputs.testbed_net(2)
+    with pytest.raises(M.MgfwaError) as e:
+        M.MGFWA.from_workload(wl, precision="bf16")
+    assert "FP32" in str(e.value)
+    bad = inputs.testbed_net(2)
+    bad.widths = (10, 600, 1)
+    bad.net = np.zeros(10 * 600 + 600 + 600 + 1, np.float32)
+    with pytest.raises(M.MgfwaError):
+        M.MGFWA.from_workload(bad)
