@@ -31,6 +31,8 @@ WORKLOAD_TAG = {
     "mlp64-128-128-10": "mgfwa-mlp64-128-128-10-relu-ce-gmm4096",
     "mlp784-256-10": "mgfwa-mlp784-256-10-relu-ce-prototypes8192",
 }
+# the paper's testbed (Table 2): input optimisation of a fixed MLP
+WORKLOAD_TAG.update({f"net{i}": f"mgfwa-testbed-net{i}-input-optimisation" for i in range(1, 13)})
 
 
 def parse():
@@ -50,6 +52,8 @@ def parse():
     ap.add_argument("--serving-study", type=int, default=1,
                     help="1: also run a Poisson stream of mixed jobs through the serving loop")
     ap.add_argument("--serve-seconds", type=float, default=8.0, help="arrival window of that study")
+    ap.add_argument("--testbed-study", type=int, default=1,
+                    help="1: the paper's testbed (Table 2 nets, input optimisation), per net")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--calib-copy-mib", type=int, default=256,
                     help="size of a plain device copy run once before the timed region; its "
@@ -362,6 +366,48 @@ def serving_study(seconds, seed, rate=20.0, arena_gib=64, n_streams=4):
                 arena_gib=arena_gib, arena_peak_gib=st["arena_peak"] / 2**30, streams=n_streams)
 
 
+def testbed_study(steps, seed, warmup=3):
+    """The paper's own testbed (Sec. 4.1, eq. (1), Table 2): minimise the output
+    of each fixed random MLP over its input, 8 fireworks x 512 sparks + 8 guiding
+    sparks per generation.  Per net: generation time, candidate evaluations per
+    second, the fused fitness kernel's time and FP32 MFMA rate, and the best
+    output after the timed generations."""
+    import torch
+
+    from paper_2501_03944_amd import inputs
+    from paper_2501_03944_amd import mgfwa as M
+
+    out = {}
+    for net_id in sorted(inputs.TESTBED_NETS):
+        wl = inputs.testbed_net(net_id)
+        g = M.MGFWA.from_workload(wl, seed=seed, max_generations=warmup + steps + 1)
+        g.step(warmup)
+        torch.cuda.synchronize()
+        g.set_timing(True)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(g.stream)
+        g.step(steps)
+        b.record(g.stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        t = g.timing()
+        g.set_timing(False)
+        x, best, gen = g.best()
+        g.close()
+        rows = wl.n_fireworks * wl.n_sparks
+        fit_ms = t["fit_kernel_ms"] / steps
+        tflops = wl.flops_per_eval() * rows / (fit_ms / 1e3) / 1e12
+        out[f"net{net_id}"] = {
+            "d": wl.dim, "widths": f"{wl.widths[0]}-{wl.widths[1]}x{len(wl.widths) - 2}-1",
+            "act": wl.acts[0], "params": wl.n_params,
+            "ms_per_generation": ms,
+            "spark_evals_per_s": g.BN * (wl.n_sparks + wl.n_guiding) / (ms / 1e3),
+            "fit_kernel_ms": fit_ms, "fit_kernel_tflops": tflops,
+            "fit_mfma_pct_fp32_peak": 100.0 * tflops / PEAK_TFLOPS["fp32"],
+            "best_output": best, "generations": gen}
+    return {"fireworks": 8, "sparks": 512, "guiding": 8, "steps": steps, "nets": out}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -387,7 +433,11 @@ def main():
     # reads them packed in its own precision), the samples once
     es = 4 if precision == "fp32" else 2
     wide = args.workload == "mlp784-256-10"
-    alg_bytes = rows * wl.dim * (es if wide else 4) + wl.n_samples * wl.widths[0] * es
+    testbed = getattr(wl, "net", None) is not None
+    if testbed:   # every spark (the network input) once, the fixed parameters once
+        alg_bytes = rows * wl.dim * 4 + wl.n_params * 4
+    else:
+        alg_bytes = rows * wl.dim * (es if wide else 4) + wl.n_samples * wl.widths[0] * es
     line = {
         "metric": METRIC,
         "value": value,
@@ -402,12 +452,14 @@ def main():
         "dtype": "f32" if precision == "fp32" else "bf16",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TAG[args.workload], "fireworks": wl.n_fireworks,
-                   "sparks": wl.n_sparks, "guiding": wl.n_guiding, "samples": wl.n_samples,
+                   "sparks": wl.n_sparks, "guiding": wl.n_guiding,
+                   "samples": 0 if testbed else wl.n_samples,
                    "D": wl.dim, "precision": precision, "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic, "traffic_source": traffic_src,
                      "algorithmic_bytes": alg_bytes,
-                     "kernel": "k_fit (explosion-spark fitness)",
+                     "kernel": ("k_net_input (explosion-spark fitness, fixed network)" if testbed
+                                else "k_fit (explosion-spark fitness)"),
                      "flop_per_launch": flops, "avg_launch_ms": fit_ms},
         "mfma_pct_peak": 100.0 * achieved / peak,
         "gen_latency_ms": {"p50": t["gen_ms_p50"], "p99": t["gen_ms_p99"],
@@ -423,6 +475,8 @@ def main():
         line["serving_study"] = serving_study(args.serve_seconds, args.seed)
     if args.batch_study:
         line["batch_study"] = batch_study(max(2, min(K, 10)), args.seed)
+    if args.testbed_study:
+        line["testbed_study"] = testbed_study(max(2, min(K, 20)), args.seed)
     if args.cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds, args.seed)
     print(json.dumps(line), flush=True)

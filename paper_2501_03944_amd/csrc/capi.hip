@@ -54,7 +54,7 @@ int round_up(int v, int a) { return (v + a - 1) / a * a; }
 struct Layout {
     size_t F, SE, SG, A, Y, Yprev, fresh, Yc, top, bottom, tie, cstar, improved, reinit, src;
     size_t best_x, best_y, best_f, best_gen, best_upd, ctrl, partial, Xp, Xb, Ypad, Lpad;
-    size_t Wpack, Xw, lo, hi, Pnet, total;
+    size_t Wpack, Xw, lo, hi, Pnet, H0, H1, total;
     int partial_rows;
 };
 
@@ -166,6 +166,10 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
         }
         in.n_packed = off;
         in.hs = hmax + 4;   // 16-byte skew between the rows of the activation tile
+        in.hnp = hmax;      // hidden outputs: np[l] = kp[l+1]
+        // MGFWA_NET_PATH=1 / 2 forces the whole-network / layer-by-layer kernels
+        const char *np_env = std::getenv("MGFWA_NET_PATH");
+        in.path = np_env && (np_env[0] == '1' || np_env[0] == '2') ? np_env[0] - '0' : 0;
         D = p->widths[0];
     } else {
         net.nl = p->n_layers;
@@ -265,6 +269,9 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
     L.lo = take(s.map_range ? (size_t)s.B * Dp * 4 : 0);
     L.hi = take(s.map_range ? (size_t)s.B * Dp * 4 : 0);
     L.Pnet = take(input && need_data ? (size_t)in.n_packed * 4 : 0);
+    const size_t hbytes = input && need_data ? (size_t)L.partial_rows * in.hnp * 4 : 0;
+    L.H0 = take(hbytes);
+    L.H1 = take(hbytes);
     L.total = off;
     if (s.lag && L.SG != L.SE + BN * s.lam * Dp * 4)
         return fail(MGFWA_EINVAL, "internal: guiding sparks must follow the explosion sparks");
@@ -343,7 +350,8 @@ mgfwa_status fit_rows(mgfwa_ctx *c, const FitPlan &plan, const float *W, size_t 
                       hipEvent_t pre = nullptr)
 {
     if (c->input) {
-        STEP(launch_net_input(c->in, c->d.Pnet, W, ld, rows, map, out, st), "fitness_input");
+        STEP(launch_net_input(c->in, c->d.Pnet, W, ld, rows, map, out, c->d.H0, c->d.H1, st),
+             "fitness_input");
         if (mid) STEP(hipEventRecord(mid, st), "event");
     } else if (c->net.wide)
         STEP(launch_fitness_wide(c->net, c->d, W, ld, rows, map, out, st, mid, pre), "fitness_wide");
@@ -551,6 +559,8 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
     d.lo = c->s.map_range ? at<float>(b, L.lo) : nullptr;
     d.hi = c->s.map_range ? at<float>(b, L.hi) : nullptr;
     d.Pnet = c->input && has_data ? at<float>(b, L.Pnet) : nullptr;
+    d.H0 = c->input && has_data ? at<float>(b, L.H0) : nullptr;
+    d.H1 = c->input && has_data ? at<float>(b, L.H1) : nullptr;
 
     auto bail = [&](mgfwa_status st) {
         mgfwa_destroy(c);
@@ -724,9 +734,9 @@ mgfwa_status mgfwa_evaluate(mgfwa_ctx *c, const float *w, int rows, int ld, floa
     if (rows < 0 || (rows > 0 && (!w || !out))) return fail(MGFWA_EINVAL, "bad rows/buffers");
     if (ld < c->s.D || ld % 4 != 0 || reinterpret_cast<uintptr_t>(w) % 16 != 0)
         return fail(MGFWA_EINVAL, "ld must be >= D and a multiple of 4; w 16-byte aligned");
-    // the weights-problem kernels stage per-row partial sums in a buffer of
-    // partial_rows rows; the input-problem kernel needs none
-    const int chunk = c->input ? std::max(rows, 1) : c->lay.partial_rows;
+    // the kernels stage per-row partial sums (weights problems) or activations
+    // (input problems) in buffers of partial_rows rows
+    const int chunk = c->lay.partial_rows;
     for (int r0 = 0; r0 < rows; r0 += chunk) {
         const int nr = std::min(chunk, rows - r0);
         FitPlan plan{};

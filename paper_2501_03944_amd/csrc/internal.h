@@ -40,6 +40,7 @@ struct DevState {
     char *Xw;          // [S_pad][Kp] samples with a ones column (wide kernel)
     float *lo, *hi;    // [B][Dp] population ranges (range mapping)
     float *Pnet;       // packed parameters of a fixed network (input problems)
+    float *H0, *H1;    // [partial_rows][hnp] activations between layers (input problems)
 };
 
 // Population shape and algorithm constants as the kernels need them.
@@ -85,7 +86,9 @@ struct InNet {
     int woff[NET_MAXL], boff[NET_MAXL];// float offsets into the packed parameters
     int n_packed;                      // floats of the packed parameters
     int hs;                            // LDS row pitch (floats) of the activation tile
+    int hnp;                           // widest hidden output (padded): activation row pitch
     int num_cu;                        // compute units (rows per block choice)
+    int path;                          // 0 choose per launch, 1 whole-network tiles, 2 layer by layer
 };
 
 // A chosen fitness kernel and its launch geometry for a given row count.
@@ -143,9 +146,11 @@ int resident_lds_bytes(const Net &net);
 // ---- net_input.hip (input problems)
 // Pack the caller's nn.Linear-layout parameters into the padded blocks.
 hipError_t launch_pack_net(const InNet &net, const float *params, float *packed, hipStream_t st);
-// out[map.index(r)] = f(x_r) for the rows of X (leading dimension ld >= fi[0]).
+// out[map.index(r)] = f(x_r) for the rows of X (leading dimension ld >= fi[0]);
+// the layer-by-layer path keeps the activations in H0/H1 ([rows][hnp] each).
 hipError_t launch_net_input(const InNet &net, const float *packed, const float *X, size_t ld,
-                            int rows, OutMap map, float *out, hipStream_t st);
+                            int rows, OutMap map, float *out, float *H0, float *H1,
+                            hipStream_t st);
 size_t net_input_lds_bytes(const InNet &net);
 hipError_t net_input_prepare(const InNet &net);   // raises the kernels' LDS limit
 

@@ -15,6 +15,16 @@
 //   * the products run on v_mfma_f32_16x16x4_f32 (FP32 in, FP32 accumulate):
 //     each wave owns the 16-column blocks j = wave, wave + 8, ... of a layer's
 //     output and all 16*RB rows.
+// Wide networks (hidden width above 128), and launches with too few rows to
+// give every compute unit a tile, run layer by layer instead (k_net_layer): one
+// launch per layer over a 2-D grid of output tiles, the activations between
+// layers in a [rows][hnp] buffer (L2-resident at these sizes).  Many rows: each
+// wave computes a 32 x 64 tile (4 waves per block, 64 x 128 per block), which
+// halves the weight traffic per product against the 16-row whole-network tile.
+// Few rows: the 4 waves of a block split the K range of one 16 x 16 tile and
+// add their partial sums in LDS (in wave order), so that a 64-row launch still
+// spreads each layer over np/16 x rows/16 blocks.
+//
 // Fragment layout (one 16-wide K chunk, lane = 16 q + c): the lane holds rows
 // (or output columns) c and the K range 4q..4q+3 of the chunk as one float4;
 // MFMA e of the chunk takes element e, so the four MFMAs together cover the 16
@@ -172,6 +182,152 @@ __global__ __launch_bounds__(TPB) void k_pack_net(InNet net, const float *__rest
 template <int RB>
 size_t lds_bytes_rb(const InNet &net) { return (size_t)16 * RB * net.hs * sizeof(float); }
 
+struct LayerArgs {
+    const float *A;       // layer input rows (the sparks for layer 0)
+    size_t lda;
+    int a_cols;           // readable columns of A: the input width for layer 0, K otherwise
+    const float *W;       // [np][K] packed weights of the layer
+    const float *bias;    // [np]
+    int K, np;
+    float *H;             // hidden layers: [rows][ldh] outputs
+    int ldh;
+    int act, last, rows;
+    OutMap map;           // last layer: where row r's output goes
+    float *out;
+};
+
+__device__ __forceinline__ float4 load_a(const float *row, int k, int cols)
+{
+    if (k + 4 <= cols) return *reinterpret_cast<const float4 *>(row + k);
+    return make_float4(k < cols ? row[k] : 0.0f, k + 1 < cols ? row[k + 1] : 0.0f,
+                       k + 2 < cols ? row[k + 2] : 0.0f, k + 3 < cols ? row[k + 3] : 0.0f);
+}
+
+// One layer over a tile grid (blockIdx.x: row tiles, blockIdx.y: column tiles).
+// KS = 1: waves 2 x 2 over (rows, columns), each a (16 RBW) x (16 CBW) tile.
+// KS = 4: the 4 waves share one tile and take every 4th K chunk each.
+template <int RBW, int CBW, int KS>
+__global__ __launch_bounds__(256) void k_net_layer(LayerArgs a)
+{
+    constexpr int RED = KS > 1 ? KS * RBW * CBW * 64 : 1;
+    __shared__ floatx4 red[RED];   // [KS][RBW][CBW][64] partial tiles
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = lane & 15, q = lane >> 4;
+    int row0, col0, kfirst;
+    if constexpr (KS == 1) {
+        row0 = (blockIdx.x * 2 + (wave >> 1)) * 16 * RBW;
+        col0 = (blockIdx.y * 2 + (wave & 1)) * 16 * CBW;
+        kfirst = 0;
+    } else {
+        row0 = blockIdx.x * 16 * RBW;
+        col0 = blockIdx.y * 16 * CBW;
+        kfirst = wave * 16;
+    }
+    const float *ar[RBW];
+#pragma unroll
+    for (int rb = 0; rb < RBW; ++rb) {
+        const int r = row0 + 16 * rb + c;   // rows past the end repeat the last row
+        ar[rb] = a.A + (size_t)(r < a.rows ? r : a.rows - 1) * a.lda;
+    }
+    // weight rows past np (the one-output last layer) read row 0 and are
+    // multiplied like the others; their results are not stored
+    const float *wr[CBW];
+    bool on[CBW];
+#pragma unroll
+    for (int cb = 0; cb < CBW; ++cb) {
+        on[cb] = col0 + 16 * cb < a.np;     // uniform over the wave
+        wr[cb] = a.W + (size_t)(on[cb] ? col0 + 16 * cb + c : 0) * a.K;
+    }
+    floatx4 acc[RBW][CBW];
+#pragma unroll
+    for (int rb = 0; rb < RBW; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CBW; ++cb) acc[rb][cb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    constexpr int KSTEP = 16 * KS;
+    // chunks whose 16 inputs all lie inside the readable columns run without
+    // guards, software-pipelined one chunk deep; a partial last chunk of the
+    // input layer follows with guarded loads
+    const int kfull = a.a_cols < a.K ? a.a_cols / 16 * 16 : a.K;
+    if (row0 < a.rows) {
+        float4 av[RBW], bv[CBW];
+        auto fetch = [&](int kc, float4 (&ra)[RBW], float4 (&rw)[CBW]) {
+            const int k = kc + 4 * q;
+#pragma unroll
+            for (int rb = 0; rb < RBW; ++rb) ra[rb] = *reinterpret_cast<const float4 *>(ar[rb] + k);
+#pragma unroll
+            for (int cb = 0; cb < CBW; ++cb) rw[cb] = *reinterpret_cast<const float4 *>(wr[cb] + k);
+        };
+        int kc = kfirst;
+        if (kc < kfull) {
+            fetch(kc, av, bv);
+            for (; kc + KSTEP < kfull; kc += KSTEP) {
+                float4 an[RBW], bn[CBW];
+                fetch(kc + KSTEP, an, bn);
+#pragma unroll
+                for (int cb = 0; cb < CBW; ++cb)
+#pragma unroll
+                    for (int rb = 0; rb < RBW; ++rb) mfma4(acc[rb][cb], av[rb], bv[cb]);
+#pragma unroll
+                for (int rb = 0; rb < RBW; ++rb) av[rb] = an[rb];
+#pragma unroll
+                for (int cb = 0; cb < CBW; ++cb) bv[cb] = bn[cb];
+            }
+#pragma unroll
+            for (int cb = 0; cb < CBW; ++cb)
+#pragma unroll
+                for (int rb = 0; rb < RBW; ++rb) mfma4(acc[rb][cb], av[rb], bv[cb]);
+            kc += KSTEP;
+        }
+        for (; kc < a.K; kc += KSTEP) {   // at most one chunk: the input's partial tail
+            const int k = kc + 4 * q;
+#pragma unroll
+            for (int rb = 0; rb < RBW; ++rb) av[rb] = load_a(ar[rb], k, a.a_cols);
+#pragma unroll
+            for (int cb = 0; cb < CBW; ++cb) bv[cb] = *reinterpret_cast<const float4 *>(wr[cb] + k);
+#pragma unroll
+            for (int cb = 0; cb < CBW; ++cb)
+#pragma unroll
+                for (int rb = 0; rb < RBW; ++rb) mfma4(acc[rb][cb], av[rb], bv[cb]);
+        }
+    }
+    if constexpr (KS > 1) {
+        // partial sums of the K slices, added in wave order
+#pragma unroll
+        for (int rb = 0; rb < RBW; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < CBW; ++cb) red[((wave * RBW + rb) * CBW + cb) * 64 + lane] = acc[rb][cb];
+        __syncthreads();
+        if (wave != 0) return;
+#pragma unroll
+        for (int rb = 0; rb < RBW; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < CBW; ++cb) {
+                floatx4 t = red[(rb * CBW + cb) * 64 + lane];
+#pragma unroll
+                for (int w = 1; w < KS; ++w) t += red[((w * RBW + rb) * CBW + cb) * 64 + lane];
+                acc[rb][cb] = t;
+            }
+    }
+#pragma unroll
+    for (int cb = 0; cb < CBW; ++cb) {
+        if (!on[cb]) continue;
+        const int col = col0 + 16 * cb + c;
+        const float bv = a.bias[col];
+#pragma unroll
+        for (int rb = 0; rb < RBW; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = row0 + 16 * rb + 4 * q + v;
+                if (row >= a.rows) continue;
+                const float z = acc[rb][cb][v] + bv;
+                if (!a.last)
+                    a.H[(size_t)row * a.ldh + col] = ni_act(a.act, z);
+                else if (col == 0)
+                    a.out[a.map.index(row)] = canon_fitness(z);
+            }
+    }
+}
+
 }  // namespace
 
 size_t net_input_lds_bytes(const InNet &net) { return lds_bytes_rb<2>(net); }
@@ -194,12 +350,58 @@ hipError_t net_input_prepare(const InNet &net)
     return e;
 }
 
+namespace {
+
+// Layer-by-layer evaluation: the largest tiles that still give every compute
+// unit a block of the widest layer; K-split 16 x 16 tiles when even 32 x 32
+// tiles do not.
+hipError_t launch_layers(const InNet &net, const float *P, const float *X, size_t ld, int rows,
+                         OutMap map, float *out, float *H0, float *H1, hipStream_t st, long cu)
+{
+    auto tiles = [&](int bm, int bn) { return (long)((rows + bm - 1) / bm) * ((net.hnp + bn - 1) / bn); };
+    const int shape = tiles(64, 128) >= cu ? 0 : tiles(64, 64) >= cu ? 1 : tiles(32, 32) >= cu ? 2 : 3;
+    const float *A = X;
+    size_t lda = ld;
+    int a_cols = net.fi[0];
+    for (int l = 0; l < net.nl; ++l) {
+        float *H = (l & 1) ? H1 : H0;
+        LayerArgs a{A, lda, a_cols, P + net.woff[l], P + net.boff[l], net.kp[l], net.np[l],
+                    H, net.hnp, net.act[l], l == net.nl - 1, rows, map, out};
+        const int np = net.np[l];
+        if (shape == 0) {
+            hipLaunchKernelGGL((k_net_layer<2, 4, 1>), dim3((rows + 63) / 64, (np + 127) / 128),
+                               dim3(256), 0, st, a);
+        } else if (shape == 1) {
+            hipLaunchKernelGGL((k_net_layer<2, 2, 1>), dim3((rows + 63) / 64, (np + 63) / 64),
+                               dim3(256), 0, st, a);
+        } else if (shape == 2) {
+            hipLaunchKernelGGL((k_net_layer<1, 1, 1>), dim3((rows + 31) / 32, (np + 31) / 32),
+                               dim3(256), 0, st, a);
+        } else {
+            hipLaunchKernelGGL((k_net_layer<1, 1, 4>), dim3((rows + 15) / 16, np / 16), dim3(256),
+                               0, st, a);
+        }
+        A = H;
+        lda = net.hnp;
+        a_cols = net.np[l];
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_net_input(const InNet &net, const float *packed, const float *X, size_t ld,
-                            int rows, OutMap map, float *out, hipStream_t st)
+                            int rows, OutMap map, float *out, float *H0, float *H1,
+                            hipStream_t st)
 {
     if (rows <= 0) return hipSuccess;
-    // the most rows per block that still gives every compute unit a block
     const long cu = net.num_cu > 0 ? net.num_cu : 256;
+    // whole-network tiles for narrow networks with a tile for every compute
+    // unit; layer by layer otherwise
+    const bool whole = net.path == 1 ||
+                       (net.path == 0 && net.hnp <= 128 && (rows + 15) / 16 >= cu / 2);
+    if (!whole) return launch_layers(net, packed, X, ld, rows, map, out, H0, H1, st, cu);
+    // the most rows per block that still gives every compute unit a block
     const dim3 block(NI_NW * 64);
     if (rows >= 32 * cu) {
         hipLaunchKernelGGL(k_net_input<2>, dim3((rows + 31) / 32), block, lds_bytes_rb<2>(net), st,

@@ -257,6 +257,8 @@ def workload(name: str, **overrides) -> Workload:
         return gaussian_mixture(**overrides)
     if name in ("mlp784-256-10", "prototypes"):
         return sparse_prototypes(**overrides)
+    if name.startswith("net") and name[3:].isdigit() and int(name[3:]) in TESTBED_NETS:
+        return testbed_net(int(name[3:]), **overrides)
     raise KeyError(name)
 
 
