@@ -282,6 +282,9 @@ typedef struct {
     int samples_per_block;
     int lds_bytes;
     int row_blocks[4];      /* 16-row MFMA blocks per layer (padded widths / 16) */
+    int net_kernel;         /* input problems: 0..3 layer by layer with 64x128, 64x64, 32x32
+                               or K-split 16x16 output tiles, 4 whole-network 16/32-row tiles,
+                               -1 chosen per launch from the shape (before autotuning) */
 } mgfwa_plan_info;
 
 MGFWA_API mgfwa_status mgfwa_fit_plan(const mgfwa_ctx *ctx, int which, mgfwa_plan_info *info);
@@ -295,7 +298,8 @@ MGFWA_API mgfwa_status mgfwa_fit_plan(const mgfwa_ctx *ctx, int which, mgfwa_pla
  * so a job's fitness values (whose summation order follows the launch shape)
  * depend only on its shape, alone or in a batch.  Call before the first
  * generation (ESTATE otherwise).  Contexts on the wide kernel keep their fixed
- * tiles (OK, nothing changes).  Synchronises the stream.
+ * tiles (OK, nothing changes).  Input problems time their kernels' tile shapes
+ * (net_kernel of mgfwa_plan_info).  Synchronises the stream.
  */
 MGFWA_API mgfwa_status mgfwa_autotune(mgfwa_ctx *ctx, int reps);
 

@@ -350,7 +350,8 @@ mgfwa_status fit_rows(mgfwa_ctx *c, const FitPlan &plan, const float *W, size_t 
                       hipEvent_t pre = nullptr)
 {
     if (c->input) {
-        STEP(launch_net_input(c->in, c->d.Pnet, W, ld, rows, map, out, c->d.H0, c->d.H1, st),
+        STEP(launch_net_input(c->in, plan.net_shape, c->d.Pnet, W, ld, rows, map, out, c->d.H0,
+                              c->d.H1, st),
              "fitness_input");
         if (mid) STEP(hipEventRecord(mid, st), "event");
     } else if (c->net.wide)
@@ -867,11 +868,35 @@ std::string tune_key(const Net &net, int rows)
     return k;
 }
 
+std::string tune_key_input(const InNet &in, int rows)
+{
+    std::string k = "in r" + std::to_string(rows);
+    for (int l = 0; l < in.nl; ++l)
+        k += " " + std::to_string(in.fi[l]) + "x" + std::to_string(in.fo[l]) + "a" +
+             std::to_string(in.act[l]);
+    return k;
+}
+
+// Candidate launches of a problem: the compiled fitness kernels that cover the
+// weights problem's shape, or the tile shapes of the input problem's kernels.
+int tune_candidates(const mgfwa_ctx *c, int rows, FitPlan *cand, int max_out)
+{
+    if (!c->input) return fit_candidates(c->net, rows, cand, max_out);
+    int n = 0;
+    for (int shape = 0; shape <= NET_WHOLE && n < max_out; ++shape) {
+        cand[n] = FitPlan{};
+        cand[n].rows = rows;
+        cand[n].net_shape = shape;
+        ++n;
+    }
+    return n;
+}
+
 // Time every candidate plan for `rows` sparks of W on the context's stream and
 // keep the fastest; a shape seen before reuses its choice without timing.
 mgfwa_status tune_plan(mgfwa_ctx *c, int rows, const float *W, OutMap map, int reps, FitPlan *out)
 {
-    const std::string key = tune_key(c->net, rows);
+    const std::string key = c->input ? tune_key_input(c->in, rows) : tune_key(c->net, rows);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
@@ -882,7 +907,7 @@ mgfwa_status tune_plan(mgfwa_ctx *c, int rows, const float *W, OutMap map, int r
         }
     }
     FitPlan cand[64];
-    const int n = fit_candidates(c->net, rows, cand, 64);
+    const int n = tune_candidates(c, rows, cand, 64);
     if (n == 0) return fail(MGFWA_EUNSUPPORTED, "no compiled fitness kernel covers this MLP shape");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
@@ -895,7 +920,10 @@ mgfwa_status tune_plan(mgfwa_ctx *c, int rows, const float *W, OutMap map, int r
         for (int k = 0; k <= reps && e == hipSuccess; ++k) {
             if (k == 1) e = hipEventRecord(e0, c->stream);
             if (e == hipSuccess)
-                e = launch_fitness(c->net, cand[i], c->d, W, c->s.Dp, rows, map, c->d.Yc, c->stream);
+                e = c->input ? launch_net_input(c->in, cand[i].net_shape, c->d.Pnet, W, c->s.Dp, rows,
+                                                map, c->d.Yc, c->d.H0, c->d.H1, c->stream)
+                             : launch_fitness(c->net, cand[i], c->d, W, c->s.Dp, rows, map, c->d.Yc,
+                                              c->stream);
         }
         if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -1001,7 +1029,7 @@ mgfwa_status mgfwa_autotune(mgfwa_ctx *c, int reps)
         return fail(MGFWA_ESTATE, "autotuning needs the built-in fitness");
     if (c->phase != PH_READY || c->gen_host != 0 || c->gexec)
         return fail(MGFWA_ESTATE, "autotune before the first generation");
-    if (c->net.wide || c->input) return MGFWA_OK;   // one fixed tile shape
+    if (c->net.wide) return MGFWA_OK;   // one fixed tile shape
     const Shape &s = c->s;
     mgfwa_status r = tune_plan(c, s.BN * expl_rows(s), c->d.SE, expl_map(s), reps, &c->plan_expl);
     if (r) return r;
@@ -1016,6 +1044,7 @@ mgfwa_status mgfwa_fit_plan(const mgfwa_ctx *c, int which, mgfwa_plan_info *info
     std::memset(info, 0, sizeof *info);
     info->wide = c->net.wide ? 1 : 0;
     info->rows = which == 0 ? c->s.BN * expl_rows(c->s) : c->s.BN * c->s.G;
+    info->net_kernel = c->input ? p.net_shape : -1;
     if (!c->net.wide && !c->input) {
         info->wavefronts = p.nw;
         info->slabs = p.P;

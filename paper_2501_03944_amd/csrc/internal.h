@@ -103,6 +103,7 @@ struct FitPlan {
     // LDS layout of the staged weights (wl = 1)
     int lw[MAXL], lpitch[MAXL], lrows[MAXL], lcols[MAXL], lb[MAXL];
     int lbias_byte, lds_bytes;
+    int net_shape = -1;   // input problems: NET_* kernel shape (-1 chosen per launch)
 };
 
 // ---- spark.hip
@@ -148,8 +149,11 @@ int resident_lds_bytes(const Net &net);
 hipError_t launch_pack_net(const InNet &net, const float *params, float *packed, hipStream_t st);
 // out[map.index(r)] = f(x_r) for the rows of X (leading dimension ld >= fi[0]);
 // the layer-by-layer path keeps the activations in H0/H1 ([rows][hnp] each).
-hipError_t launch_net_input(const InNet &net, const float *packed, const float *X, size_t ld,
-                            int rows, OutMap map, float *out, float *H0, float *H1,
+// shape: 0..3 layer by layer with 64x128, 64x64, 32x32 or K-split 16x16 tiles,
+// NET_WHOLE the whole-network tiles, -1 a choice from the shape and row count.
+constexpr int NET_WHOLE = 4;
+hipError_t launch_net_input(const InNet &net, int shape, const float *packed, const float *X,
+                            size_t ld, int rows, OutMap map, float *out, float *H0, float *H1,
                             hipStream_t st);
 size_t net_input_lds_bytes(const InNet &net);
 hipError_t net_input_prepare(const InNet &net);   // raises the kernels' LDS limit

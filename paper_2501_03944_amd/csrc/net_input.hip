@@ -245,8 +245,8 @@ __global__ __launch_bounds__(256) void k_net_layer(LayerArgs a)
         for (int cb = 0; cb < CBW; ++cb) acc[rb][cb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
     constexpr int KSTEP = 16 * KS;
     // chunks whose 16 inputs all lie inside the readable columns run without
-    // guards, software-pipelined one chunk deep; a partial last chunk of the
-    // input layer follows with guarded loads
+    // guards and software-pipelined; a partial last chunk of the input layer
+    // follows with guarded loads
     const int kfull = a.a_cols < a.K ? a.a_cols / 16 * 16 : a.K;
     if (row0 < a.rows) {
         float4 av[RBW], bv[CBW];
@@ -257,26 +257,38 @@ __global__ __launch_bounds__(256) void k_net_layer(LayerArgs a)
 #pragma unroll
             for (int cb = 0; cb < CBW; ++cb) rw[cb] = *reinterpret_cast<const float4 *>(wr[cb] + k);
         };
-        int kc = kfirst;
-        if (kc < kfull) {
-            fetch(kc, av, bv);
-            for (; kc + KSTEP < kfull; kc += KSTEP) {
-                float4 an[RBW], bn[CBW];
-                fetch(kc + KSTEP, an, bn);
-#pragma unroll
-                for (int cb = 0; cb < CBW; ++cb)
-#pragma unroll
-                    for (int rb = 0; rb < RBW; ++rb) mfma4(acc[rb][cb], av[rb], bv[cb]);
-#pragma unroll
-                for (int rb = 0; rb < RBW; ++rb) av[rb] = an[rb];
-#pragma unroll
-                for (int cb = 0; cb < CBW; ++cb) bv[cb] = bn[cb];
-            }
+        auto multiply = [&](const float4 (&ra)[RBW], const float4 (&rw)[CBW]) {
 #pragma unroll
             for (int cb = 0; cb < CBW; ++cb)
 #pragma unroll
-                for (int rb = 0; rb < RBW; ++rb) mfma4(acc[rb][cb], av[rb], bv[cb]);
-            kc += KSTEP;
+                for (int rb = 0; rb < RBW; ++rb) mfma4(acc[rb][cb], ra[rb], rw[cb]);
+        };
+        // two register sets take turns, so that no loaded value is copied and
+        // the loads of the next two chunks stay in flight during a multiply;
+        // fetches past the last chunk repeat it (they are never multiplied)
+        const int n = kfirst < kfull ? (kfull - kfirst + KSTEP - 1) / KSTEP : 0;
+        int kc = kfirst + n * KSTEP;
+        if (n > 0) {
+            const int klast = kfirst + (n - 1) * KSTEP;
+            float4 a1[RBW], b1[CBW];
+            fetch(kfirst, av, bv);
+            fetch(min(kfirst + KSTEP, klast), a1, b1);
+            int i = 0;
+            for (; i + 2 <= n; i += 2) {
+                const int k = kfirst + i * KSTEP;
+                // the scheduling barriers keep each set's refill behind its
+                // multiply and ahead of the other set's, so the waits before a
+                // multiply leave the other set's loads outstanding
+                multiply(av, bv);
+                __builtin_amdgcn_sched_barrier(0);
+                fetch(min(k + 2 * KSTEP, klast), av, bv);
+                __builtin_amdgcn_sched_barrier(0);
+                multiply(a1, b1);
+                __builtin_amdgcn_sched_barrier(0);
+                fetch(min(k + 3 * KSTEP, klast), a1, b1);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (i < n) multiply(av, bv);   // an odd count ends in the first set
         }
         for (; kc < a.K; kc += KSTEP) {   // at most one chunk: the input's partial tail
             const int k = kc + 4 * q;
@@ -355,11 +367,20 @@ namespace {
 // Layer-by-layer evaluation: the largest tiles that still give every compute
 // unit a block of the widest layer; K-split 16 x 16 tiles when even 32 x 32
 // tiles do not.
-hipError_t launch_layers(const InNet &net, const float *P, const float *X, size_t ld, int rows,
-                         OutMap map, float *out, float *H0, float *H1, hipStream_t st, long cu)
+int auto_shape(const InNet &net, int rows, long cu)
 {
+    // whole-network tiles for narrow networks with a tile for every other
+    // compute unit; otherwise layer by layer with the largest tiles that still
+    // give every compute unit a block of the widest layer
+    if (net.path == 1 || (net.path == 0 && net.hnp <= 128 && (rows + 15) / 16 >= cu / 2))
+        return NET_WHOLE;
     auto tiles = [&](int bm, int bn) { return (long)((rows + bm - 1) / bm) * ((net.hnp + bn - 1) / bn); };
-    const int shape = tiles(64, 128) >= cu ? 0 : tiles(64, 64) >= cu ? 1 : tiles(32, 32) >= cu ? 2 : 3;
+    return tiles(64, 128) >= cu ? 0 : tiles(64, 64) >= cu ? 1 : tiles(32, 32) >= cu ? 2 : 3;
+}
+
+hipError_t launch_layers(const InNet &net, int shape, const float *P, const float *X, size_t ld,
+                         int rows, OutMap map, float *out, float *H0, float *H1, hipStream_t st)
+{
     const float *A = X;
     size_t lda = ld;
     int a_cols = net.fi[0];
@@ -390,17 +411,15 @@ hipError_t launch_layers(const InNet &net, const float *P, const float *X, size_
 
 }  // namespace
 
-hipError_t launch_net_input(const InNet &net, const float *packed, const float *X, size_t ld,
-                            int rows, OutMap map, float *out, float *H0, float *H1,
+hipError_t launch_net_input(const InNet &net, int shape, const float *packed, const float *X,
+                            size_t ld, int rows, OutMap map, float *out, float *H0, float *H1,
                             hipStream_t st)
 {
     if (rows <= 0) return hipSuccess;
     const long cu = net.num_cu > 0 ? net.num_cu : 256;
-    // whole-network tiles for narrow networks with a tile for every compute
-    // unit; layer by layer otherwise
-    const bool whole = net.path == 1 ||
-                       (net.path == 0 && net.hnp <= 128 && (rows + 15) / 16 >= cu / 2);
-    if (!whole) return launch_layers(net, packed, X, ld, rows, map, out, H0, H1, st, cu);
+    if (shape < 0 || shape > NET_WHOLE) shape = auto_shape(net, rows, cu);
+    if (shape != NET_WHOLE)
+        return launch_layers(net, shape, packed, X, ld, rows, map, out, H0, H1, st);
     // the most rows per block that still gives every compute unit a block
     const dim3 block(NI_NW * 64);
     if (rows >= 32 * cu) {

@@ -84,7 +84,7 @@ class mgfwa_plan_info(C.Structure):
     _fields_ = [("wide", C.c_int), ("rows", C.c_int), ("wavefronts", C.c_int), ("slabs", C.c_int),
                 ("lds_weights", C.c_int), ("blocks_per_row", C.c_int),
                 ("samples_per_block", C.c_int), ("lds_bytes", C.c_int),
-                ("row_blocks", C.c_int * 4)]
+                ("row_blocks", C.c_int * 4), ("net_kernel", C.c_int)]
 
 
 class MgfwaError(RuntimeError):

@@ -225,6 +225,33 @@ def test_full_size_generation_sampled():
     g.close()
 
 
+def test_autotuned_input_problem_matches_oracle():
+    """The autotuner picks a tile shape per launch size; the tuned generation
+    still agrees with the oracle."""
+    torch, M = require_gpu()
+    wl = inputs.testbed_net(10)
+    g = M.MGFWA.from_workload(wl, n_fireworks=4, n_sparks=256, n_guiding=4, seed=3)
+    assert g.fit_plan(0)["net_kernel"] == -1
+    g.autotune(2)
+    k0, k1 = g.fit_plan(0)["net_kernel"], g.fit_plan(1)["net_kernel"]
+    assert 0 <= k0 <= 4 and 0 <= k1 <= 4
+    print(f"tuned kernels: explosion {k0}, guiding {k1}")
+    p = O.Problem.from_workload(wl)
+    o = O.Oracle(p, N=4, lam=256, G=4, lb=wl.lb, ub=wl.ub, T=wl.generations, seed=3)
+    o.init()
+    o.generation()
+    g.step(1)
+    s, v = g.state_numpy(), o.view()
+    D = g.D
+    assert_bits(s["SE"][:, :D], v["SE"], "tuned generation SE")
+    idx = np.random.default_rng(1).integers(0, 4 * 256, 40)
+    assert_net_close(wl, v["SE"][idx], s["Yc"][idx // 256, idx % 256], v["Yc64"][idx // 256, idx % 256],
+                     "tuned explosion fitness")
+    assert_net_close(wl, v["SG"], s["Yc"][:, 256:].reshape(-1), v["Yc64"][:, 256:].reshape(-1),
+                     "tuned guiding fitness")
+    g.close()
+
+
 def test_input_problem_errors():
     torch, M = require_gpu()
     wl = inputs.testbed_net(2)
