@@ -1,9 +1,12 @@
 // Multi-guiding sparks (Alg. 1: generate the multi-guiding sparks, then their
 // random mapping).
 //
-// k_rank  -- one block per firework: ranks the members of every guiding group
-//            by (fitness key, spark index), writes the top-k and bottom-k member
-//            lists in ascending spark index and the all-tie flag.
+// k_rank  -- ranks the members of every guiding group by (fitness key, spark
+//            index), writes the top-k and bottom-k member lists in ascending
+//            spark index and the all-tie flag.  Groups of up to 64 members: one
+//            wavefront per group, one lane per member (keys broadcast by lane
+//            shuffles, list positions from ballots); larger groups: one block
+//            per firework over LDS.
 // k_guide -- grid over (group, 4-coordinate chunk): the guiding vector is
 //            (sum of top sparks - sum of bottom sparks) * (1/k), each sum taken
 //            in ascending spark index (zero when the group ties); the guiding
@@ -76,6 +79,52 @@ __global__ __launch_bounds__(TPB) void k_rank(const float *__restrict__ Yc, int 
     }
 }
 
+// m <= 64: wavefront w of a block ranks group blockIdx.x * (TPB / 64) + w.
+__global__ __launch_bounds__(TPB) void k_rank_wave(const float *__restrict__ Yc, int C, int G,
+                                                   int m, int k, int groups,
+                                                   int32_t *__restrict__ top,
+                                                   int32_t *__restrict__ bottom,
+                                                   int32_t *__restrict__ tie,
+                                                   const int32_t *__restrict__ ctrl, int lag)
+{
+    if (ctrl[CTRL_DONE]) return;
+    const int lane = threadIdx.x & 63;
+    const int gi = blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);   // gf * G + g
+    if (gi >= groups) return;
+    const int gf = gi / G, g = gi % G;
+    const size_t base = (size_t)gi * k;
+    if (lag && ctrl[CTRL_GEN] == 0) {
+        // lagged guiding before any explosion: every guiding vector is zero
+        if (lane < k) {
+            top[base + lane] = g * m + lane;
+            bottom[base + lane] = g * m + m - k + lane;
+        }
+        if (lane == 0) tie[gi] = 1;
+        return;
+    }
+    const bool in = lane < m;
+    const uint32_t kj = in ? fit_key(Yc[(size_t)gf * C + g * m + lane]) : 0xffffffffu;
+    int r = 0;
+    for (int i = 0; i < m; ++i) {
+        const uint32_t ki = (uint32_t)__shfl((int)kj, i);
+        r += (ki < kj) || (ki == kj && i < lane);
+    }
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const bool is_top = in && r < k, is_bottom = in && r >= m - k;
+    const uint64_t tmask = __ballot(is_top), bmask = __ballot(is_bottom);
+    if (is_top) top[base + __popcll(tmask & below)] = g * m + lane;
+    if (is_bottom) bottom[base + __popcll(bmask & below)] = g * m + lane;
+    // the group ties iff its first and last ranked members share a key, i.e.
+    // iff its smallest and largest keys are equal
+    uint32_t lo = in ? kj : 0xffffffffu, hi = in ? kj : 0u;
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t l2 = (uint32_t)__shfl_xor((int)lo, off), h2 = (uint32_t)__shfl_xor((int)hi, off);
+        lo = l2 < lo ? l2 : lo;
+        hi = h2 > hi ? h2 : hi;
+    }
+    if (lane == 0) tie[gi] = lo == hi;
+}
+
 __global__ __launch_bounds__(TPB) void k_guide(const float *__restrict__ F,
                                                const float *__restrict__ SE,
                                                float *__restrict__ SG,
@@ -138,6 +187,12 @@ __global__ __launch_bounds__(TPB) void k_guide(const float *__restrict__ F,
 
 hipError_t launch_rank(const Shape &s, const DevState &d, hipStream_t st)
 {
+    if (s.m <= 64) {
+        const int groups = s.BN * s.G, per = TPB / 64;
+        hipLaunchKernelGGL(k_rank_wave, dim3((groups + per - 1) / per), dim3(TPB), 0, st, d.Yc, s.C,
+                           s.G, s.m, s.k, groups, d.top, d.bottom, d.tie, d.ctrl, s.lag);
+        return hipGetLastError();
+    }
     const size_t shmem = (size_t)s.lam * 8;
     hipLaunchKernelGGL(k_rank, dim3(s.BN), dim3(TPB), shmem, st, d.Yc, s.C, s.lam, s.G, s.m, s.k,
                        d.top, d.bottom, d.tie, d.ctrl, s.lag);
