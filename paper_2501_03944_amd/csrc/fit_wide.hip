@@ -20,24 +20,32 @@ constexpr int MAX_GRID_Y = 65535;
 //                        p(g, e) = 4g + e (e < 4) or 16 + 4g + e - 4 (e >= 4);
 //                        FP32: natural order
 //   b2     [16]          FP32
+constexpr int PACK_CPT = 4;   // 16-byte chunks per thread (strided by the block)
+constexpr int PACK_RPB = 4;   // spark rows per block
+
+// One 16-byte output chunk of a packed row (see the layout above).
 template <bool BF>
-__global__ __launch_bounds__(TPB) void k_pack_wide_rows(const float *__restrict__ W, size_t ld,
-                                                        int rows, char *__restrict__ Wp, size_t pr,
-                                                        int in, int hid, int out, int Kp, int woff1,
-                                                        int boff1, int woff2, int boff2)
+__device__ __forceinline__ void pack_chunk(const float *__restrict__ w, char *__restrict__ wp,
+                                           int chunk, int c1, int c2, int in, int hid, int out,
+                                           int woff1, int boff1, int woff2, int boff2)
 {
     constexpr int ES = BF ? 2 : 4, EPC = 16 / ES;   // elements per chunk
-    const int c1 = WT_M * Kp / EPC;                  // chunks of W1aug
-    const int c2 = 16 * WT_M / EPC;                  // chunks of W2
-    const int nchunk = c1 + c2 + 4;
-    const int chunk = blockIdx.x * TPB + threadIdx.x;
-    if (chunk >= nchunk) return;
-    for (int r = blockIdx.y; r < rows; r += gridDim.y) {
-        const float *w = W + (size_t)r * ld;
-        float v[EPC];
-        if (chunk < c1) {
-            const int e0 = chunk * EPC, kb = e0 / (WT_M * WT_K), rem = e0 % (WT_M * WT_K);
-            const int o = rem / WT_K, k0 = kb * WT_K + rem % WT_K;
+    float v[EPC];
+    if (chunk < c1) {
+        const int e0 = chunk * EPC, kb = e0 / (WT_M * WT_K), rem = e0 % (WT_M * WT_K);
+        const int o = rem / WT_K, k0 = kb * WT_K + rem % WT_K;
+        const float *src = w + woff1 + (size_t)o * in + k0;
+        if (o < hid && k0 + EPC <= in && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+            // inside W1 and 16-byte aligned: vector loads
+#pragma unroll
+            for (int e = 0; e < EPC; e += 4) {
+                const float4 t = *reinterpret_cast<const float4 *>(src + e);
+                v[e] = t.x;
+                v[e + 1] = t.y;
+                v[e + 2] = t.z;
+                v[e + 3] = t.w;
+            }
+        } else {
 #pragma unroll
             for (int e = 0; e < EPC; ++e) {
                 const int k = k0 + e;
@@ -48,41 +56,69 @@ __global__ __launch_bounds__(TPB) void k_pack_wide_rows(const float *__restrict_
                 }
                 v[e] = x;
             }
-        } else if (chunk < c1 + c2) {
-            const int e0 = (chunk - c1) * EPC, i = e0 / WT_M, c0 = e0 % WT_M;
+        }
+    } else if (chunk < c1 + c2) {
+        const int e0 = (chunk - c1) * EPC, i = e0 / WT_M, c0 = e0 % WT_M;
 #pragma unroll
-            for (int e = 0; e < EPC; ++e) {
-                int col = c0 + e;
-                if (BF) {
-                    const int blk = c0 & ~31, g = (c0 & 31) >> 3;   // c0 = 32kb + 8g
-                    col = blk + (e < 4 ? 4 * g + e : 16 + 4 * g + e - 4);
-                }
-                v[e] = (i < out && col < hid) ? w[woff2 + (size_t)i * hid + col] : 0.0f;
+        for (int e = 0; e < EPC; ++e) {
+            int col = c0 + e;
+            if (BF) {
+                const int blk = c0 & ~31, g = (c0 & 31) >> 3;   // c0 = 32kb + 8g
+                col = blk + (e < 4 ? 4 * g + e : 16 + 4 * g + e - 4);
             }
-        } else {
-            const int i0 = (chunk - c1 - c2) * 4;
-            float *dst = reinterpret_cast<float *>(Wp + (size_t)r * pr + (size_t)c1 * 16 + (size_t)c2 * 16);
-            float4 b;
-            b.x = i0 + 0 < out ? w[boff2 + i0 + 0] : 0.0f;
-            b.y = i0 + 1 < out ? w[boff2 + i0 + 1] : 0.0f;
-            b.z = i0 + 2 < out ? w[boff2 + i0 + 2] : 0.0f;
-            b.w = i0 + 3 < out ? w[boff2 + i0 + 3] : 0.0f;
-            reinterpret_cast<float4 *>(dst)[i0 / 4] = b;
-            continue;
+            v[e] = (i < out && col < hid) ? w[woff2 + (size_t)i * hid + col] : 0.0f;
         }
-        uint4 q;
-        if constexpr (BF) {
-            uint32_t h[4];
+    } else {
+        const int i0 = (chunk - c1 - c2) * 4;
+        float *dst = reinterpret_cast<float *>(wp + (size_t)c1 * 16 + (size_t)c2 * 16);
+        float4 b;
+        b.x = i0 + 0 < out ? w[boff2 + i0 + 0] : 0.0f;
+        b.y = i0 + 1 < out ? w[boff2 + i0 + 1] : 0.0f;
+        b.z = i0 + 2 < out ? w[boff2 + i0 + 2] : 0.0f;
+        b.w = i0 + 3 < out ? w[boff2 + i0 + 3] : 0.0f;
+        reinterpret_cast<float4 *>(dst)[i0 / 4] = b;
+        return;
+    }
+    uint4 q;
+    if constexpr (BF) {
+        uint32_t h[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                h[e] = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[2 * e]) |
-                       ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[2 * e + 1]) << 16);
-            q = make_uint4(h[0], h[1], h[2], h[3]);
-        } else {
-            q = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
-                           __float_as_uint(v[3]));
+        for (int e = 0; e < 4; ++e)
+            h[e] = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[2 * e]) |
+                   ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[2 * e + 1]) << 16);
+        q = make_uint4(h[0], h[1], h[2], h[3]);
+    } else {
+        q = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
+                       __float_as_uint(v[3]));
+    }
+    reinterpret_cast<uint4 *>(wp)[chunk] = q;
+}
+
+// A block packs PACK_RPB rows x (PACK_CPT * TPB) chunks: fat blocks, so the
+// dispatcher is not what bounds the pass.
+template <bool BF>
+__global__ __launch_bounds__(TPB) void k_pack_wide_rows(const float *__restrict__ W, size_t ld,
+                                                        int rows, char *__restrict__ Wp, size_t pr,
+                                                        int in, int hid, int out, int Kp, int woff1,
+                                                        int boff1, int woff2, int boff2)
+{
+    constexpr int ES = BF ? 2 : 4, EPC = 16 / ES;   // elements per chunk
+    const int c1 = WT_M * Kp / EPC;                  // chunks of W1aug
+    const int c2 = 16 * WT_M / EPC;                  // chunks of W2
+    const int nchunk = c1 + c2 + 4;
+    const int cfirst = blockIdx.x * TPB * PACK_CPT + threadIdx.x;
+    for (int r0 = blockIdx.y * PACK_RPB; r0 < rows; r0 += gridDim.y * PACK_RPB) {
+        const int rend = r0 + PACK_RPB < rows ? r0 + PACK_RPB : rows;
+        for (int r = r0; r < rend; ++r) {
+            const float *w = W + (size_t)r * ld;
+            char *wp = Wp + (size_t)r * pr;
+#pragma unroll
+            for (int i = 0; i < PACK_CPT; ++i) {
+                const int chunk = cfirst + i * TPB;
+                if (chunk < nchunk)
+                    pack_chunk<BF>(w, wp, chunk, c1, c2, in, hid, out, woff1, boff1, woff2, boff2);
+            }
         }
-        reinterpret_cast<uint4 *>(Wp + (size_t)r * pr)[chunk] = q;
     }
 }
 
@@ -208,7 +244,9 @@ hipError_t launch_fitness_wide(const Net &net, const DevState &d, const float *W
     const size_t pr = wide_row_bytes(net);
     const int es = net.bf16 ? 2 : 4, epc = 16 / es;
     const int nchunk = WT_M * Kp / epc + 16 * WT_M / epc + 4;
-    dim3 pg((nchunk + TPB - 1) / TPB, rows < MAX_GRID_Y ? rows : MAX_GRID_Y);
+    const int rgroups = (rows + PACK_RPB - 1) / PACK_RPB;
+    dim3 pg((nchunk + TPB * PACK_CPT - 1) / (TPB * PACK_CPT),
+            rgroups < MAX_GRID_Y ? rgroups : MAX_GRID_Y);
     if (net.bf16)
         hipLaunchKernelGGL(k_pack_wide_rows<true>, pg, dim3(TPB), 0, st, W, ld, rows, d.Wpack, pr,
                            net.fi[0], net.fo[0], net.fo[1], Kp, net.woff[0], net.boff[0],
