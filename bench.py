@@ -66,6 +66,7 @@ PROFILE_FOR = {   # (workload, precision) -> committed rocprofv3 traffic summary
     ("mlp64-128-128-10", "bf16"): "k_fit_mlp64-128-128-10_bf16_traffic.json",
     ("mlp784-256-10", "bf16"): "k_fit_wide_mlp784-256-10_bf16_traffic.json",
     ("mlp784-256-10", "fp32"): "k_fit_wide_mlp784-256-10_fp32_traffic.json",
+    ("net12", "fp32"): "k_net_layer_net12_fp32_traffic.json",   # the fitness step's launches
 }
 
 
