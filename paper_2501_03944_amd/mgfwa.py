@@ -514,8 +514,10 @@ class Server:
         self._keep = {}
         self._dims = {}
 
-    def submit(self, widths, acts, loss, x=None, y=None, labels=None, sync=True, **config) -> int:
+    def submit(self, widths, acts, loss=None, x=None, y=None, labels=None, sync=True, net=None,
+               **config) -> int:
         """Queue one job; the problem's device copies live until the server is closed.
+        net= makes it an input problem (the spark is the fixed network's input).
         sync=False skips the device synchronisation that makes freshly uploaded inputs
         visible to the job's stream (pass it for inputs already complete on the device)."""
         torch = self.torch
@@ -529,21 +531,26 @@ class Server:
         xt = dev(x, torch.float32)
         yt = dev(y, torch.float32) if loss == "mse" else None
         lt = dev(labels, torch.int32) if loss == "ce" else None
+        nt = dev(net, torch.float32)
         prob = make_problem(widths, acts, loss, 0 if xt is None else xt.shape[0],
                             0 if xt is None else xt.data_ptr(),
                             0 if yt is None else yt.data_ptr(),
-                            0 if lt is None else lt.data_ptr())
+                            0 if lt is None else lt.data_ptr(),
+                            None if nt is None else nt.data_ptr())
         if sync:
             torch.cuda.synchronize(self.device)   # the copies above are complete before admission
         jid = mgfwa_server_submit(self.h, make_config(**config), prob)
-        self._keep[jid] = (xt, yt, lt)
-        self._dims[jid] = sum((widths[i] + 1) * widths[i + 1] for i in range(len(widths) - 1))
+        self._keep[jid] = (xt, yt, lt, nt)
+        self._dims[jid] = (int(widths[0]) if nt is not None else
+                           sum((widths[i] + 1) * widths[i + 1] for i in range(len(widths) - 1)))
         return jid
 
     def submit_workload(self, wl, sync=True, **config) -> int:
         kw = dict(n_fireworks=wl.n_fireworks, n_sparks=wl.n_sparks, n_guiding=wl.n_guiding,
                   lb=wl.lb, ub=wl.ub, max_generations=wl.generations)
         kw.update(config)
+        if getattr(wl, "net", None) is not None:
+            return self.submit(wl.widths, wl.acts, sync=sync, net=wl.net, **kw)
         return self.submit(wl.widths, wl.acts, wl.loss, wl.x, wl.y, wl.labels, sync=sync, **kw)
 
     def tick(self):

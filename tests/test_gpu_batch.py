@@ -108,6 +108,29 @@ def test_tuned_fitness_matches_oracle():
     g.close()
 
 
+def test_batch_of_testbed_jobs_equals_jobs_stepped_alone():
+    torch, M = require_gpu()
+    wls = [inputs.testbed_net(i) for i in (1, 5, 10)]
+    cfgs = [dict(n_fireworks=4, n_sparks=64, n_guiding=4, seed=20 + i) for i in range(3)]
+    jobs = [M.MGFWA.from_workload(wl, **cfg) for wl, cfg in zip(wls, cfgs)]
+    for g in jobs:
+        g.autotune(2)
+    b = M.Batch(jobs)
+    b.step(4)
+    torch.cuda.synchronize()
+    for i, (wl, cfg) in enumerate(zip(wls, cfgs)):
+        alone = M.MGFWA.from_workload(wl, **cfg)
+        alone.autotune(2)                       # same shape: the cached plan
+        alone.step(4)
+        sa, sb = alone.state_numpy(), jobs[i].state_numpy()
+        for k in STATE_KEYS:
+            assert_bits(sb[k], sa[k], f"testbed job {i} {k}")
+        alone.close()
+    b.close()
+    for g in jobs:
+        g.close()
+
+
 def test_batch_errors():
     torch, M = require_gpu()
     js, cfgs = _jobs(n=2)

@@ -19,7 +19,7 @@ def _alone(wl, **cfg):
     kw = dict(n_fireworks=wl.n_fireworks, n_sparks=wl.n_sparks, n_guiding=wl.n_guiding,
               lb=wl.lb, ub=wl.ub, max_generations=wl.generations)
     kw.update(cfg)
-    g = M.MGFWA(wl.widths, wl.acts, wl.loss, wl.x, wl.y, wl.labels, **kw)
+    g = M.MGFWA.from_workload(wl, **kw)
     g.step(kw["max_generations"])
     x, f, gen = g.best()
     g.close()
@@ -56,6 +56,31 @@ def test_served_jobs_equal_jobs_run_alone():
         info, x = srv.job(jid)
         xa, fa, gen = _alone(wl, **cfg)
         assert info["state"] == "done" and info["generations"] == gen == cfg["max_generations"]
+        assert_bits(np.float32(info["best_fitness"]), np.float32(fa), f"job {jid} best fitness")
+        assert_bits(x, xa, f"job {jid} best position")
+    srv.close()
+
+
+def test_served_testbed_jobs_equal_jobs_run_alone():
+    """Input problems (the paper's testbed) served beside weight problems."""
+    torch, M = require_gpu()
+    jobs = [(inputs.testbed_net(2), dict(n_fireworks=4, n_sparks=64, n_guiding=4,
+                                         max_generations=30, seed=1)),
+            (inputs.teacher_regression(), dict(seed=7, max_generations=20)),
+            (inputs.testbed_net(9), dict(n_fireworks=2, n_sparks=128, n_guiding=4,
+                                         max_generations=8, seed=2, lag_guiding=True)),
+            (inputs.testbed_net(6), dict(n_fireworks=3, n_sparks=32, n_guiding=4,
+                                         max_generations=12, seed=3, map_range=True))]
+    srv = M.Server(512 << 20, n_streams=3)
+    ids = [srv.submit_workload(wl, **cfg) for wl, cfg in jobs]
+    srv.drain()
+    st = srv.stats()
+    assert st["done"] == len(jobs) and st["failed"] == 0
+    for jid, (wl, cfg) in zip(ids, jobs):
+        info, x = srv.job(jid)
+        xa, fa, gen = _alone(wl, **cfg)
+        assert info["generations"] == gen == cfg["max_generations"]
+        assert x.shape == xa.shape == (wl.dim,)
         assert_bits(np.float32(info["best_fitness"]), np.float32(fa), f"job {jid} best fitness")
         assert_bits(x, xa, f"job {jid} best position")
     srv.close()
