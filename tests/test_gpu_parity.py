@@ -78,6 +78,8 @@ def test_lockstep_teacher_100_generations():
     dict(n_populations=3, n_fireworks=2, n_sparks=8, n_guiding=2, T=6, seed=11),
     dict(n_fireworks=3, n_sparks=12, n_guiding=3, boost=1.75, sigma=0.5, seed=5, T=40),
     dict(n_fireworks=5, n_sparks=2, n_guiding=1, sigma=0.5, seed=9, loser_out=False),
+    # one firework per population: it is always its population's best (no loser-out)
+    dict(n_populations=2, n_fireworks=1, n_sparks=8, n_guiding=2, seed=15, T=20),
     # groups of 64 (one wavefront each) and of 128 members (the per-firework path)
     dict(n_fireworks=2, n_sparks=128, n_guiding=2, seed=13, T=30),
     dict(n_fireworks=2, n_sparks=256, n_guiding=2, sigma=0.3, seed=14, T=30),

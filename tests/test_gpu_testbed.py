@@ -252,6 +252,23 @@ def test_autotuned_input_problem_matches_oracle():
     g.close()
 
 
+@pytest.mark.parametrize("widths", [(7, 1), (300, 1), (5, 3, 1)])
+def test_degenerate_networks(widths):
+    """A single linear layer (no hidden activations at all) and a tiny hidden
+    layer: fitness, and free-running generations with one firework per
+    population."""
+    torch, M = require_gpu()
+    wl = inputs.net_input_problem(widths, ("relu",) * (len(widths) - 2), seed=len(widths) + widths[0])
+    g = M.MGFWA.from_workload(wl, n_fireworks=2, n_sparks=16, n_guiding=4)
+    p = O.Problem.from_workload(wl)
+    X = np.random.default_rng(2).uniform(-5, 5, (45, wl.dim)).astype(np.float32)
+    got, _ = _eval(torch, g, X)
+    assert_net_close(wl, X, got, p.loss_rows(X), f"{widths}")
+    g.close()
+    at = _free_run(wl, 10, n_populations=2, n_fireworks=1, n_sparks=16, n_guiding=2, seed=9, T=20)
+    print(f"{widths}: diverged_at={at}")
+
+
 def test_input_problem_errors():
     torch, M = require_gpu()
     wl = inputs.testbed_net(2)
