@@ -284,6 +284,7 @@ typedef struct {
     int row_blocks[4];      /* 16-row MFMA blocks per layer (padded widths / 16) */
     int net_kernel;         /* input problems: 0..3 layer by layer with 64x128, 64x64, 32x32
                                or K-split 16x16 output tiles, 4 whole-network 16/32-row tiles,
+                               5 / 6 layer by layer with LDS-staged 64x128 / 64x64 tiles,
                                -1 chosen per launch from the shape (before autotuning) */
 } mgfwa_plan_info;
 

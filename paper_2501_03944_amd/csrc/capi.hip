@@ -54,7 +54,7 @@ int round_up(int v, int a) { return (v + a - 1) / a * a; }
 struct Layout {
     size_t F, SE, SG, A, Y, Yprev, fresh, Yc, top, bottom, tie, cstar, improved, reinit, src;
     size_t best_x, best_y, best_f, best_gen, best_upd, ctrl, partial, Xp, Xb, Ypad, Lpad;
-    size_t Wpack, Xw, lo, hi, Pnet, H0, H1, total;
+    size_t Wpack, Xw, lo, hi, Pnet, H0, H1, Zero, total;
     int partial_rows;
 };
 
@@ -167,9 +167,10 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
         in.n_packed = off;
         in.hs = hmax + 4;   // 16-byte skew between the rows of the activation tile
         in.hnp = hmax;      // hidden outputs: np[l] = kp[l+1]
-        // MGFWA_NET_PATH=1 / 2 forces the whole-network / layer-by-layer kernels
+        // MGFWA_NET_PATH=1 / 2 / 3 forces the whole-network / layer-by-layer /
+        // LDS-staged layer-by-layer kernels (before autotuning)
         const char *np_env = std::getenv("MGFWA_NET_PATH");
-        in.path = np_env && (np_env[0] == '1' || np_env[0] == '2') ? np_env[0] - '0' : 0;
+        in.path = np_env && np_env[0] >= '1' && np_env[0] <= '3' ? np_env[0] - '0' : 0;
         D = p->widths[0];
     } else {
         net.nl = p->n_layers;
@@ -272,6 +273,7 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
     const size_t hbytes = input && need_data ? (size_t)L.partial_rows * in.hnp * 4 : 0;
     L.H0 = take(hbytes);
     L.H1 = take(hbytes);
+    L.Zero = take(input && need_data ? 256 : 0);
     L.total = off;
     if (s.lag && L.SG != L.SE + BN * s.lam * Dp * 4)
         return fail(MGFWA_EINVAL, "internal: guiding sparks must follow the explosion sparks");
@@ -351,7 +353,7 @@ mgfwa_status fit_rows(mgfwa_ctx *c, const FitPlan &plan, const float *W, size_t 
 {
     if (c->input) {
         STEP(launch_net_input(c->in, plan.net_shape, c->d.Pnet, W, ld, rows, map, out, c->d.H0,
-                              c->d.H1, st),
+                              c->d.H1, c->d.zero, st),
              "fitness_input");
         if (mid) STEP(hipEventRecord(mid, st), "event");
     } else if (c->net.wide)
@@ -562,6 +564,7 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
     d.Pnet = c->input && has_data ? at<float>(b, L.Pnet) : nullptr;
     d.H0 = c->input && has_data ? at<float>(b, L.H0) : nullptr;
     d.H1 = c->input && has_data ? at<float>(b, L.H1) : nullptr;
+    d.zero = c->input && has_data ? at<float>(b, L.Zero) : nullptr;
 
     auto bail = [&](mgfwa_status st) {
         mgfwa_destroy(c);
@@ -571,6 +574,8 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
     if (r) return bail(r);
     if (has_data && c->input) {
         r = check(c, launch_pack_net(c->in, problem->net_dev, d.Pnet, c->stream), "pack_net");
+        if (r) return bail(r);
+        r = check(c, hipMemsetAsync(d.zero, 0, 256, c->stream), "zero");
         if (r) return bail(r);
     } else if (has_data) {
         r = check(c, launch_pack_problem(c->net, problem->x_dev, problem->y_dev,
@@ -883,7 +888,7 @@ int tune_candidates(const mgfwa_ctx *c, int rows, FitPlan *cand, int max_out)
 {
     if (!c->input) return fit_candidates(c->net, rows, cand, max_out);
     int n = 0;
-    for (int shape = 0; shape <= NET_WHOLE && n < max_out; ++shape) {
+    for (int shape = 0; shape <= NET_LDS64 && n < max_out; ++shape) {
         cand[n] = FitPlan{};
         cand[n].rows = rows;
         cand[n].net_shape = shape;
@@ -921,7 +926,7 @@ mgfwa_status tune_plan(mgfwa_ctx *c, int rows, const float *W, OutMap map, int r
             if (k == 1) e = hipEventRecord(e0, c->stream);
             if (e == hipSuccess)
                 e = c->input ? launch_net_input(c->in, cand[i].net_shape, c->d.Pnet, W, c->s.Dp, rows,
-                                                map, c->d.Yc, c->d.H0, c->d.H1, c->stream)
+                                                map, c->d.Yc, c->d.H0, c->d.H1, c->d.zero, c->stream)
                              : launch_fitness(c->net, cand[i], c->d, W, c->s.Dp, rows, map, c->d.Yc,
                                               c->stream);
         }

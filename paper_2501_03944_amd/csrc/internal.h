@@ -41,6 +41,7 @@ struct DevState {
     float *lo, *hi;    // [B][Dp] population ranges (range mapping)
     float *Pnet;       // packed parameters of a fixed network (input problems)
     float *H0, *H1;    // [partial_rows][hnp] activations between layers (input problems)
+    float *zero;       // 256 zero bytes (input problems)
 };
 
 // Population shape and algorithm constants as the kernels need them.
@@ -88,7 +89,8 @@ struct InNet {
     int hs;                            // LDS row pitch (floats) of the activation tile
     int hnp;                           // widest hidden output (padded): activation row pitch
     int num_cu;                        // compute units (rows per block choice)
-    int path;                          // 0 choose per launch, 1 whole-network tiles, 2 layer by layer
+    int path;                          // 0 choose per launch, 1 whole-network tiles, 2 layer by
+                                       // layer, 3 layer by layer with LDS-staged tiles
 };
 
 // A chosen fitness kernel and its launch geometry for a given row count.
@@ -150,11 +152,15 @@ hipError_t launch_pack_net(const InNet &net, const float *params, float *packed,
 // out[map.index(r)] = f(x_r) for the rows of X (leading dimension ld >= fi[0]);
 // the layer-by-layer path keeps the activations in H0/H1 ([rows][hnp] each).
 // shape: 0..3 layer by layer with 64x128, 64x64, 32x32 or K-split 16x16 tiles,
-// NET_WHOLE the whole-network tiles, -1 a choice from the shape and row count.
+// NET_WHOLE the whole-network tiles, NET_LDS / NET_LDS64 layer by layer with
+// LDS-staged 64x128 / 64x64 tiles, -1 a choice from the shape and row count.
+// zero: 16 zero bytes.
 constexpr int NET_WHOLE = 4;
+constexpr int NET_LDS = 5;
+constexpr int NET_LDS64 = 6;
 hipError_t launch_net_input(const InNet &net, int shape, const float *packed, const float *X,
                             size_t ld, int rows, OutMap map, float *out, float *H0, float *H1,
-                            hipStream_t st);
+                            const float *zero, hipStream_t st);
 size_t net_input_lds_bytes(const InNet &net);
 hipError_t net_input_prepare(const InNet &net);   // raises the kernels' LDS limit
 
