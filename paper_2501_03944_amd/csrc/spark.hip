@@ -103,10 +103,13 @@ __global__ __launch_bounds__(TPB) void k_explode(const float *__restrict__ F,
     }
 }
 
-dim3 row_grid(int Dp, int rows)
+// Blocks over (chunk range, rows); a block takes rows_per_block rows (strided by
+// the grid), so that launches of many rows are not bound by block dispatch.
+dim3 row_grid(int Dp, int rows, int rows_per_block = 1)
 {
     const int nchunk = Dp >> 2;
-    return dim3((nchunk + TPB - 1) / TPB, rows < MAX_GRID_Y ? rows : MAX_GRID_Y);
+    const int ry = (rows + rows_per_block - 1) / rows_per_block;
+    return dim3((nchunk + TPB - 1) / TPB, ry < MAX_GRID_Y ? ry : MAX_GRID_Y);
 }
 
 }  // namespace
@@ -129,7 +132,10 @@ hipError_t launch_pop_range(const Shape &s, const DevState &d, hipStream_t st)
 hipError_t launch_explode(const Shape &s, const DevState &d, hipStream_t st)
 {
     const int rows = s.BN * s.lam;
-    hipLaunchKernelGGL(k_explode, row_grid(s.Dp, rows), dim3(TPB), 0, st, d.F, d.A, d.SE, s.lam,
+    // 32 or 8 rows per block while there are enough blocks to fill the device
+    const long blocks_x = ((s.Dp >> 2) + TPB - 1) / TPB;
+    const int rpb = blocks_x * (rows / 32) >= 2048 ? 32 : blocks_x * (rows / 8) >= 2048 ? 8 : 1;
+    hipLaunchKernelGGL(k_explode, row_grid(s.Dp, rows, rpb), dim3(TPB), 0, st, d.F, d.A, d.SE, s.lam,
                        rows, s.D, s.Dp, s.key, s.box, d.ctrl, s.N, s.map_range ? d.lo : nullptr,
                        s.map_range ? d.hi : nullptr);
     return hipGetLastError();
