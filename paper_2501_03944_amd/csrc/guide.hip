@@ -1,12 +1,12 @@
 // Multi-guiding sparks (Alg. 1: generate the multi-guiding sparks, then their
 // random mapping).
 //
-// k_rank  -- ranks the members of every guiding group by (fitness key, spark
-//            index), writes the top-k and bottom-k member lists in ascending
-//            spark index and the all-tie flag.  Groups of up to 64 members: one
-//            wavefront per group, one lane per member (keys broadcast by lane
-//            shuffles, list positions from ballots); larger groups: one block
-//            per firework over LDS.
+// Ranking: the members of every guiding group ordered by (fitness key, spark
+//            index) give the top-k and bottom-k member lists in ascending spark
+//            index and the all-tie flag.  Groups of up to 64 members are ranked
+//            inside k_guide by one wavefront, one lane per member (keys
+//            broadcast by lane shuffles, list positions from ballots); larger
+//            groups by k_rank, one block per firework over LDS.
 // k_guide -- grid over (group, 4-coordinate chunk): the guiding vector is
 //            (sum of top sparks - sum of bottom sparks) * (1/k), each sum taken
 //            in ascending spark index (zero when the group ties); the guiding
@@ -79,27 +79,32 @@ __global__ __launch_bounds__(TPB) void k_rank(const float *__restrict__ Yc, int 
     }
 }
 
-// m <= 64: wavefront w of a block ranks group blockIdx.x * (TPB / 64) + w.
-__global__ __launch_bounds__(TPB) void k_rank_wave(const float *__restrict__ Yc, int C, int G,
-                                                   int m, int k, int groups,
-                                                   int32_t *__restrict__ top,
-                                                   int32_t *__restrict__ bottom,
-                                                   int32_t *__restrict__ tie,
-                                                   const int32_t *__restrict__ ctrl, int lag)
+// Groups of m <= 64 members: the calling wavefront ranks group gi (g = gi % G
+// of firework gi / G), one lane per member, and writes its top-k and bottom-k
+// lists (spark indices within the firework, ascending) and tie flag through
+// the given pointers (LDS, and global memory when g_top is non-null).
+__device__ __forceinline__ void rank_group_wave(const float *__restrict__ Yc, int C, int G, int m,
+                                                int k, int gi, bool zero_guide, int32_t *l_top,
+                                                int32_t *l_bottom, int32_t *l_tie, int32_t *g_top,
+                                                int32_t *g_bottom, int32_t *g_tie)
 {
-    if (ctrl[CTRL_DONE]) return;
     const int lane = threadIdx.x & 63;
-    const int gi = blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);   // gf * G + g
-    if (gi >= groups) return;
     const int gf = gi / G, g = gi % G;
     const size_t base = (size_t)gi * k;
-    if (lag && ctrl[CTRL_GEN] == 0) {
+    if (zero_guide) {
         // lagged guiding before any explosion: every guiding vector is zero
         if (lane < k) {
-            top[base + lane] = g * m + lane;
-            bottom[base + lane] = g * m + m - k + lane;
+            l_top[lane] = g * m + lane;
+            l_bottom[lane] = g * m + m - k + lane;
+            if (g_top) {
+                g_top[base + lane] = g * m + lane;
+                g_bottom[base + lane] = g * m + m - k + lane;
+            }
         }
-        if (lane == 0) tie[gi] = 1;
+        if (lane == 0) {
+            *l_tie = 1;
+            if (g_tie) g_tie[gi] = 1;
+        }
         return;
     }
     const bool in = lane < m;
@@ -112,8 +117,16 @@ __global__ __launch_bounds__(TPB) void k_rank_wave(const float *__restrict__ Yc,
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const bool is_top = in && r < k, is_bottom = in && r >= m - k;
     const uint64_t tmask = __ballot(is_top), bmask = __ballot(is_bottom);
-    if (is_top) top[base + __popcll(tmask & below)] = g * m + lane;
-    if (is_bottom) bottom[base + __popcll(bmask & below)] = g * m + lane;
+    if (is_top) {
+        const int pos = __popcll(tmask & below);
+        l_top[pos] = g * m + lane;
+        if (g_top) g_top[base + pos] = g * m + lane;
+    }
+    if (is_bottom) {
+        const int pos = __popcll(bmask & below);
+        l_bottom[pos] = g * m + lane;
+        if (g_bottom) g_bottom[base + pos] = g * m + lane;
+    }
     // the group ties iff its first and last ranked members share a key, i.e.
     // iff its smallest and largest keys are equal
     uint32_t lo = in ? kj : 0xffffffffu, hi = in ? kj : 0u;
@@ -122,33 +135,63 @@ __global__ __launch_bounds__(TPB) void k_rank_wave(const float *__restrict__ Yc,
         lo = l2 < lo ? l2 : lo;
         hi = h2 > hi ? h2 : hi;
     }
-    if (lane == 0) tie[gi] = lo == hi;
+    if (lane == 0) {
+        *l_tie = lo == hi;
+        if (g_tie) g_tie[gi] = lo == hi;
+    }
 }
 
+// RANK: groups of m <= 64 members are ranked inside the kernel (wavefront 0 of
+// each block, into LDS; the x-block 0 also stores the lists); otherwise the
+// lists come from k_rank.
+template <bool RANK>
 __global__ __launch_bounds__(TPB) void k_guide(const float *__restrict__ F,
                                                const float *__restrict__ SE,
                                                float *__restrict__ SG,
-                                               const int32_t *__restrict__ top,
-                                               const int32_t *__restrict__ bottom,
-                                               const int32_t *__restrict__ tie, int G, int lam,
+                                               int32_t *__restrict__ top,
+                                               int32_t *__restrict__ bottom,
+                                               int32_t *__restrict__ tie, int G, int lam,
                                                int k, float inv_k, float boost, int groups, int D,
                                                int Dp, uint2 key, Box box,
                                                const int32_t *__restrict__ ctrl, int N,
                                                const float *__restrict__ lo,
-                                               const float *__restrict__ hi)
+                                               const float *__restrict__ hi,
+                                               const float *__restrict__ Yc, int C, int m, int lag)
 {
+    __shared__ int32_t s_top[64], s_bottom[64], s_tie;
     if (ctrl[CTRL_DONE]) return;
     const uint32_t tn = (uint32_t)ctrl[CTRL_GEN] + 1u;
     const int chunk = blockIdx.x * TPB + threadIdx.x;
-    if (chunk >= (Dp >> 2)) return;
+    const bool active = chunk < (Dp >> 2);
+    const bool zero_guide = lag && ctrl[CTRL_GEN] == 0;
     for (int gi = blockIdx.y; gi < groups; gi += gridDim.y) {
+        const int32_t *tp, *bp;
+        int tied;
+        if constexpr (RANK) {
+            if (threadIdx.x < 64) {
+                const bool store = blockIdx.x == 0;
+                rank_group_wave(Yc, C, G, m, k, gi, zero_guide, s_top, s_bottom, &s_tie,
+                                store ? top : nullptr, store ? bottom : nullptr,
+                                store ? tie : nullptr);
+            }
+            __syncthreads();
+            tp = s_top;
+            bp = s_bottom;
+            tied = s_tie;
+        } else {
+            tp = top + (size_t)gi * k;
+            bp = bottom + (size_t)gi * k;
+            tied = tie[gi];
+        }
+        if (!active) {
+            if constexpr (RANK) __syncthreads();   // the lists are read before the next group
+            continue;
+        }
         const int gf = gi / G;
         const float4 x4 = reinterpret_cast<const float4 *>(F + (size_t)gf * Dp)[chunk];
         float dlt[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (!tie[gi]) {
+        if (!tied) {
             float st[4] = {0.0f, 0.0f, 0.0f, 0.0f}, sb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-            const int32_t *tp = top + (size_t)gi * k;
-            const int32_t *bp = bottom + (size_t)gi * k;
             const float *base = SE + (size_t)gf * lam * Dp;
             for (int i = 0; i < k; ++i) {
                 const float4 a = reinterpret_cast<const float4 *>(base + (size_t)tp[i] * Dp)[chunk];
@@ -180,6 +223,7 @@ __global__ __launch_bounds__(TPB) void k_guide(const float *__restrict__ F,
         for (int e = 0; e < 4; ++e)
             if (4 * chunk + e >= D) v[e] = 0.0f;
         reinterpret_cast<float4 *>(SG + (size_t)gi * Dp)[chunk] = make_float4(v[0], v[1], v[2], v[3]);
+        if constexpr (RANK) __syncthreads();   // the lists are read before the next group
     }
 }
 
@@ -187,12 +231,7 @@ __global__ __launch_bounds__(TPB) void k_guide(const float *__restrict__ F,
 
 hipError_t launch_rank(const Shape &s, const DevState &d, hipStream_t st)
 {
-    if (s.m <= 64) {
-        const int groups = s.BN * s.G, per = TPB / 64;
-        hipLaunchKernelGGL(k_rank_wave, dim3((groups + per - 1) / per), dim3(TPB), 0, st, d.Yc, s.C,
-                           s.G, s.m, s.k, groups, d.top, d.bottom, d.tie, d.ctrl, s.lag);
-        return hipGetLastError();
-    }
+    if (s.m <= 64) return hipSuccess;   // ranked inside k_guide
     const size_t shmem = (size_t)s.lam * 8;
     hipLaunchKernelGGL(k_rank, dim3(s.BN), dim3(TPB), shmem, st, d.Yc, s.C, s.lam, s.G, s.m, s.k,
                        d.top, d.bottom, d.tie, d.ctrl, s.lag);
@@ -204,9 +243,15 @@ hipError_t launch_guide(const Shape &s, const DevState &d, hipStream_t st)
     const int groups = s.BN * s.G;
     const int nchunk = s.Dp >> 2;
     dim3 grid((nchunk + TPB - 1) / TPB, groups < MAX_GRID_Y ? groups : MAX_GRID_Y);
-    hipLaunchKernelGGL(k_guide, grid, dim3(TPB), 0, st, d.F, d.SE, d.SG, d.top, d.bottom, d.tie,
-                       s.G, s.lam, s.k, s.inv_k, s.boost, groups, s.D, s.Dp, s.key, s.box, d.ctrl,
-                       s.N, s.map_range ? d.lo : nullptr, s.map_range ? d.hi : nullptr);
+    const float *lo = s.map_range ? d.lo : nullptr, *hi = s.map_range ? d.hi : nullptr;
+    if (s.m <= 64)
+        hipLaunchKernelGGL(k_guide<true>, grid, dim3(TPB), 0, st, d.F, d.SE, d.SG, d.top, d.bottom,
+                           d.tie, s.G, s.lam, s.k, s.inv_k, s.boost, groups, s.D, s.Dp, s.key, s.box,
+                           d.ctrl, s.N, lo, hi, d.Yc, s.C, s.m, s.lag);
+    else
+        hipLaunchKernelGGL(k_guide<false>, grid, dim3(TPB), 0, st, d.F, d.SE, d.SG, d.top, d.bottom,
+                           d.tie, s.G, s.lam, s.k, s.inv_k, s.boost, groups, s.D, s.Dp, s.key, s.box,
+                           d.ctrl, s.N, lo, hi, d.Yc, s.C, s.m, s.lag);
     return hipGetLastError();
 }
 
