@@ -3,8 +3,10 @@
  *
  * The library runs the generation loop of GPU-MGFWA (the GPU multi-guiding spark
  * fireworks algorithm, Sec. 3 and Alg. 1 of the paper) on one GPU for black-box
- * optimisation of an MLP's weights: every spark is one weight vector of length
- * D, and its fitness is the MLP's loss over a fixed, shared sample set.  Per
+ * optimisation of an MLP's weights (every spark is one weight vector of length
+ * D, its fitness the MLP's loss over a fixed, shared sample set) or of a fixed
+ * MLP's input (the paper's testbed, Sec. 4.1: the spark is the input, its
+ * fitness the network's output; see mgfwa_problem).  Per
  * generation it generates the explosion sparks of all fireworks of all
  * populations at once, maps out-of-bounds coordinates back into the box,
  * evaluates every spark, builds the multi-guiding sparks from the top and
@@ -15,8 +17,9 @@
  * Conventions shared by every entry point:
  *  - All functions return an mgfwa_status (0 = success) and never abort; on
  *    failure mgfwa_last_error() returns a thread-local message.
- *  - Device memory is owned by the caller: the workspace, the problem's sample
- *    and target buffers, and every buffer passed to ask/tell/evaluate.  The
+ *  - Device memory is owned by the caller: the workspace, the problem's sample,
+ *    target and network-parameter buffers, and every buffer passed to
+ *    ask/tell/evaluate.  The
  *    library never allocates device memory.  The context object itself is
  *    host memory owned by the library; release it with mgfwa_destroy.
  *  - All device work is enqueued on the caller's HIP stream given to
@@ -178,9 +181,12 @@ typedef struct {
 #define MGFWA_N_PHASES 5
 typedef struct {
     double ms[MGFWA_N_PHASES];  /* 0 explosion sparks, 1 explosion fitness, 2 ranking + guiding
-                                   sparks, 3 guiding fitness, 4 selection + loser-out */
+                                   sparks, 3 guiding fitness, 4 selection + loser-out; with
+                                   lag_guiding, 0 also holds the ranking and guiding sparks,
+                                   1 the fitness of both kinds and 2, 3 are empty */
     double gen_ms_p50, gen_ms_p99, gen_ms_mean; /* whole-generation device time */
-    double fit_kernel_ms;       /* explosion-spark fitness GEMM kernel alone (subset of ms[1]) */
+    double fit_kernel_ms;       /* explosion-spark fitness GEMM kernel(s) alone (subset of
+                                   ms[1]; the layer-by-layer launches of an input problem) */
     int generations;            /* generations measured since timing was switched on */
 } mgfwa_timing_info;
 
@@ -236,7 +242,8 @@ MGFWA_API mgfwa_status mgfwa_ask(mgfwa_ctx *ctx, const float **sparks_dev, int *
 MGFWA_API mgfwa_status mgfwa_tell(mgfwa_ctx *ctx, const float *fitness_dev);
 
 /*
- * Fitness of `rows` weight vectors (the evaluation step of Alg. 1 on its own):
+ * Fitness of `rows` sparks (weight vectors, or network inputs for an input
+ * problem; the evaluation step of Alg. 1 on its own):
  * w_dev float [rows][ld] device (16-byte aligned, ld >= D, ld % 4 == 0),
  * out_dev float [rows] device; both caller-owned, read/written in stream order.
  * Uses the context's problem and precision.  EINVAL without a problem.
