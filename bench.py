@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--serving-study", type=int, default=1,
                     help="1: also run a Poisson stream of mixed jobs through the serving loop")
     ap.add_argument("--serve-seconds", type=float, default=8.0, help="arrival window of that study")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: autotune the fitness launches before timing (mgfwa_autotune)")
     ap.add_argument("--testbed-study", type=int, default=1,
                     help="1: the paper's testbed (Table 2 nets, input optimisation), per net")
     ap.add_argument("--seed", type=int, default=0)
@@ -104,7 +106,7 @@ def calibration_copy(mib):
     del src, dst
 
 
-def run_gpu(wl, precision, steps, warmup, seed):
+def run_gpu(wl, precision, steps, warmup, seed, autotune=True):
     import torch
 
     from paper_2501_03944_amd import mgfwa as M
@@ -112,8 +114,8 @@ def run_gpu(wl, precision, steps, warmup, seed):
     g = M.MGFWA.from_workload(wl, precision=precision, seed=seed,
                               max_generations=max(wl.generations, warmup + 2 * steps + 1))
     C = g.BN * (wl.n_sparks + wl.n_guiding)
-    if getattr(wl, "net", None) is not None:
-        g.autotune(3)     # testbed networks: the tile shape of each launch size
+    if autotune:
+        g.autotune(3)     # the kernel variant / tile shape of each launch size
     g.step(warmup)
     torch.cuda.synchronize()
     # timed region: per-phase HIP events on the library's stream
@@ -425,7 +427,7 @@ def main():
     wl = inputs.workload(args.workload)
     precision = args.precision or "fp32"
     calibration_copy(args.calib_copy_mib)
-    r = run_gpu(wl, precision, args.steps, args.warmup, args.seed)
+    r = run_gpu(wl, precision, args.steps, args.warmup, args.seed, bool(args.autotune))
     K = args.steps
     value = r["C"] * K / (r["ms"] / 1e3)
     t = r["timing"]
@@ -460,7 +462,8 @@ def main():
         "config": {"workload": WORKLOAD_TAG[args.workload], "fireworks": wl.n_fireworks,
                    "sparks": wl.n_sparks, "guiding": wl.n_guiding,
                    "samples": 0 if testbed else wl.n_samples,
-                   "D": wl.dim, "precision": precision, "parallelism": "single-gpu"},
+                   "D": wl.dim, "precision": precision, "autotuned": bool(args.autotune),
+                   "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic, "traffic_source": traffic_src,
                      "algorithmic_bytes": alg_bytes,
