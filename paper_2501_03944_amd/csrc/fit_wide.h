@@ -191,15 +191,6 @@ __device__ __forceinline__ void wait_stage()
     cfence();
 }
 
-// 16-byte LDS read issued as an instruction the compiler does not track; the
-// caller waits for it with lgkm_wait_all before using the value.
-__device__ __forceinline__ bf16x8 lds_read16(const char *p)
-{
-    bf16x8 v;
-    asm volatile("ds_read_b128 %0, %1" : "=v"(v) : "v"((const lds_void_t *)p));
-    return v;
-}
-
 // All of this wave's LDS reads have completed; the fragments passed through are
 // tied to the wait so that nothing uses them earlier.
 __device__ __forceinline__ void lgkm_wait_all(bf16x8 (&a)[8], bf16x8 (&b)[8])
@@ -210,24 +201,91 @@ __device__ __forceinline__ void lgkm_wait_all(bf16x8 (&a)[8], bf16x8 (&b)[8])
                    "+v"(b[4]), "+v"(b[5]), "+v"(b[6]), "+v"(b[7]));
 }
 
-// One wave load (t of LOADS) of K step kt of tile (r, col) into an LDS stage.
-__device__ __forceinline__ void pipe_issue_one(const WideArgs &a, char *stage, int r, int col,
-                                               int kt, int wave, int lane, int t)
+// Per-lane constants of the pipelined kernel.  The swizzle term of a row that
+// a lane touches depends only on the row's low bits, which are the same for
+// every row block the lane visits, so one offset per operand serves all of them.
+struct PipeLane {
+    uint32_t goff;    // lane's byte offset inside a 1 KiB block of 16 rows (global side)
+    uint32_t aoff;    // LDS offset of the lane's A fragment of row block 0 (stage-relative)
+    uint32_t boff;    // same for the B fragment (X half of the stage)
+    int woff;         // byte offset of this wave's first 16-row block of a tile (uniform)
+};
+
+__device__ __forceinline__ PipeLane pipe_lane(int wave, int lane, int nh, int sh)
 {
     using C = WideCfg<true>;
-    // K-blocked operands: step kt of a tile is one contiguous 256-row block
-    const char *wrow = a.Wp + (size_t)r * a.pr + (size_t)kt * C::TILEB;
-    const char *xrow = a.Xw + ((size_t)col * a.nk + kt) * C::TILEB;
-    const uint32_t gpitch = C::ROWB;
+    const int n = lane & 15, g = lane >> 4;
     const int lr = lane / C::NCH, pc = lane % C::NCH;
+    PipeLane L;
+    L.goff = (uint32_t)(lr * C::ROWB + ((pc ^ ((lr >> 1) & 3)) << 4));
+    const uint32_t fo = (uint32_t)(n * C::ROWB + ((g ^ ((n >> 1) & 3)) << 4));
+    L.aoff = (uint32_t)(128 * nh * C::ROWB) + fo;
+    L.boff = (uint32_t)(C::TILEB + 128 * sh * C::ROWB) + fo;
+    L.woff = wave * (C::LOADS / 2) * C::RPL * C::ROWB;
+    return L;
+}
+
+// Global sources of the look-ahead loads: K step kt of the current tile, or
+// step kt - nk of the next one.  Past the last tile the look-ahead stays on the
+// current tile's last step (re-loaded into the free stage, so the wait counts
+// are constants).
+struct Look {
+    const char *wcur, *xcur, *wnext, *xnext;
+    int nmask;        // -1 while a next tile exists, else 0
+};
+
+__device__ __forceinline__ void look_set(const WideArgs &a, const TileIter &it, int i, int ntiles,
+                                         Look &lk)
+{
+    using C = WideCfg<true>;
+    int r, col;
+    it.tile(i, &r, &col);
+    lk.wcur = a.Wp + (size_t)r * a.pr;
+    lk.xcur = a.Xw + (size_t)col * a.nk * C::TILEB;
+    if (i + 1 < ntiles) {
+        it.tile(i + 1, &r, &col);
+        lk.wnext = a.Wp + (size_t)r * a.pr;
+        lk.xnext = a.Xw + (size_t)col * a.nk * C::TILEB;
+        lk.nmask = -1;
+    } else {
+        lk.wnext = lk.wcur + (size_t)(a.nk - 1) * C::TILEB;
+        lk.xnext = lk.xcur + (size_t)(a.nk - 1) * C::TILEB;
+        lk.nmask = 0;
+    }
+}
+
+// One wave load (t of LOADS) of the K step whose W and X blocks start at wsrc
+// and xsrc, into an LDS stage: alternately a 1 KiB block of the W tile and of
+// the X tile.  The 16-byte chunks are gathered in swizzled order on the global
+// side and land contiguously in LDS.
+__device__ __forceinline__ void pipe_issue_one(const char *wsrc, const char *xsrc, char *stage,
+                                               const PipeLane &L, int t)
+{
+    using C = WideCfg<true>;
     const int half = t & 1;
-    const int r0 = (wave * (C::LOADS / 2) + (t >> 1)) * C::RPL;
-    const int row = r0 + lr;
-    const int q = pc ^ wide_swz(row, C::NCH);
-    const uint32_t off = (uint32_t)row * gpitch + (uint32_t)q * 16u;
-    const char *src = (half ? xrow : wrow) + off;
-    char *dst = stage + half * C::TILEB + r0 * C::ROWB;
+    const int blk = L.woff + (t >> 1) * C::RPL * C::ROWB;
+    const char *src = (half ? xsrc : wsrc) + blk + L.goff;
+    char *dst = stage + half * C::TILEB + blk;
     __builtin_amdgcn_global_load_lds(src, (lds_void_t *)dst, 16, 0, 0);
+}
+
+// 16-byte LDS read at a lane address plus an immediate offset, issued as an
+// instruction the compiler does not track; the caller waits for it with
+// lgkm_wait_all before using the value.
+template <int OFF>
+__device__ __forceinline__ bf16x8 lds_read16_at(uint32_t addr)
+{
+    bf16x8 v;
+    asm volatile("ds_read_b128 %0, %1 offset:%2" : "=v"(v) : "v"(addr), "i"(OFF));
+    return v;
+}
+
+// Fragments of row block RB of both operands from the stage at LDS address st.
+template <int RB>
+__device__ __forceinline__ void pipe_read_rb(uint32_t st, const PipeLane &L, bf16x8 &fa, bf16x8 &fb)
+{
+    fb = lds_read16_at<RB * 16 * WideCfg<true>::ROWB>(st + L.boff);
+    fa = lds_read16_at<RB * 16 * WideCfg<true>::ROWB>(st + L.aoff);
 }
 
 // Wait until this wave's loads of the next step's stage have landed (the loads
@@ -244,45 +302,58 @@ __device__ __forceinline__ void pipe_wait()
     cfence();
 }
 
-// One pipelined K step q (register set P holds its fragments): refill the
-// stage of step q with step q+4, read the fragments of step q+1 into set 1-P,
-// and run the 64 multiplies of step q; per row block of 8 multiplies, two
-// fragment reads go first and one load in the middle.
-template <int P>
-__device__ __forceinline__ void pipe_step(const WideArgs &a, char *smem, const TileIter &it, int q,
-                                          int Q, int wave, int lane, int nh, int sh, int n, int g,
-                                          floatx4 (&acc)[8][8], bf16x8 (&fa)[2][8],
-                                          bf16x8 (&fb)[2][8])
+// The multiply of one accumulator tile in a K step; the first step of a tile
+// starts from zero (addend 0), so the accumulators need no clearing between
+// tiles.
+template <bool FIRST>
+__device__ __forceinline__ void mfma_step(floatx4 &c, const bf16x8 &a, const bf16x8 &b)
+{
+    if constexpr (FIRST) asm("v_mfma_f32_16x16x32_bf16 %0, %1, %2, 0" : "=a"(c) : "v"(a), "v"(b));
+    else mfma_acc(c, a, b);
+}
+
+// Row block RB of one pipelined K step (register set P holds the step's
+// fragments): two fragment reads of the next step into set 1-P, four
+// multiplies, one look-ahead load, four multiplies.
+template <int P, bool FIRST, int RB>
+__device__ __forceinline__ void pipe_rb(uint32_t next, const char *wsrc, const char *xsrc,
+                                        char *fill, const PipeLane &L, floatx4 (&acc)[8][8],
+                                        bf16x8 (&fa)[2][8], bf16x8 (&fb)[2][8])
+{
+    pipe_read_rb<RB>(next, L, fa[1 - P][RB], fb[1 - P][RB]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) mfma_step<FIRST>(acc[RB][cb], fa[P][RB], fb[P][cb]);
+    __builtin_amdgcn_sched_barrier(0);
+    pipe_issue_one(wsrc, xsrc, fill, L, RB);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int cb = 4; cb < 8; ++cb) mfma_step<FIRST>(acc[RB][cb], fa[P][RB], fb[P][cb]);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (RB + 1 < 8) pipe_rb<P, FIRST, RB + 1>(next, wsrc, xsrc, fill, L, acc, fa, fb);
+}
+
+// One pipelined K step: step kt of the tile, global step q.  Refill the stage
+// of step q with the step STAGES ahead, read the fragments of step q+1 into set
+// 1-P, and run the 64 multiplies of step q.  The per-step address work is a
+// handful of scalar operations: the look-ahead sources come from the tile
+// bases in lk, the fragment addresses from the per-lane offsets in L.
+template <int P, bool FIRST = false>
+__device__ __forceinline__ void pipe_step(const WideArgs &a, char *smem, const Look &lk, int kt,
+                                          int q, const PipeLane &L, floatx4 (&acc)[8][8],
+                                          bf16x8 (&fa)[2][8], bf16x8 (&fb)[2][8])
 {
     using C = WideCfg<true>;
     pipe_wait();
-    int qq = q + PipeCfg::STAGES;
-    qq = qq < Q ? qq : Q - 1;                     // past the end: re-load into the free stage
-    int r, col;
-    it.tile(qq / a.nk, &r, &col);
-    const int kt = qq % a.nk;
+    const int la = kt + PipeCfg::STAGES;
+    const bool wrap = la >= a.nk;
+    const int lo = wrap ? ((la - a.nk) & lk.nmask) : la;
+    const char *wsrc = (wrap ? lk.wnext : lk.wcur) + (size_t)lo * C::TILEB;
+    const char *xsrc = (wrap ? lk.xnext : lk.xcur) + (size_t)lo * C::TILEB;
     char *fill = smem + (q & (PipeCfg::STAGES - 1)) * PipeCfg::STAGEB;
-    const int qn = q + 1 < Q ? q + 1 : Q - 1;
-    const char *next = smem + (qn & (PipeCfg::STAGES - 1)) * PipeCfg::STAGEB;
-    const char *wt = next, *xt = next + C::TILEB;
-#pragma unroll
-    for (int rb = 0; rb < 8; ++rb) {
-        {
-            const int rowb = 128 * sh + 16 * rb + n;
-            fb[1 - P][rb] = lds_read16(xt + rowb * C::ROWB + ((g ^ wide_swz(rowb, 4)) << 4));
-            const int rowa = 128 * nh + 16 * rb + n;
-            fa[1 - P][rb] = lds_read16(wt + rowa * C::ROWB + ((g ^ wide_swz(rowa, 4)) << 4));
-        }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) mfma_acc(acc[rb][cb], fa[P][rb], fb[P][cb]);
-        __builtin_amdgcn_sched_barrier(0);
-        pipe_issue_one(a, fill, r, col, kt, wave, lane, rb);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int cb = 4; cb < 8; ++cb) mfma_acc(acc[rb][cb], fa[P][rb], fb[P][cb]);
-        __builtin_amdgcn_sched_barrier(0);
-    }
+    const uint32_t next = (uint32_t)(uintptr_t)(lds_void_t *)(smem + ((q + 1) & (PipeCfg::STAGES - 1)) *
+                                                                          PipeCfg::STAGEB);
+    pipe_rb<P, FIRST, 0>(next, wsrc, xsrc, fill, L, acc, fa, fb);
     lgkm_wait_all(fa[1 - P], fb[1 - P]);
 }
 
@@ -367,6 +438,26 @@ __device__ __forceinline__ void w2_load(const WideArgs &a, int r, int nh, int n,
     }
     const float *b2 = reinterpret_cast<const float *>(base + 16 * WT_M * C::ES);
     w.b2 = *reinterpret_cast<const floatx4 *>(b2 + 4 * g);
+    // cross-entropy: the logit slots past the output width become -inf (their
+    // weights and bias are zero), so the loss needs no per-output predicate
+    if (a.loss == 1) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            if (4 * g + v >= a.fo1) w.b2[v] = -__builtin_huge_valf();
+    }
+}
+
+typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
+
+// ReLU of eight BF16 values as packed 16-bit integer maxima against zero: a
+// non-negative BF16 is a non-negative integer, a negative one (or -0) a negative
+// integer.  Rounding to BF16 keeps the sign, so this equals ReLU before rounding.
+__device__ __forceinline__ bf16x8 relu_bf16x8(bf16x8 v)
+{
+    uintx4 u = __builtin_bit_cast(uintx4, v);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) asm("v_pk_max_i16 %0, %1, 0" : "=v"(u[e]) : "v"(u[e]));
+    return __builtin_bit_cast(bf16x8, u);
 }
 
 template <int ACT>
@@ -377,9 +468,22 @@ __device__ __forceinline__ floatx4 act4(floatx4 v)
     return v;
 }
 
-// Loss of one sample from its logits zz[0..fo1): cross-entropy against its
-// label (log1p form when the label holds the maximum), or the squared error
-// summed over the outputs.
+// Maximum of three values (no NaN canonicalisation: the operands are finite or
+// -inf logits).
+__device__ __forceinline__ float vmax3(float a, float b, float c)
+{
+    float d;
+    asm("v_max3_f32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
+// Loss of one sample from its 16 logit slots zz (cross-entropy: slots at or past
+// the output width hold -inf): cross-entropy against its label as log-sum-exp
+// around the maximum (log1p of the other terms when the label holds the
+// maximum), or the squared error summed over the outputs.  FAST takes exp(x) as
+// 2^(x log2 e) on the hardware exp2 unit (the BF16 kernels, whose logits carry
+// BF16 rounding far above its error).
+template <bool FAST>
 __device__ __forceinline__ float sample_loss(const WideArgs &a, int s, int label,
                                              const float (&zz)[16])
 {
@@ -394,21 +498,19 @@ __device__ __forceinline__ float sample_loss(const WideArgs &a, int s, int label
             }
         return acc;
     }
-    float mx = -__builtin_huge_valf(), zl = 0.0f;
+    float mx = vmax3(zz[0], zz[1], zz[2]);
 #pragma unroll
-    for (int o = 0; o < 16; ++o)
-        if (o < a.fo1) {
-            mx = fmaxf(mx, zz[o]);
-            if (o == label) zl = zz[o];
-        }
-    float se = 0.0f, rest = 0.0f;
+    for (int o = 3; o < 15; o += 2) mx = vmax3(mx, zz[o], zz[o + 1]);
+    mx = vmax3(mx, zz[15], zz[15]);
+    float se = 0.0f, rest = 0.0f, zl = 0.0f;
 #pragma unroll
-    for (int o = 0; o < 16; ++o)
-        if (o < a.fo1) {
-            const float e = expf(zz[o] - mx);
-            se += e;
-            if (o != label) rest += e;
-        }
+    for (int o = 0; o < 16; ++o) {
+        const float d = zz[o] - mx;
+        const float e = FAST ? __builtin_amdgcn_exp2f(d * 1.44269504088896341f) : expf(d);
+        se += e;
+        rest += o == label ? 0.0f : e;
+        zl = o == label ? zz[o] : zl;
+    }
     return zl == mx ? log1pf(rest) : (mx - zl) + logf(se);
 }
 
@@ -440,7 +542,9 @@ __device__ void wide_epilogue(const WideArgs &a, char *smem, int r, int col, int
             const bf16x8 afr = __builtin_bit_cast(bf16x8, w2.f[kb]);
 #pragma unroll
             for (int cb = 0; cb < 8; ++cb) {
-                const bf16x8 bfr = to_bf16x8(act4<ACT>(acc[2 * kb][cb]), act4<ACT>(acc[2 * kb + 1][cb]));
+                const bf16x8 bfr = ACT == 1 ? relu_bf16x8(to_bf16x8(acc[2 * kb][cb], acc[2 * kb + 1][cb]))
+                                            : to_bf16x8(act4<ACT>(acc[2 * kb][cb]),
+                                                        act4<ACT>(acc[2 * kb + 1][cb]));
                 z[cb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr, z[cb][0], 0, 0, 0);
             }
         }
@@ -457,16 +561,18 @@ __device__ void wide_epilogue(const WideArgs &a, char *smem, int r, int col, int
     }
     // the upper hidden half hands its partial logits to the lower half
     float *zx = reinterpret_cast<float *>(smem + zx_off);
-    float *mine = zx + (size_t)sh * 64 * 32 + lane * 32;
+    // (block cb of the 64 lanes' 16-byte partials is contiguous: consecutive
+    // lanes hit consecutive bank groups)
+    float *mine = zx + ((size_t)sh * 8 * 64 + lane) * 4;
     if (nh == 1) {
 #pragma unroll
-        for (int cb = 0; cb < 8; ++cb) *reinterpret_cast<floatx4 *>(mine + 4 * cb) = z[cb][0];
+        for (int cb = 0; cb < 8; ++cb) *reinterpret_cast<floatx4 *>(mine + cb * 64 * 4) = z[cb][0];
     }
     lds_barrier();
     if (nh == 0) {
 #pragma unroll
         for (int cb = 0; cb < 8; ++cb) {
-            const floatx4 o = *reinterpret_cast<const floatx4 *>(mine + 4 * cb);
+            const floatx4 o = *reinterpret_cast<const floatx4 *>(mine + cb * 64 * 4);
 #pragma unroll
             for (int v = 0; v < 4; ++v) z[cb][0][v] = z[cb][0][v] + o[v] + w2.b2[v];
         }
@@ -491,7 +597,7 @@ __device__ void wide_epilogue(const WideArgs &a, char *smem, int r, int col, int
 #pragma unroll
             for (int e = 0; e < 4; ++e) zz[4 * q4 + e] = v[e];
         }
-        ls = sample_loss(a, s, label, zz);
+        ls = sample_loss<BF>(a, s, label, zz);
     }
     // fixed-order reduction: wavefront butterfly, then the four wavefronts in order
 #pragma unroll
@@ -607,16 +713,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     it.setup();
     const int ntiles = it.count();
     if (ntiles == 0) return;
-    const int Q = ntiles * a.nk;          // K steps of this block; nk is even
-    // prologue: steps 0..3 into stages 0..3, then the fragments of step 0
+    // K steps of this block: nk is even and at least STAGES, so the look-ahead
+    // of a step lies in its own tile or the next one
+    const PipeLane L = pipe_lane(wave, lane, nh, sh);
+    Look lk;
+    look_set(a, it, 0, ntiles, lk);
+    // prologue: steps 0..3 of tile 0 into stages 0..3, then the fragments of step 0
 #pragma unroll
     for (int s = 0; s < PipeCfg::STAGES; ++s) {
-        const int qq = s < Q ? s : Q - 1;
-        int r, col;
-        it.tile(qq / a.nk, &r, &col);
 #pragma unroll
         for (int t = 0; t < C::LOADS; ++t)
-            pipe_issue_one(a, smem + s * PipeCfg::STAGEB, r, col, qq % a.nk, wave, lane, t);
+            pipe_issue_one(lk.wcur + (size_t)s * C::TILEB, lk.xcur + (size_t)s * C::TILEB,
+                           smem + s * PipeCfg::STAGEB, L, t);
     }
     {
         constexpr int n3 = 3 * PipeCfg::LOADS;
@@ -626,31 +734,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         cfence();
     }
     bf16x8 fa[2][8], fb[2][8];
-#pragma unroll
-    for (int rb = 0; rb < 8; ++rb) {
-        const int rowb = 128 * sh + 16 * rb + n;
-        fb[0][rb] = lds_read16(smem + C::TILEB + rowb * C::ROWB + ((g ^ wide_swz(rowb, 4)) << 4));
-        const int rowa = 128 * nh + 16 * rb + n;
-        fa[0][rb] = lds_read16(smem + rowa * C::ROWB + ((g ^ wide_swz(rowa, 4)) << 4));
+    {
+        const uint32_t st0 = (uint32_t)(uintptr_t)(lds_void_t *)smem;
+        pipe_read_rb<0>(st0, L, fa[0][0], fb[0][0]);
+        pipe_read_rb<1>(st0, L, fa[0][1], fb[0][1]);
+        pipe_read_rb<2>(st0, L, fa[0][2], fb[0][2]);
+        pipe_read_rb<3>(st0, L, fa[0][3], fb[0][3]);
+        pipe_read_rb<4>(st0, L, fa[0][4], fb[0][4]);
+        pipe_read_rb<5>(st0, L, fa[0][5], fb[0][5]);
+        pipe_read_rb<6>(st0, L, fa[0][6], fb[0][6]);
+        pipe_read_rb<7>(st0, L, fa[0][7], fb[0][7]);
     }
     lgkm_wait_all(fa[0], fb[0]);
     for (int i = 0; i < ntiles; ++i) {
         int r, col;
         it.tile(i, &r, &col);
+        if (i > 0) look_set(a, it, i, ntiles, lk);
         floatx4 acc[8][8];
-#pragma unroll
-        for (int rb = 0; rb < 8; ++rb)
-#pragma unroll
-            for (int cb = 0; cb < 8; ++cb) acc[rb][cb] = zero4();
-        mfma_acc_sync(acc);
         // the epilogue's global inputs are fetched at the start of the tile
         W2Frag<true> w2;
         w2_load<true>(a, r, nh, n, g, w2);
         const int label = tile_label(a, col, wave, lane);
         const int qbase = i * a.nk;
-        for (int kt = 0; kt < a.nk; kt += 2) {
-            pipe_step<0>(a, smem, it, qbase + kt, Q, wave, lane, nh, sh, n, g, acc, fa, fb);
-            pipe_step<1>(a, smem, it, qbase + kt + 1, Q, wave, lane, nh, sh, n, g, acc, fa, fb);
+        pipe_step<0, true>(a, smem, lk, 0, qbase, L, acc, fa, fb);
+        pipe_step<1>(a, smem, lk, 1, qbase + 1, L, acc, fa, fb);
+        for (int kt = 2; kt < a.nk; kt += 2) {
+            pipe_step<0>(a, smem, lk, kt, qbase + kt, L, acc, fa, fb);
+            pipe_step<1>(a, smem, lk, kt + 1, qbase + kt + 1, L, acc, fa, fb);
         }
         mfma_acc_sync(acc);
         wide_epilogue<true, ACT>(a, smem, r, col, wave, lane, acc, w2, red, label, PipeCfg::ZX);

@@ -203,7 +203,10 @@ bool wide_applicable(const Net &net)
 int wide_kp(const Net &net)
 {
     const int step = net.bf16 ? WideCfg<true>::KMULT : WideCfg<false>::KMULT;
-    return (net.fi[0] + 1 + step - 1) / step * step;
+    const int kp = (net.fi[0] + 1 + step - 1) / step * step;
+    // the BF16 pipeline looks STAGES K steps ahead within a tile and the next
+    const int kmin = net.bf16 ? PipeCfg::STAGES * WT_K : 0;
+    return kp > kmin ? kp : kmin;
 }
 
 size_t wide_row_bytes(const Net &net)
