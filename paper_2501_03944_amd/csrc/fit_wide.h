@@ -84,7 +84,7 @@ struct WideCfg {
     static constexpr int ZX = STAGES * STAGEB;             // logits exchange area
     static constexpr int ZXB = WT_N * ZP * 4;              // logits of the tile's samples
     static constexpr int LDS = ZX + ZXB;
-    static constexpr int KMULT = BF ? 2 * WT_K : STAGES * WT_K;   // padded K is a multiple
+    static constexpr int KMULT = BF ? WT_K : STAGES * WT_K;       // padded K is a multiple
 };
 
 // BF16 software pipeline: a 4-stage ring; fragments of the next step are read
@@ -355,6 +355,23 @@ __device__ __forceinline__ void pipe_step(const WideArgs &a, char *smem, const L
                                                                           PipeCfg::STAGEB);
     pipe_rb<P, FIRST, 0>(next, wsrc, xsrc, fill, L, acc, fa, fb);
     lgkm_wait_all(fa[1 - P], fb[1 - P]);
+}
+
+// The K steps of one tile whose first step (global step qbase) uses register
+// set P0: step kt uses set (P0 + kt) & 1, i.e. the parity of its global step,
+// so an odd step count per tile just alternates P0 from tile to tile.
+template <int P0>
+__device__ __forceinline__ void pipe_tile(const WideArgs &a, char *smem, const Look &lk, int qbase,
+                                          const PipeLane &L, floatx4 (&acc)[8][8],
+                                          bf16x8 (&fa)[2][8], bf16x8 (&fb)[2][8])
+{
+    pipe_step<P0, true>(a, smem, lk, 0, qbase, L, acc, fa, fb);
+    int kt = 1;
+    for (; kt + 1 < a.nk; kt += 2) {
+        pipe_step<1 - P0>(a, smem, lk, kt, qbase + kt, L, acc, fa, fb);
+        pipe_step<P0>(a, smem, lk, kt + 1, qbase + kt + 1, L, acc, fa, fb);
+    }
+    if (kt < a.nk) pipe_step<1 - P0>(a, smem, lk, kt, qbase + kt, L, acc, fa, fb);
 }
 
 // MFMAs of one K step on the stage: acc[rb][cb] over this wave's quarter.
@@ -693,7 +710,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 }
 
 // BF16 variant of k_fit_wide with the software pipeline above (same tiles,
-// layout, epilogue and results; the padded K is a multiple of 64).
+// layout, epilogue and results).
 template <int ACT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_fit_wide_pipe(WideArgs a)
 {
@@ -713,8 +730,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     it.setup();
     const int ntiles = it.count();
     if (ntiles == 0) return;
-    // K steps of this block: nk is even and at least STAGES, so the look-ahead
-    // of a step lies in its own tile or the next one
+    // K steps per tile: at least STAGES, so the look-ahead of a step lies in its
+    // own tile or the next one
     const PipeLane L = pipe_lane(wave, lane, nh, sh);
     Look lk;
     look_set(a, it, 0, ntiles, lk);
@@ -756,12 +773,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         w2_load<true>(a, r, nh, n, g, w2);
         const int label = tile_label(a, col, wave, lane);
         const int qbase = i * a.nk;
-        pipe_step<0, true>(a, smem, lk, 0, qbase, L, acc, fa, fb);
-        pipe_step<1>(a, smem, lk, 1, qbase + 1, L, acc, fa, fb);
-        for (int kt = 2; kt < a.nk; kt += 2) {
-            pipe_step<0>(a, smem, lk, kt, qbase + kt, L, acc, fa, fb);
-            pipe_step<1>(a, smem, lk, kt + 1, qbase + kt + 1, L, acc, fa, fb);
-        }
+        if (qbase & 1) pipe_tile<1>(a, smem, lk, qbase, L, acc, fa, fb);
+        else pipe_tile<0>(a, smem, lk, qbase, L, acc, fa, fb);
         mfma_acc_sync(acc);
         wide_epilogue<true, ACT>(a, smem, r, col, wave, lane, acc, w2, red, label, PipeCfg::ZX);
     }

@@ -155,6 +155,9 @@ WIDE_SHAPES = [
     ((100, 7, 2), ("gelu",), "ce", 513),
     ((95, 200, 10), ("identity",), "ce", 1),
     ((784, 256, 10), ("relu",), "ce", 700),
+    # odd K-step count per tile and more tiles than blocks (tiles alternate the
+    # pipeline's register-set parity)
+    ((200, 128, 5), ("relu",), "ce", 2000),
 ]
 
 
