@@ -254,19 +254,31 @@ __device__ __forceinline__ void look_set(const WideArgs &a, const TileIter &it, 
     }
 }
 
-// One wave load (t of LOADS) of the K step whose W and X blocks start at wsrc
-// and xsrc, into an LDS stage: alternately a 1 KiB block of the W tile and of
-// the X tile.  The 16-byte chunks are gathered in swizzled order on the global
-// side and land contiguously in LDS.
+// Wave load T (of LOADS) of the K step whose W and X blocks start at wsrc and
+// xsrc, into an LDS stage: loads 0-3 take this wave's four 1 KiB blocks of the W
+// tile, loads 4-7 those of the X tile.  The 16-byte chunks are gathered in
+// swizzled order on the global side and land contiguously in LDS.  The block is
+// the instruction's immediate offset, which applies to the global and the LDS
+// address alike, so the four loads of a tile share one address register and one
+// LDS base (M0).
+template <int T>
 __device__ __forceinline__ void pipe_issue_one(const char *wsrc, const char *xsrc, char *stage,
-                                               const PipeLane &L, int t)
+                                               const PipeLane &L)
 {
     using C = WideCfg<true>;
-    const int half = t & 1;
-    const int blk = L.woff + (t >> 1) * C::RPL * C::ROWB;
-    const char *src = (half ? xsrc : wsrc) + blk + L.goff;
-    char *dst = stage + half * C::TILEB + blk;
-    __builtin_amdgcn_global_load_lds(src, (lds_void_t *)dst, 16, 0, 0);
+    constexpr int half = T >> 2, blk = (T & 3) * C::RPL * C::ROWB;
+    const char *src = (half ? xsrc : wsrc) + L.woff + L.goff;
+    char *dst = stage + half * C::TILEB + L.woff;
+    __builtin_amdgcn_global_load_lds(src, (lds_void_t *)dst, 16, blk, 0);
+}
+
+// All LOADS wave loads of one K step.
+template <int T = 0>
+__device__ __forceinline__ void pipe_issue_all(const char *wsrc, const char *xsrc, char *stage,
+                                               const PipeLane &L)
+{
+    pipe_issue_one<T>(wsrc, xsrc, stage, L);
+    if constexpr (T + 1 < WideCfg<true>::LOADS) pipe_issue_all<T + 1>(wsrc, xsrc, stage, L);
 }
 
 // 16-byte LDS read at a lane address plus an immediate offset, issued as an
@@ -325,7 +337,7 @@ __device__ __forceinline__ void pipe_rb(uint32_t next, const char *wsrc, const c
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) mfma_step<FIRST>(acc[RB][cb], fa[P][RB], fb[P][cb]);
     __builtin_amdgcn_sched_barrier(0);
-    pipe_issue_one(wsrc, xsrc, fill, L, RB);
+    pipe_issue_one<RB>(wsrc, xsrc, fill, L);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int cb = 4; cb < 8; ++cb) mfma_step<FIRST>(acc[RB][cb], fa[P][RB], fb[P][cb]);
@@ -737,12 +749,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     look_set(a, it, 0, ntiles, lk);
     // prologue: steps 0..3 of tile 0 into stages 0..3, then the fragments of step 0
 #pragma unroll
-    for (int s = 0; s < PipeCfg::STAGES; ++s) {
-#pragma unroll
-        for (int t = 0; t < C::LOADS; ++t)
-            pipe_issue_one(lk.wcur + (size_t)s * C::TILEB, lk.xcur + (size_t)s * C::TILEB,
-                           smem + s * PipeCfg::STAGEB, L, t);
-    }
+    for (int s = 0; s < PipeCfg::STAGES; ++s)
+        pipe_issue_all(lk.wcur + (size_t)s * C::TILEB, lk.xcur + (size_t)s * C::TILEB,
+                       smem + s * PipeCfg::STAGEB, L);
     {
         constexpr int n3 = 3 * PipeCfg::LOADS;
         cfence();
