@@ -40,6 +40,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace mgfwa {
 namespace fit {
 
@@ -259,16 +261,14 @@ template <bool BF, bool WL, int P, int RO, int SCHED = 1>
 __device__ __forceinline__ void layer_x(const FitArgs &a, const WView<BF, WL> &wv, int s0, int n,
                                         int g, floatx4 (&out)[P][RO])
 {
-#pragma unroll
-    for (int p = 0; p < P; ++p)
-#pragma unroll
-        for (int rb = 0; rb < RO; ++rb) out[p][rb] = zero4();
     if constexpr (!BF) {
         const float *xp[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) xp[p] = a.X + (size_t)(s0 + 16 * p + n) * a.in_pad + 4 * g;
         const int nkb = a.in_pad >> 4;
-        for (int kb = 0; kb < nkb; ++kb) {
+        // one K block of 16 columns; the first (FIRST) starts every accumulator
+        // from a zero addend, so no register clearing precedes the layer
+        auto kblock = [&](int kb, auto first) {
             floatx4 bx[P];
 #pragma unroll
             for (int p = 0; p < P; ++p) bx[p] = *reinterpret_cast<const floatx4 *>(xp[p] + 16 * kb);
@@ -282,11 +282,18 @@ __device__ __forceinline__ void layer_x(const FitArgs &a, const WView<BF, WL> &w
                 for (int v = 0; v < 4; ++v)
 #pragma unroll
                     for (int p = 0; p < P; ++p)
-                        out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[v], bx[p][v], out[p][rb], 0, 0, 0);
+                        out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            aw[v], bx[p][v], decltype(first)::value && v == 0 ? zero4() : out[p][rb], 0, 0, 0);
                 aw = an;
             }
-        }
+        };
+        kblock(0, std::true_type());
+        for (int kb = 1; kb < nkb; ++kb) kblock(kb, std::false_type());
     } else {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int rb = 0; rb < RO; ++rb) out[p][rb] = zero4();
         // lane (n, g) element e: k = 32kb + 4g + e (e < 4), 32kb + 16 + 4g + e - 4 (e >= 4)
         const uint16_t *xp[P];
 #pragma unroll
@@ -319,10 +326,6 @@ template <bool BF, bool WL, int P, int RI, int RO, int SCHED = 1>
 __device__ __forceinline__ void layer_h(const WView<BF, WL> &wv, const floatx4 (&in)[P][RI],
                                         floatx4 (&out)[P][RO])
 {
-#pragma unroll
-    for (int p = 0; p < P; ++p)
-#pragma unroll
-        for (int rb = 0; rb < RO; ++rb) out[p][rb] = zero4();
     if constexpr (!BF) {
         // fragments of (kb, rb) in order; the next one is fetched before the
         // current one's MFMAs so the LDS latency overlaps matrix work
@@ -342,11 +345,17 @@ __device__ __forceinline__ void layer_h(const WView<BF, WL> &wv, const floatx4 (
                 for (int v = 0; v < 4; ++v)
 #pragma unroll
                     for (int p = 0; p < P; ++p)
-                        out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[v], in[p][kb][v], out[p][rb], 0, 0, 0);
+                        // the first K block starts from a zero addend (no clearing)
+                        out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            aw[v], in[p][kb][v], kb == 0 && v == 0 ? zero4() : out[p][rb], 0, 0, 0);
                 aw = an;
             }
         }
     } else {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int rb = 0; rb < RO; ++rb) out[p][rb] = zero4();
         constexpr int NKB = (RI + 1) / 2;
         const int nkb = WL ? NKB : ((wv.fi + 31) >> 5 < NKB ? (wv.fi + 31) >> 5 : NKB);
         bf16x8 aw = wv.b16(0, 0);
