@@ -257,17 +257,28 @@ __device__ __forceinline__ void stage_weights(const FitArgs &a, const float *w, 
 }
 
 // ---- first layer: B operand from the packed samples ------------------------
+// SCHED bit 0: fetch the next row block's weight fragment before the current
+// block's MFMAs (else right before use); bit 1: the first K block multiplies
+// with a zero addend instead of clearing the accumulators first (fewer
+// instructions, but more registers in most instances: enabled only where it
+// measured faster).
 template <bool BF, bool WL, int P, int RO, int SCHED = 1>
 __device__ __forceinline__ void layer_x(const FitArgs &a, const WView<BF, WL> &wv, int s0, int n,
                                         int g, floatx4 (&out)[P][RO])
 {
+    constexpr bool PF = (SCHED & 1) != 0, ZA = (SCHED & 2) != 0;
+    if constexpr (!ZA) {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int rb = 0; rb < RO; ++rb) out[p][rb] = zero4();
+    }
     if constexpr (!BF) {
         const float *xp[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) xp[p] = a.X + (size_t)(s0 + 16 * p + n) * a.in_pad + 4 * g;
         const int nkb = a.in_pad >> 4;
-        // one K block of 16 columns; the first (FIRST) starts every accumulator
-        // from a zero addend, so no register clearing precedes the layer
+        // one K block of 16 columns; FIRST: zero addend
         auto kblock = [&](int kb, auto first) {
             floatx4 bx[P];
 #pragma unroll
@@ -275,9 +286,8 @@ __device__ __forceinline__ void layer_x(const FitArgs &a, const WView<BF, WL> &w
             floatx4 aw = wv.f32(0, kb);
 #pragma unroll
             for (int rb = 0; rb < RO; ++rb) {
-                // fetch the next block's fragment before this block's MFMAs
-                const floatx4 an = SCHED && rb + 1 < RO ? wv.f32(rb + 1, kb) : aw;
-                if constexpr (!SCHED) aw = wv.f32(rb, kb);
+                const floatx4 an = PF && rb + 1 < RO ? wv.f32(rb + 1, kb) : aw;
+                if constexpr (!PF) aw = wv.f32(rb, kb);
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -287,19 +297,36 @@ __device__ __forceinline__ void layer_x(const FitArgs &a, const WView<BF, WL> &w
                 aw = an;
             }
         };
-        kblock(0, std::true_type());
-        for (int kb = 1; kb < nkb; ++kb) kblock(kb, std::false_type());
+        if constexpr (ZA) {
+            kblock(0, std::true_type());
+            for (int kb = 1; kb < nkb; ++kb) kblock(kb, std::false_type());
+        } else {
+            for (int kb = 0; kb < nkb; ++kb) {
+                floatx4 bx[P];
+#pragma unroll
+                for (int p = 0; p < P; ++p) bx[p] = *reinterpret_cast<const floatx4 *>(xp[p] + 16 * kb);
+                floatx4 aw = wv.f32(0, kb);
+#pragma unroll
+                for (int rb = 0; rb < RO; ++rb) {
+                    // fetch the next block's fragment before this block's MFMAs
+                    const floatx4 an = PF && rb + 1 < RO ? wv.f32(rb + 1, kb) : aw;
+                    if constexpr (!PF) aw = wv.f32(rb, kb);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+#pragma unroll
+                        for (int p = 0; p < P; ++p)
+                            out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[v], bx[p][v], out[p][rb], 0, 0, 0);
+                    aw = an;
+                }
+            }
+        }
     } else {
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-#pragma unroll
-            for (int rb = 0; rb < RO; ++rb) out[p][rb] = zero4();
         // lane (n, g) element e: k = 32kb + 4g + e (e < 4), 32kb + 16 + 4g + e - 4 (e >= 4)
         const uint16_t *xp[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) xp[p] = a.Xb + (size_t)(s0 + 16 * p + n) * a.in_pad + 4 * g;
         const int nkb = a.in_pad >> 5;
-        for (int kb = 0; kb < nkb; ++kb) {
+        auto kblock = [&](int kb, auto first) {
             bf16x8 bx[P];
 #pragma unroll
             for (int p = 0; p < P; ++p) {
@@ -310,12 +337,37 @@ __device__ __forceinline__ void layer_x(const FitArgs &a, const WView<BF, WL> &w
             bf16x8 aw = wv.b16(0, kb);
 #pragma unroll
             for (int rb = 0; rb < RO; ++rb) {
-                const bf16x8 an = SCHED && rb + 1 < RO ? wv.b16(rb + 1, kb) : aw;
-                if constexpr (!SCHED) aw = wv.b16(rb, kb);
+                const bf16x8 an = PF && rb + 1 < RO ? wv.b16(rb + 1, kb) : aw;
+                if constexpr (!PF) aw = wv.b16(rb, kb);
 #pragma unroll
                 for (int p = 0; p < P; ++p)
-                    out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bx[p], out[p][rb], 0, 0, 0);
+                    out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        aw, bx[p], decltype(first)::value ? zero4() : out[p][rb], 0, 0, 0);
                 aw = an;
+            }
+        };
+        if constexpr (ZA) {
+            kblock(0, std::true_type());
+            for (int kb = 1; kb < nkb; ++kb) kblock(kb, std::false_type());
+        } else {
+            for (int kb = 0; kb < nkb; ++kb) {
+                bf16x8 bx[P];
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const uint2 lo = *reinterpret_cast<const uint2 *>(xp[p] + 32 * kb);
+                    const uint2 hi = *reinterpret_cast<const uint2 *>(xp[p] + 32 * kb + 16);
+                    bx[p] = __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+                }
+                bf16x8 aw = wv.b16(0, kb);
+#pragma unroll
+                for (int rb = 0; rb < RO; ++rb) {
+                    const bf16x8 an = PF && rb + 1 < RO ? wv.b16(rb + 1, kb) : aw;
+                    if constexpr (!PF) aw = wv.b16(rb, kb);
+#pragma unroll
+                    for (int p = 0; p < P; ++p)
+                        out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bx[p], out[p][rb], 0, 0, 0);
+                    aw = an;
+                }
             }
         }
     }
@@ -326,6 +378,13 @@ template <bool BF, bool WL, int P, int RI, int RO, int SCHED = 1>
 __device__ __forceinline__ void layer_h(const WView<BF, WL> &wv, const floatx4 (&in)[P][RI],
                                         floatx4 (&out)[P][RO])
 {
+    constexpr bool PF = (SCHED & 1) != 0, ZA = (SCHED & 2) != 0;
+    if constexpr (!ZA) {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int rb = 0; rb < RO; ++rb) out[p][rb] = zero4();
+    }
     if constexpr (!BF) {
         // fragments of (kb, rb) in order; the next one is fetched before the
         // current one's MFMAs so the LDS latency overlaps matrix work
@@ -338,24 +397,19 @@ __device__ __forceinline__ void layer_h(const WView<BF, WL> &wv, const floatx4 (
 #pragma unroll
             for (int rb = 0; rb < RO; ++rb) {
                 floatx4 an = aw;
-                if constexpr (!SCHED) aw = wv.f32(rb, kb);
+                if constexpr (!PF) aw = wv.f32(rb, kb);
                 else if (rb + 1 < RO) an = wv.f32(rb + 1, kb);
                 else if (kb + 1 < nkb) an = wv.f32(0, kb + 1);
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
 #pragma unroll
                     for (int p = 0; p < P; ++p)
-                        // the first K block starts from a zero addend (no clearing)
                         out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                            aw[v], in[p][kb][v], kb == 0 && v == 0 ? zero4() : out[p][rb], 0, 0, 0);
+                            aw[v], in[p][kb][v], ZA && kb == 0 && v == 0 ? zero4() : out[p][rb], 0, 0, 0);
                 aw = an;
             }
         }
     } else {
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-#pragma unroll
-            for (int rb = 0; rb < RO; ++rb) out[p][rb] = zero4();
         constexpr int NKB = (RI + 1) / 2;
         const int nkb = WL ? NKB : ((wv.fi + 31) >> 5 < NKB ? (wv.fi + 31) >> 5 : NKB);
         bf16x8 aw = wv.b16(0, 0);
@@ -372,12 +426,13 @@ __device__ __forceinline__ void layer_h(const WView<BF, WL> &wv, const floatx4 (
 #pragma unroll
             for (int rb = 0; rb < RO; ++rb) {
                 bf16x8 an = aw;
-                if constexpr (!SCHED) aw = wv.b16(rb, kb);
+                if constexpr (!PF) aw = wv.b16(rb, kb);
                 else if (rb + 1 < RO) an = wv.b16(rb + 1, kb);
                 else if (kb + 1 < nkb) an = wv.b16(0, kb + 1);
 #pragma unroll
                 for (int p = 0; p < P; ++p)
-                    out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bx[p], out[p][rb], 0, 0, 0);
+                    out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        aw, bx[p], ZA && kb == 0 ? zero4() : out[p][rb], 0, 0, 0);
                 aw = an;
             }
         }

@@ -11,9 +11,10 @@ const KernelEntry kEntries[] = {
     FIT_ENTRY_ACT(true, true, 4, 4, 2, 2, 1, 0, 0),
     // 64-128-128-10 ReLU: weights in LDS.  Measured best: FP32 with 8
     // wavefronts x 2 slabs and fragments fetched right before use; BF16 with
-    // 4 wavefronts x 4 slabs (more A-fragment reuse per LDS read)
-    FIT_ENTRY_SCHED(false, true, 8, 2, 1, 0, 8, 8, 1, 0),
-    FIT_ENTRY_SCHED(true, true, 4, 4, 1, 1, 8, 8, 1, 0),
+    // 4 wavefronts x 4 slabs (more A-fragment reuse per LDS read); both with
+    // zero-addend first K blocks (SCHED bit 1)
+    FIT_ENTRY_SCHED(false, true, 8, 2, 1, 2, 8, 8, 1, 0),
+    FIT_ENTRY_SCHED(true, true, 4, 4, 1, 3, 8, 8, 1, 0),
     // 784-256-10 ReLU: the first layer does not fit in LDS
     FIT_ENTRY_ACT(false, false, 4, 2, 1, 16, 1, 0, 0),
     FIT_ENTRY_ACT(true, false, 4, 2, 1, 16, 1, 0, 0),

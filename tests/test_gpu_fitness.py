@@ -158,6 +158,9 @@ WIDE_SHAPES = [
     # odd K-step count per tile and more tiles than blocks (tiles alternate the
     # pipeline's register-set parity)
     ((200, 128, 5), ("relu",), "ce", 2000),
+    # the fewest K steps per tile (BF16: 4, so every look-ahead load crosses
+    # into the next tile) and more tiles than blocks
+    ((100, 64, 4), ("relu",), "mse", 2000),
 ]
 
 
