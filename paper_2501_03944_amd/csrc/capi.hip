@@ -349,7 +349,7 @@ OutMap expl_map(const Shape &s)
 
 mgfwa_status fit_rows(mgfwa_ctx *c, const FitPlan &plan, const float *W, size_t ld, int rows,
                       OutMap map, float *out, hipStream_t st, hipEvent_t mid = nullptr,
-                      hipEvent_t pre = nullptr)
+                      hipEvent_t pre = nullptr, int prepacked = 0)
 {
     if (c->input) {
         STEP(launch_net_input(c->in, plan.net_shape, c->d.Pnet, W, ld, rows, map, out, c->d.H0,
@@ -357,7 +357,8 @@ mgfwa_status fit_rows(mgfwa_ctx *c, const FitPlan &plan, const float *W, size_t 
              "fitness_input");
         if (mid) STEP(hipEventRecord(mid, st), "event");
     } else if (c->net.wide)
-        STEP(launch_fitness_wide(c->net, c->d, W, ld, rows, map, out, st, mid, pre), "fitness_wide");
+        STEP(launch_fitness_wide(c->net, c->d, W, ld, rows, map, out, st, mid, pre, prepacked),
+             "fitness_wide");
     else
         STEP(launch_fitness(c->net, plan, c->d, W, ld, rows, map, out, st, mid), "fitness");
     return MGFWA_OK;
@@ -392,11 +393,13 @@ mgfwa_status enqueue_generation(mgfwa_ctx *c, hipStream_t st, hipEvent_t *ev)
         STEP(launch_rank(s, c->d, st), "rank");
         STEP(launch_guide(s, c->d, st), "guide");
     }
-    STEP(launch_explode(s, c->d, st), "explode");
+    // wide fitness kernel: the explosion also writes the sparks' packed rows
+    const WidePack wp = c->net.wide ? wide_pack_geometry(c->net, c->d) : WidePack{};
+    STEP(launch_explode(s, c->d, st, c->net.wide ? &wp : nullptr), "explode");
     if (ev) STEP(hipEventRecord(ev[1], st), "event");
     mgfwa_status r = fit_rows(c, c->plan_expl, c->d.SE, s.Dp, s.BN * expl_rows(s), expl_map(s),
                               c->d.Yc, st, ev ? ev[6] : nullptr,
-                              ev && c->net.wide ? ev[7] : nullptr);
+                              ev && c->net.wide ? ev[7] : nullptr, c->net.wide ? s.BN * s.lam : 0);
     if (r) return r;
     if (ev) STEP(hipEventRecord(ev[2], st), "event");
     if (!s.lag) {
@@ -583,6 +586,11 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
         if (r) return bail(r);
         if (c->net.wide) {
             r = check(c, launch_pack_wide_x(c->net, problem->x_dev, d.Xw, c->stream), "pack_x");
+            if (r) return bail(r);
+            // the explosion writes only the parameters of its packed rows: the
+            // padding must read as zero
+            r = check(c, hipMemsetAsync(d.Wpack, 0, (size_t)L.partial_rows * wide_row_bytes(c->net),
+                                        c->stream), "zero Wpack");
             if (r) return bail(r);
         }
     }

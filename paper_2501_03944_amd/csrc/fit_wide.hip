@@ -238,28 +238,52 @@ hipError_t launch_pack_wide_x(const Net &net, const float *x, char *Xw, hipStrea
     return hipGetLastError();
 }
 
+WidePack wide_pack_geometry(const Net &net, const DevState &d)
+{
+    static_assert(WT_M == 256 && WT_K == 32, "wide_pack_offset assumes 256 x 32 K blocks");
+    WidePack p;
+    p.Wp = d.Wpack;
+    p.pr = wide_row_bytes(net);
+    p.in = net.fi[0];
+    p.hid = net.fo[0];
+    p.out = net.fo[1];
+    p.Kp = wide_kp(net);
+    p.bf16 = net.bf16;
+    p.woff1 = net.woff[0];
+    p.boff1 = net.boff[0];
+    p.woff2 = net.woff[1];
+    p.boff2 = net.boff[1];
+    return p;
+}
+
 hipError_t launch_fitness_wide(const Net &net, const DevState &d, const float *W, size_t ld,
                                int rows, OutMap map, float *out, hipStream_t st, hipEvent_t mid,
-                               hipEvent_t pre)
+                               hipEvent_t pre, int prepacked)
 {
     if (rows <= 0) return hipSuccess;
     const int Kp = wide_kp(net);
     const size_t pr = wide_row_bytes(net);
-    const int es = net.bf16 ? 2 : 4, epc = 16 / es;
-    const int nchunk = WT_M * Kp / epc + 16 * WT_M / epc + 4;
-    const int rgroups = (rows + PACK_RPB - 1) / PACK_RPB;
-    dim3 pg((nchunk + TPB * PACK_CPT - 1) / (TPB * PACK_CPT),
-            rgroups < MAX_GRID_Y ? rgroups : MAX_GRID_Y);
-    if (net.bf16)
-        hipLaunchKernelGGL(k_pack_wide_rows<true>, pg, dim3(TPB), 0, st, W, ld, rows, d.Wpack, pr,
-                           net.fi[0], net.fo[0], net.fo[1], Kp, net.woff[0], net.boff[0],
-                           net.woff[1], net.boff[1]);
-    else
-        hipLaunchKernelGGL(k_pack_wide_rows<false>, pg, dim3(TPB), 0, st, W, ld, rows, d.Wpack, pr,
-                           net.fi[0], net.fo[0], net.fo[1], Kp, net.woff[0], net.boff[0],
-                           net.woff[1], net.boff[1]);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    const int npack = rows - prepacked;
+    if (npack > 0) {
+        const int es = net.bf16 ? 2 : 4, epc = 16 / es;
+        const int nchunk = WT_M * Kp / epc + 16 * WT_M / epc + 4;
+        const int rgroups = (npack + PACK_RPB - 1) / PACK_RPB;
+        dim3 pg((nchunk + TPB * PACK_CPT - 1) / (TPB * PACK_CPT),
+                rgroups < MAX_GRID_Y ? rgroups : MAX_GRID_Y);
+        const float *Wsrc = W + (size_t)prepacked * ld;
+        char *Wdst = d.Wpack + (size_t)prepacked * pr;
+        if (net.bf16)
+            hipLaunchKernelGGL(k_pack_wide_rows<true>, pg, dim3(TPB), 0, st, Wsrc, ld, npack, Wdst, pr,
+                               net.fi[0], net.fo[0], net.fo[1], Kp, net.woff[0], net.boff[0],
+                               net.woff[1], net.boff[1]);
+        else
+            hipLaunchKernelGGL(k_pack_wide_rows<false>, pg, dim3(TPB), 0, st, Wsrc, ld, npack, Wdst,
+                               pr, net.fi[0], net.fo[0], net.fo[1], Kp, net.woff[0], net.boff[0],
+                               net.woff[1], net.boff[1]);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (pre) {                          // packing done: the GEMM kernel starts here
         e = hipEventRecord(pre, st);
         if (e != hipSuccess) return e;

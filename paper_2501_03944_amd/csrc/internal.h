@@ -108,10 +108,52 @@ struct FitPlan {
     int net_shape = -1;   // input problems: NET_* kernel shape (-1 chosen per launch)
 };
 
+// The wide fitness kernel's packed spark rows, for the explosion kernel to
+// write each spark there as well (the fitness launch then skips packing them).
+// Row layout (fit_wide.hip): W1 with b1 as column `in`, K-blocked as
+// [Kp/32][256][32]; W2 [16][256] (BF16: each 32-column block in MFMA lane
+// order); b2 [16] FP32.  Padding stays zero from initialisation.
+struct WidePack {
+    char *Wp;                           // packed rows
+    size_t pr;                          // row pitch (bytes)
+    int in, hid, out, Kp, bf16;
+    int woff1, boff1, woff2, boff2;     // parameter offsets inside a spark
+};
+
+// Byte offset of spark coordinate j (< D) in its packed row; *f32 is set when
+// the element is stored as FP32 whatever the precision (b2).
+__device__ __forceinline__ size_t wide_pack_offset(const WidePack &p, int j, bool *f32)
+{
+    const size_t es = p.bf16 ? 2 : 4;
+    *f32 = false;
+    int o, k;
+    if (j >= p.woff1 && j < p.woff1 + p.hid * p.in) {
+        const int rel = j - p.woff1;
+        o = rel / p.in;
+        k = rel - o * p.in;
+    } else if (j >= p.boff1 && j < p.boff1 + p.hid) {
+        o = j - p.boff1;
+        k = p.in;
+    } else if (j >= p.woff2 && j < p.woff2 + p.out * p.hid) {
+        const int rel = j - p.woff2, i = rel / p.hid, c = rel - i * p.hid;
+        int pos = c;
+        if (p.bf16) {
+            const int r = c & 31;
+            pos = (c & ~31) + (r < 16 ? (r >> 2) * 8 + (r & 3) : ((r - 16) >> 2) * 8 + 4 + (r & 3));
+        }
+        return (size_t)256 * p.Kp * es + ((size_t)i * 256 + pos) * es;
+    } else {
+        *f32 = true;
+        return (size_t)256 * p.Kp * es + (size_t)16 * 256 * es + (size_t)(j - p.boff2) * 4;
+    }
+    return (((size_t)(k >> 5) * 256 + o) * 32 + (k & 31)) * es;
+}
+
 // ---- spark.hip
 hipError_t launch_init_positions(const Shape &s, const DevState &d, hipStream_t st);
 hipError_t launch_pop_range(const Shape &s, const DevState &d, hipStream_t st);
-hipError_t launch_explode(const Shape &s, const DevState &d, hipStream_t st);
+hipError_t launch_explode(const Shape &s, const DevState &d, hipStream_t st,
+                          const WidePack *wp = nullptr);
 
 // ---- guide.hip
 hipError_t launch_rank(const Shape &s, const DevState &d, hipStream_t st);
@@ -171,9 +213,12 @@ size_t wide_row_bytes(const Net &net);
 int wide_lds_bytes(const Net &net);
 hipError_t wide_prepare(const Net &net);
 hipError_t launch_pack_wide_x(const Net &net, const float *x, char *Xw, hipStream_t st);
+// prepacked: the first rows are already in d.Wpack (written by the explosion)
 hipError_t launch_fitness_wide(const Net &net, const DevState &d, const float *W, size_t ld,
                                int rows, OutMap map, float *out, hipStream_t st,
-                               hipEvent_t mid = nullptr, hipEvent_t pre = nullptr);
+                               hipEvent_t mid = nullptr, hipEvent_t pre = nullptr,
+                               int prepacked = 0);
+WidePack wide_pack_geometry(const Net &net, const DevState &d);
 
 // Record the message returned by mgfwa_last_error (printf format) and return code.
 mgfwa_status fail(mgfwa_status code, const char *fmt, ...);

@@ -60,13 +60,48 @@ __global__ __launch_bounds__(TPB) void k_pop_range(const float *__restrict__ F, 
 // Explosion spark j of firework f (row = f*lambda + j) for generation t+1:
 // s = fma(A_f, 2u - 1, x_f); out-of-box coordinates take a uniform draw from
 // the mapping stream of the same (chunk, row, generation).
+// With PACK the spark is also written in the wide fitness kernel's packed
+// layout (row `row` of wp.Wp): four coordinates of one W1 row inside one
+// 32-column block (the common case) as one store, others one by one.
+template <bool BF>
+__device__ __forceinline__ void pack_four(const WidePack &wp, int row, int j0, int D,
+                                          const float (&s)[4])
+{
+    char *dst = wp.Wp + (size_t)row * wp.pr;
+    const int rel = j0 - wp.woff1;
+    if (j0 >= wp.woff1 && j0 + 3 < wp.woff1 + wp.hid * wp.in && rel % wp.in + 3 < wp.in &&
+        (rel % wp.in & 31) <= 28 && (rel % wp.in & 3) == 0) {
+        bool f32;
+        const size_t off = wide_pack_offset(wp, j0, &f32);
+        if constexpr (BF) {
+            const uint32_t lo = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)s[0]) |
+                                ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)s[1]) << 16);
+            const uint32_t hi = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)s[2]) |
+                                ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)s[3]) << 16);
+            *reinterpret_cast<uint2 *>(dst + off) = make_uint2(lo, hi);
+        } else {
+            *reinterpret_cast<float4 *>(dst + off) = make_float4(s[0], s[1], s[2], s[3]);
+        }
+        return;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        if (j0 + e >= D) break;
+        bool f32;
+        const size_t off = wide_pack_offset(wp, j0 + e, &f32);
+        if (BF && !f32) *reinterpret_cast<uint16_t *>(dst + off) = __builtin_bit_cast(uint16_t, (__bf16)s[e]);
+        else *reinterpret_cast<float *>(dst + off) = s[e];
+    }
+}
+
+template <int PACK>   // 0: no packing, 1: FP32 packed rows, 2: BF16
 __global__ __launch_bounds__(TPB) void k_explode(const float *__restrict__ F,
                                                  const float *__restrict__ A,
                                                  float *__restrict__ SE, int lam, int rows, int D,
                                                  int Dp, uint2 key, Box box,
                                                  const int32_t *__restrict__ ctrl, int N,
                                                  const float *__restrict__ lo,
-                                                 const float *__restrict__ hi)
+                                                 const float *__restrict__ hi, WidePack wp)
 {
     if (ctrl[CTRL_DONE]) return;
     const uint32_t tn = (uint32_t)ctrl[CTRL_GEN] + 1u;
@@ -100,6 +135,8 @@ __global__ __launch_bounds__(TPB) void k_explode(const float *__restrict__ F,
         for (int e = 0; e < 4; ++e)
             if (4 * chunk + e >= D) s[e] = 0.0f;
         reinterpret_cast<float4 *>(SE + (size_t)row * Dp)[chunk] = make_float4(s[0], s[1], s[2], s[3]);
+        if constexpr (PACK != 0)
+            if (4 * chunk < D) pack_four<PACK == 2>(wp, row, 4 * chunk, D, s);
     }
 }
 
@@ -129,15 +166,18 @@ hipError_t launch_pop_range(const Shape &s, const DevState &d, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_explode(const Shape &s, const DevState &d, hipStream_t st)
+hipError_t launch_explode(const Shape &s, const DevState &d, hipStream_t st, const WidePack *wp)
 {
     const int rows = s.BN * s.lam;
     // 32 or 8 rows per block while there are enough blocks to fill the device
     const long blocks_x = ((s.Dp >> 2) + TPB - 1) / TPB;
     const int rpb = blocks_x * (rows / 32) >= 2048 ? 32 : blocks_x * (rows / 8) >= 2048 ? 8 : 1;
-    hipLaunchKernelGGL(k_explode, row_grid(s.Dp, rows, rpb), dim3(TPB), 0, st, d.F, d.A, d.SE, s.lam,
-                       rows, s.D, s.Dp, s.key, s.box, d.ctrl, s.N, s.map_range ? d.lo : nullptr,
-                       s.map_range ? d.hi : nullptr);
+    const WidePack none{};
+    const WidePack &w = wp ? *wp : none;
+    auto *k = !wp ? &k_explode<0> : wp->bf16 ? &k_explode<2> : &k_explode<1>;
+    hipLaunchKernelGGL(k, row_grid(s.Dp, rows, rpb), dim3(TPB), 0, st, d.F, d.A, d.SE, s.lam, rows,
+                       s.D, s.Dp, s.key, s.box, d.ctrl, s.N, s.map_range ? d.lo : nullptr,
+                       s.map_range ? d.hi : nullptr, w);
     return hipGetLastError();
 }
 

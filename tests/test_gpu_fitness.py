@@ -232,3 +232,36 @@ def test_wide_and_resident_paths_agree_on_state(monkeypatch):
         g.close()
     assert_bits(states[0]["SE"], states[1]["SE"], "sparks")
     assert_fitness_close(states[1]["Yc"], states[0]["Yc"].astype(np.float64), "wide vs resident")
+
+
+@pytest.mark.parametrize("widths,loss,lag", [((40, 64, 5), "ce", False), ((33, 48, 3), "mse", True),
+                                             ((95, 200, 10), "ce", False)])
+def test_wide_bf16_generation_fitness_from_explosion_packing(monkeypatch, widths, loss, lag):
+    """In a generation the explosion kernel writes the wide kernel's packed BF16
+    rows itself (the fitness launch packs only the guiding sparks): every
+    candidate's fitness matches the oracle's loss of the same spark within the
+    BF16 bound."""
+    torch, M = require_gpu()
+    monkeypatch.setenv("MGFWA_FORCE_WIDE", "1")
+    wl = inputs.random_mlp_problem(widths, ("relu",), loss, 300, seed=11)
+    p = O.Problem.from_workload(wl)
+    g = M.MGFWA(wl.widths, wl.acts, wl.loss, wl.x, wl.y, wl.labels, n_fireworks=3, n_sparks=16,
+                n_guiding=2, seed=5, precision="bf16", lag_guiding=lag)
+    D = g.D
+    for gen in range(2):
+        g.step(1)
+        st = g.state_numpy()
+        se, sg = st["SE"][:, :D].astype(np.float64), st["SG"][:, :D].astype(np.float64)
+        got = st["Yc"].astype(np.float64)          # [B*N][lambda + G]
+        want = np.concatenate([p.loss_rows(se).reshape(3, 16), p.loss_rows(sg).reshape(3, 2)],
+                              axis=1)
+        err = np.abs(got - want)
+        bound = 5e-2 * np.abs(want) + 5e-2
+        if loss == "ce":
+            rows = np.concatenate([se, sg])
+            scale = _logit_scale(p, rows, 300)
+            bound = bound + 2.0 ** -6 * np.concatenate([scale[:48].reshape(3, 16),
+                                                        scale[48:].reshape(3, 2)], axis=1)
+        print(f"gen {gen + 1} {widths} lag={lag}: max abs err {err.max():.3e}")
+        assert np.all(err <= bound), f"generation {gen + 1}"
+    g.close()
