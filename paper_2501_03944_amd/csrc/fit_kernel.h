@@ -127,6 +127,19 @@ __device__ __forceinline__ floatx4 ldw4(const float *p, bool row_ok, int kbase, 
     return r;
 }
 
+typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
+
+// ReLU of eight BF16 values as packed 16-bit integer maxima against zero: a
+// non-negative BF16 is a non-negative integer, a negative one (or -0) a negative
+// integer.  Rounding to BF16 keeps the sign, so this equals ReLU before rounding.
+__device__ __forceinline__ bf16x8 relu_bf16x8(bf16x8 v)
+{
+    uintx4 u = __builtin_bit_cast(uintx4, v);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) asm("v_pk_max_i16 %0, %1, 0" : "=v"(u[e]) : "v"(u[e]));
+    return __builtin_bit_cast(bf16x8, u);
+}
+
 __device__ __forceinline__ bf16x8 to_bf16x8(floatx4 lo, floatx4 hi)
 {
     bf16x8 r;
@@ -262,9 +275,9 @@ __device__ __forceinline__ void stage_weights(const FitArgs &a, const float *w, 
 // with a zero addend instead of clearing the accumulators first (fewer
 // instructions, but more registers in most instances: enabled only where it
 // measured faster).
-template <bool BF, bool WL, int P, int RO, int SCHED = 1>
+template <bool BF, bool WL, int P, int RO, int SCHED = 1, bool FOLD = false>
 __device__ __forceinline__ void layer_x(const FitArgs &a, const WView<BF, WL> &wv, int s0, int n,
-                                        int g, floatx4 (&out)[P][RO])
+                                        int g, floatx4 (&out)[P][RO], const floatx4 *c0 = nullptr)
 {
     constexpr bool PF = (SCHED & 1) != 0, ZA = (SCHED & 2) != 0;
     if constexpr (!ZA) {
@@ -342,7 +355,8 @@ __device__ __forceinline__ void layer_x(const FitArgs &a, const WView<BF, WL> &w
 #pragma unroll
                 for (int p = 0; p < P; ++p)
                     out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        aw, bx[p], decltype(first)::value ? zero4() : out[p][rb], 0, 0, 0);
+                        aw, bx[p], decltype(first)::value ? (FOLD ? c0[rb] : zero4()) : out[p][rb],
+                        0, 0, 0);
                 aw = an;
             }
         };
@@ -374,9 +388,9 @@ __device__ __forceinline__ void layer_x(const FitArgs &a, const WView<BF, WL> &w
 }
 
 // ---- later layers: B operand from the previous layer's accumulators ----------
-template <bool BF, bool WL, int P, int RI, int RO, int SCHED = 1>
+template <bool BF, bool WL, int P, int RI, int RO, int SCHED = 1, bool FOLD = false>
 __device__ __forceinline__ void layer_h(const WView<BF, WL> &wv, const floatx4 (&in)[P][RI],
-                                        floatx4 (&out)[P][RO])
+                                        floatx4 (&out)[P][RO], const floatx4 *c0 = nullptr)
 {
     constexpr bool PF = (SCHED & 1) != 0, ZA = (SCHED & 2) != 0;
     if constexpr (!ZA) {
@@ -422,6 +436,7 @@ __device__ __forceinline__ void layer_h(const WView<BF, WL> &wv, const floatx4 (
                 floatx4 hi = zero4();
                 if (2 * kb + 1 < RI) hi = in[p][(2 * kb + 1) < RI ? 2 * kb + 1 : 0];
                 bx[p] = to_bf16x8(in[p][2 * kb], hi);
+                if constexpr (FOLD) bx[p] = relu_bf16x8(bx[p]);
             }
 #pragma unroll
             for (int rb = 0; rb < RO; ++rb) {
@@ -432,7 +447,7 @@ __device__ __forceinline__ void layer_h(const WView<BF, WL> &wv, const floatx4 (
 #pragma unroll
                 for (int p = 0; p < P; ++p)
                     out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        aw, bx[p], ZA && kb == 0 ? zero4() : out[p][rb], 0, 0, 0);
+                        aw, bx[p], ZA && kb == 0 ? (FOLD ? c0[rb] : zero4()) : out[p][rb], 0, 0, 0);
                 aw = an;
             }
         }
@@ -460,14 +475,12 @@ __device__ __forceinline__ void add_act(floatx4 (&h)[P][R], const floatx4 (&bb)[
             for (int v = 0; v < 4; ++v) h[p][rb][v] = act_c<ACT>(h[p][rb][v] + bb[rb][v]);
 }
 
-// Bias then activation of layer l.  ACT >= 0 fixes the hidden activation at
-// compile time; ACT < 0 dispatches once per call on the runtime code.
-template <int ACT, bool WL, int P, int R>
-__device__ __forceinline__ void bias_act(const FitArgs &a, const float *w, const char *smem, int l,
-                                         int g, bool apply_act, floatx4 (&h)[P][R])
+// This lane's biases of layer l (rows 16rb + 4g .. +3 of every output block).
+template <bool WL, int R>
+__device__ __forceinline__ void load_bias(const FitArgs &a, const float *w, const char *smem, int l,
+                                          int g, floatx4 (&bb)[R])
 {
     const int fo = a.fo[l];
-    floatx4 bb[R];
 #pragma unroll
     for (int rb = 0; rb < R; ++rb) {
         if constexpr (WL) {
@@ -482,6 +495,16 @@ __device__ __forceinline__ void bias_act(const FitArgs &a, const float *w, const
             }
         }
     }
+}
+
+// Bias then activation of layer l.  ACT >= 0 fixes the hidden activation at
+// compile time; ACT < 0 dispatches once per call on the runtime code.
+template <int ACT, bool WL, int P, int R>
+__device__ __forceinline__ void bias_act(const FitArgs &a, const float *w, const char *smem, int l,
+                                         int g, bool apply_act, floatx4 (&h)[P][R])
+{
+    floatx4 bb[R];
+    load_bias<WL, R>(a, w, smem, l, g, bb);
     if (!apply_act) {
         add_act<0, P, R>(h, bb);
         return;
@@ -620,30 +643,39 @@ __global__ __launch_bounds__(NW * 64) void k_fit(FitArgs a)
         // fence the compiler hoists those reads out of the loop and, short of
         // registers, spills the whole weight fragment set to scratch memory.
         asm volatile("" ::: "memory");
-        floatx4 h1[P][R1];
-        layer_x<BF, WL, P, R1, SCHED>(a, w0, s0, n, g, h1);
+        // FOLD (BF16, zero-addend instances, ReLU): each layer's bias is the
+        // addend of its first K block and the ReLU of a hidden layer is applied
+        // to its BF16-rounded values as the next layer converts them, so no
+        // per-value bias or activation pass runs.
+        constexpr bool FOLD = BF && (SCHED & 2) != 0 && ACT == 1;
+        floatx4 h1[P][R1], c1[R1];
+        if constexpr (FOLD) load_bias<WL, R1>(a, w, smem, 0, g, c1);
+        layer_x<BF, WL, P, R1, SCHED, FOLD>(a, w0, s0, n, g, h1, c1);
         if constexpr (R2 == 0) {
-            bias_act<ACT, WL, P, R1>(a, w, smem, 0, g, false, h1);
+            if constexpr (!FOLD) bias_act<ACT, WL, P, R1>(a, w, smem, 0, g, false, h1);
             lsum += slab_loss<P, R1>(a, 0, s0, n, g, h1);
         } else {
-            bias_act<ACT, WL, P, R1>(a, w, smem, 0, g, true, h1);
-            floatx4 h2[P][R2];
-            layer_h<BF, WL, P, R1, R2, SCHED>(w1, h1, h2);
+            if constexpr (!FOLD) bias_act<ACT, WL, P, R1>(a, w, smem, 0, g, true, h1);
+            floatx4 h2[P][R2], c2[R2];
+            if constexpr (FOLD) load_bias<WL, R2>(a, w, smem, 1, g, c2);
+            layer_h<BF, WL, P, R1, R2, SCHED, FOLD>(w1, h1, h2, c2);
             if constexpr (R3 == 0) {
-                bias_act<ACT, WL, P, R2>(a, w, smem, 1, g, false, h2);
+                if constexpr (!FOLD) bias_act<ACT, WL, P, R2>(a, w, smem, 1, g, false, h2);
                 lsum += slab_loss<P, R2>(a, 1, s0, n, g, h2);
             } else {
-                bias_act<ACT, WL, P, R2>(a, w, smem, 1, g, true, h2);
-                floatx4 h3[P][R3];
-                layer_h<BF, WL, P, R2, R3, SCHED>(w2, h2, h3);
+                if constexpr (!FOLD) bias_act<ACT, WL, P, R2>(a, w, smem, 1, g, true, h2);
+                floatx4 h3[P][R3], c3[R3];
+                if constexpr (FOLD) load_bias<WL, R3>(a, w, smem, 2, g, c3);
+                layer_h<BF, WL, P, R2, R3, SCHED, FOLD>(w2, h2, h3, c3);
                 if constexpr (R4 == 0) {
-                    bias_act<ACT, WL, P, R3>(a, w, smem, 2, g, false, h3);
+                    if constexpr (!FOLD) bias_act<ACT, WL, P, R3>(a, w, smem, 2, g, false, h3);
                     lsum += slab_loss<P, R3>(a, 2, s0, n, g, h3);
                 } else {
-                    bias_act<ACT, WL, P, R3>(a, w, smem, 2, g, true, h3);
-                    floatx4 h4[P][R4];
-                    layer_h<BF, WL, P, R3, R4, SCHED>(w3, h3, h4);
-                    bias_act<ACT, WL, P, R4>(a, w, smem, 3, g, false, h4);
+                    if constexpr (!FOLD) bias_act<ACT, WL, P, R3>(a, w, smem, 2, g, true, h3);
+                    floatx4 h4[P][R4], c4[R4];
+                    if constexpr (FOLD) load_bias<WL, R4>(a, w, smem, 3, g, c4);
+                    layer_h<BF, WL, P, R3, R4, SCHED, FOLD>(w3, h3, h4, c4);
+                    if constexpr (!FOLD) bias_act<ACT, WL, P, R4>(a, w, smem, 3, g, false, h4);
                     lsum += slab_loss<P, R4>(a, 3, s0, n, g, h4);
                 }
             }

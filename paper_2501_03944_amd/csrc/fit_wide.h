@@ -469,19 +469,6 @@ __device__ __forceinline__ void w2_load(const WideArgs &a, int r, int nh, int n,
     w.b2 = *reinterpret_cast<const floatx4 *>(b2 + 4 * g);
 }
 
-typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
-
-// ReLU of eight BF16 values as packed 16-bit integer maxima against zero: a
-// non-negative BF16 is a non-negative integer, a negative one (or -0) a negative
-// integer.  Rounding to BF16 keeps the sign, so this equals ReLU before rounding.
-__device__ __forceinline__ bf16x8 relu_bf16x8(bf16x8 v)
-{
-    uintx4 u = __builtin_bit_cast(uintx4, v);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) asm("v_pk_max_i16 %0, %1, 0" : "=v"(u[e]) : "v"(u[e]));
-    return __builtin_bit_cast(bf16x8, u);
-}
-
 template <int ACT>
 __device__ __forceinline__ floatx4 act4(floatx4 v)
 {
