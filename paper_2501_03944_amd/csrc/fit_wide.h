@@ -15,10 +15,12 @@
 //             step refills the stage it consumed with the step 4 ahead and reads
 //             the next step's MFMA fragments into the second of two register
 //             sets, one load and two fragment reads interleaved with every 8
-//             multiplies, so loads, LDS reads and matrix work overlap.  FP32
-//             (k_fit_wide): a 2-stage ring, loads issued one step ahead.  Past
-//             the end a step re-loads the last tile, so wait counts are
-//             constants;
+//             multiplies, so loads, LDS reads and matrix work overlap; a step
+//             needs few other instructions (its look-ahead sources come from
+//             tile bases set once per tile), since with one wavefront per SIMD
+//             they take issue slots from the multiplies.  FP32 (k_fit_wide): a
+//             2-stage ring, loads issued one step ahead.  Past the end a step
+//             re-loads the last tile, so wait counts are constants;
 //  * swizzle: a 16-byte chunk c of tile row r lives at chunk c ^ s(r), with
 //             s(r) = (r >> 1) & 3 for 64-byte rows (BF16) and r & 7 for 128-byte
 //             rows (FP32), so the 8 lanes served together by a 16-byte LDS read
@@ -33,7 +35,8 @@
 //             to one XCD, whose blocks split the group's sample tiles, so a
 //             spark's weights are fetched from HBM into that XCD's L2 once.
 //
-// Packed spark layout (written by k_pack_wide, row pitch PR bytes):
+// Packed spark layout (written by k_pack_wide_rows, or by the explosion kernel
+// for explosion sparks; row pitch PR bytes):
 //   [0, 256*Kp*es)          W1aug as [Kp/32][256][32] (K-blocked: the tile of one
 //                           K step is 16 or 32 KiB of contiguous memory): W1
 //                           (zero-padded), b1 in column `in`
