@@ -120,6 +120,12 @@ struct WidePack {
     int woff1, boff1, woff2, boff2;     // parameter offsets inside a spark
 };
 
+// Byte offset of W1aug element (o, k) (b1 is column k = in) in a packed row.
+__device__ __forceinline__ size_t wide_w1_offset(int o, int k, size_t es)
+{
+    return (((size_t)(k >> 5) * 256 + o) * 32 + (k & 31)) * es;
+}
+
 // Byte offset of spark coordinate j (< D) in its packed row; *f32 is set when
 // the element is stored as FP32 whatever the precision (b2).
 __device__ __forceinline__ size_t wide_pack_offset(const WidePack &p, int j, bool *f32)
@@ -146,7 +152,7 @@ __device__ __forceinline__ size_t wide_pack_offset(const WidePack &p, int j, boo
         *f32 = true;
         return (size_t)256 * p.Kp * es + (size_t)16 * 256 * es + (size_t)(j - p.boff2) * 4;
     }
-    return (((size_t)(k >> 5) * 256 + o) * 32 + (k & 31)) * es;
+    return wide_w1_offset(o, k, es);
 }
 
 // ---- spark.hip

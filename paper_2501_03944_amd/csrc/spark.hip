@@ -68,11 +68,15 @@ __device__ __forceinline__ void pack_four(const WidePack &wp, int row, int j0, i
                                           const float (&s)[4])
 {
     char *dst = wp.Wp + (size_t)row * wp.pr;
-    const int rel = j0 - wp.woff1;
-    if (j0 >= wp.woff1 && j0 + 3 < wp.woff1 + wp.hid * wp.in && rel % wp.in + 3 < wp.in &&
-        (rel % wp.in & 31) <= 28 && (rel % wp.in & 3) == 0) {
-        bool f32;
-        const size_t off = wide_pack_offset(wp, j0, &f32);
+    int o = -1, k = 0;
+    if (j0 >= wp.woff1 && j0 + 3 < wp.woff1 + wp.hid * wp.in) {
+        const int rel = j0 - wp.woff1;
+        o = rel / wp.in;
+        k = rel - o * wp.in;
+    }
+    // four columns of one W1 row inside one 32-column block, 4-aligned
+    if (o >= 0 && k + 3 < wp.in && (k & 31) <= 28 && (k & 3) == 0) {
+        const size_t off = wide_w1_offset(o, k, BF ? 2 : 4);
         if constexpr (BF) {
             const uint32_t lo = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)s[0]) |
                                 ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)s[1]) << 16);
