@@ -23,10 +23,13 @@
 //
 // Weight source (template flag WL):
 //   WL = true   the block copies its spark's weights once into LDS, every
-//               layer zero-padded to whole 16-row blocks and to the padded K,
-//               with a row pitch of an odd number of 16-byte (FP32) or 8-byte
-//               (BF16) units so the fragment reads of a quarter-wavefront hit
-//               distinct banks; biases in an FP32 area after the weights.
+//               layer zero-padded to whole 16-row blocks and to the padded K;
+//               biases in an FP32 area after the weights.  FP32: the row pitch
+//               is 2 (mod 8) 16-byte chunks and chunk c of row r sits at
+//               c ^ (r & 1), so the 16-byte fragment reads served together (four
+//               lanes from each half of the wavefront: rows 4a..4a+3, chunks g
+//               and g + 2) hit eight distinct bank groups.  BF16: rows padded by
+//               16 bytes.
 //   WL = false  fragments are read from the spark row in global memory (L2),
 //               with row/column guards; used when the weights exceed the LDS.
 //
@@ -170,7 +173,10 @@ struct WView {
         pitch = a.lpitch[l];
         if constexpr (WL) {
             constexpr int es = BF ? 2 : 4;
-            sp = smem + (size_t)(a.lw[l] + n * pitch + 4 * g_) * es;
+            // FP32: 16-byte chunk c of row r is stored at chunk c ^ (r & 1) (see
+            // stage_weights); the lane's chunk in every K block is 4kb + g
+            const int gq = BF ? g_ : (g_ ^ (n & 1));
+            sp = smem + (size_t)(a.lw[l] + n * pitch + 4 * gq) * es;
             gp = nullptr;
         } else {
             gp = w + a.woff[l] + (size_t)n * fi + 4 * g_;
@@ -229,7 +235,7 @@ __device__ __forceinline__ void stage_weights(const FitArgs &a, const float *w, 
                 for (int u = 0; u < 4; ++u) {
                     const int idx = i0 + u * nt;
                     const int o = (4 * idx) / cols, k = 4 * idx - o * cols;
-                    dst[u] = idx < n4 ? base + o * pitch + k : -1;
+                    dst[u] = idx < n4 ? base + o * pitch + (BF ? k : k ^ ((o & 1) << 2)) : -1;
                     v[u] = (idx < n4 && o < fo && k < fi)
                                ? *reinterpret_cast<const floatx4 *>(src + (size_t)o * fi + k)
                                : zero4();
@@ -261,7 +267,7 @@ __device__ __forceinline__ void stage_weights(const FitArgs &a, const float *w, 
                 reinterpret_cast<uint16_t *>(smem)[base + o * pitch + k] =
                     __builtin_bit_cast(uint16_t, (__bf16)v);
             else
-                reinterpret_cast<float *>(smem)[base + o * pitch + k] = v;
+                reinterpret_cast<float *>(smem)[base + o * pitch + (k ^ ((o & 1) << 2))] = v;
         }
         for (int o = threadIdx.x; o < rows; o += blockDim.x)
             bias[a.lb[l] + o] = o < fo ? w[a.boff[l] + o] : 0.0f;

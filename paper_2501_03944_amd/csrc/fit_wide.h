@@ -23,9 +23,11 @@
 //             re-loads the last tile, so wait counts are constants;
 //  * swizzle: a 16-byte chunk c of tile row r lives at chunk c ^ s(r), with
 //             s(r) = (r >> 1) & 3 for 64-byte rows (BF16) and r & 7 for 128-byte
-//             rows (FP32), so the 8 lanes served together by a 16-byte LDS read
-//             (8 consecutive rows, same chunk) hit 8 distinct 16-byte bank
-//             groups;
+//             rows (FP32).  A 16-byte LDS read serves eight lanes at a time,
+//             four from each half of the wavefront (lanes i..i+3 and
+//             i+32..i+35: here rows 4a..4a+3 with chunks g and g + 2, measured
+//             with the bank-conflict counter); for BF16 those eight land in
+//             distinct 16-byte bank groups;
 //  * epilogue per tile: activation, layer 2 as MFMAs whose B operand is the
 //             hidden tile straight from the accumulators, the two hidden halves'
 //             logits summed through LDS and stored sample-major, then every lane

@@ -77,7 +77,9 @@ int fit_max_bpr() { return MAX_BPR; }
 static int lds_layout(const Net &net, const KernelEntry &e, FitPlan *p)
 {
     const int es = e.bf16 ? 2 : 4;          // storage bytes per weight
-    const int unit = e.bf16 ? 8 : 4;        // pitch padding: 16 / 8 bytes
+    // pitch padding in elements: BF16 16 bytes; FP32 32 bytes (a pitch of 2 mod 8
+    // 16-byte chunks, with the row-parity chunk swizzle of the kernel)
+    const int unit = 8;
     int off = 0, boff = 0;
     for (int l = 0; l < MAXL; ++l) {
         p->lw[l] = p->lpitch[l] = p->lrows[l] = p->lcols[l] = p->lb[l] = 0;
