@@ -23,9 +23,18 @@
  *    library never allocates device memory.  The context object itself is
  *    host memory owned by the library; release it with mgfwa_destroy.
  *  - All device work is enqueued on the caller's HIP stream given to
- *    mgfwa_init, in stream order; only mgfwa_best, mgfwa_best_all and
- *    mgfwa_timing synchronise with the host.
- *  - The same (config, problem, seed) gives bit-identical state on any run.
+ *    mgfwa_init, in stream order; the library never uses the null stream
+ *    (a NULL stream is rejected).  Only mgfwa_best, mgfwa_best_all,
+ *    mgfwa_timing, mgfwa_autotune and the set-up of mgfwa_set_fit_plan
+ *    synchronise with the host.
+ *  - Determinism: the same (config, problem, seed, fitness plan) gives
+ *    bit-identical state on any run.  The fitness plan is the launch shape of
+ *    each fitness launch (mgfwa_plan_info); its FP32 summation order follows
+ *    that shape.  Without autotuning the plan is a fixed function of the shape;
+ *    mgfwa_autotune picks the fastest of the candidates by the clock, so two
+ *    processes may pick different plans: every candidate meets the same
+ *    fitness tolerance, and mgfwa_fit_candidates / mgfwa_set_fit_plan let a
+ *    caller read the candidates and force one.
  */
 #ifndef MGFWA_H
 #define MGFWA_H
@@ -114,17 +123,29 @@ typedef struct {
  *   external_fitness  1: no fitness kernels, the caller tells every fitness
  *   use_target, target_loss  stop once a population's best <= target_loss
  *   seed      key of the counter-based generator
- *   lag_guiding  1: Alg. 1's own order -- each generation first builds its
- *             guiding sparks from the PREVIOUS generation's explosion sparks
- *             and their fitness (around the current fireworks; zero guiding
- *             vectors in the first generation), then explodes, then evaluates
- *             the explosion and guiding sparks in one fitness launch.  0 (the
- *             default) builds them from the current generation's sparks as
- *             Sec. 3.2 describes.  Not available with external_fitness.
+ *   lag_guiding  1: Alg. 1's listing order taken literally -- each generation
+ *             first builds its guiding sparks from the PREVIOUS generation's
+ *             explosion sparks and their fitness (around the current fireworks;
+ *             zero guiding vectors in the first generation), then explodes,
+ *             then evaluates the explosion and guiding sparks in one fitness
+ *             launch.  0 (the default) evaluates the explosion sparks first and
+ *             builds the guiding sparks from them and their fitness (a guiding
+ *             vector needs the fitness of the sparks it is built from: the
+ *             guided-sparks scheme of GFWA that Sec. 2.1 credits).  Not
+ *             available with external_fitness or with ask/tell.
  *   map_range 1: a coordinate that leaves [lb, ub] lands uniformly in the
  *             population's current range min..max of that dimension over its
- *             fireworks (the mapping rule of the FWA family, Sec. 2) instead
- *             of uniformly in [lb, ub]
+ *             fireworks instead of uniformly in [lb, ub] (one reading of the
+ *             "population-based random mapping" that Sec. 2.1 names as part of
+ *             MGFWA; the paper does not define it)
+ *   fit_path  0: the fitness kernel family follows from the problem's shape.
+ *             A non-zero value forces a family, for tests and measurement:
+ *             weights problems 1 = register-chain kernels (the MLP chained in
+ *             registers, weights staged in LDS or read from L2), 2 = the
+ *             K-streamed wide-first-layer kernel (two-layer nets with hidden
+ *             width <= 256 and <= 16 outputs); input problems 1 = whole-network
+ *             tiles, 2 = layer by layer, 3 = layer by layer with LDS-staged
+ *             tiles.  EUNSUPPORTED when the family does not cover the shape.
  */
 typedef struct {
     int n_populations;      /* B >= 1 */
@@ -147,6 +168,7 @@ typedef struct {
     uint64_t seed;
     int lag_guiding;
     int map_range;
+    int fit_path;
 } mgfwa_config;
 
 /* Layout of the device state inside the workspace, for inspection: byte
@@ -175,6 +197,11 @@ typedef struct {
     size_t best_gen; /* int32 [B] */
     size_t gen;      /* int32 device generation counter */
     size_t done;     /* int32 device stop flag */
+    int se_written;  /* 1: mgfwa_step writes every explosion spark to SE.  0: it does
+                        not (the wide fitness kernel reads packed rows, and the guiding,
+                        selection and best-so-far steps regenerate the sparks they need
+                        from the counter-based generator); SE then holds sparks only
+                        after mgfwa_ask */
 } mgfwa_state_info;
 
 /* Per-phase device time accumulated while timing is on (milliseconds). */
@@ -198,9 +225,13 @@ MGFWA_API size_t mgfwa_workspace_bytes(const mgfwa_config *config, const mgfwa_p
  * the box, amplitude A0, fitness of every firework (unless external_fitness),
  * best-so-far.  workspace_dev must be 256-byte aligned and hold at least
  * mgfwa_workspace_bytes bytes; it is owned by the caller and must outlive the
- * context.  hip_stream is a hipStream_t (NULL = the null stream).
- * Errors: EINVAL (config/problem), ENOMEM (workspace), EUNSUPPORTED (shape),
- * EHIP (no device, launch failure).  *out is NULL on failure.
+ * context.  hip_stream is a hipStream_t created by the caller (NULL -> EINVAL);
+ * every later call on the context enqueues its work there.  The control words
+ * are cleared by a kernel on that stream: mgfwa_init does not wait for the
+ * device.
+ * Errors: EINVAL (config/problem, NULL stream), ENOMEM (workspace),
+ * EUNSUPPORTED (shape), EHIP (no device, launch failure).  *out is NULL on
+ * failure.
  */
 MGFWA_API mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config,
                                   const mgfwa_problem *problem, void *workspace_dev,
@@ -236,7 +267,8 @@ MGFWA_API mgfwa_status mgfwa_best_all(mgfwa_ctx *ctx, float *x_host, float *f_ho
  * valid until the next tell) and enqueues the work that produces it.  tell reads
  * fitness_dev (float[rows], device, caller-owned) in stream order; NaN counts as
  * +inf.  Any other order -> ESTATE.  In problem mode (external_fitness = 0)
- * ask/tell may replace the built-in fitness for any generation.
+ * ask/tell may replace the built-in fitness for any generation.  A context with
+ * lag_guiding returns EUNSUPPORTED (its order has no ask/tell form).
  */
 MGFWA_API mgfwa_status mgfwa_ask(mgfwa_ctx *ctx, const float **sparks_dev, int *rows, int *ld);
 MGFWA_API mgfwa_status mgfwa_tell(mgfwa_ctx *ctx, const float *fitness_dev);
@@ -303,13 +335,33 @@ MGFWA_API mgfwa_status mgfwa_fit_plan(const mgfwa_ctx *ctx, int which, mgfwa_pla
  * launches each, on the context's stream, over its own spark buffers) and the
  * fastest is kept.  The choice is cached for the process per (shape, precision,
  * samples, sparks): any later context of the same shape takes it without timing,
- * so a job's fitness values (whose summation order follows the launch shape)
- * depend only on its shape, alone or in a batch.  Call before the first
- * generation (ESTATE otherwise).  Contexts on the wide kernel keep their fixed
- * tiles (OK, nothing changes).  Input problems time their kernels' tile shapes
- * (net_kernel of mgfwa_plan_info).  Synchronises the stream.
+ * so within a process a job's fitness values (whose summation order follows the
+ * launch shape) depend only on its shape, alone or in a batch.  Another process
+ * may time the candidates differently and keep another one: read the choice with
+ * mgfwa_fit_plan and force it with mgfwa_set_fit_plan where bit-identical
+ * results across processes are needed.  Call before the first generation
+ * (ESTATE otherwise).  Contexts on the wide kernel keep their fixed tiles (OK,
+ * nothing changes).  Input problems time their kernels' tile shapes (net_kernel
+ * of mgfwa_plan_info).  Synchronises the stream.
  */
 MGFWA_API mgfwa_status mgfwa_autotune(mgfwa_ctx *ctx, int reps);
+
+/*
+ * The candidate plans of one fitness launch of a context (which as in
+ * mgfwa_fit_plan): the compiled kernel variants that cover the shape with their
+ * sample splits (weights problems), the tile shapes (input problems), or the one
+ * fixed plan of the wide kernel.  Writes up to max_out entries to out (may be
+ * NULL) and their total count to *n.  No device work.
+ */
+MGFWA_API mgfwa_status mgfwa_fit_candidates(const mgfwa_ctx *ctx, int which, mgfwa_plan_info *out,
+                                            int max_out, int *n);
+
+/*
+ * Force candidate `index` (of mgfwa_fit_candidates) as the plan of fitness launch
+ * `which`, bypassing the shape rule and the autotuner's cache.  Call before the
+ * first generation (ESTATE otherwise).  EINVAL for an index out of range.
+ */
+MGFWA_API mgfwa_status mgfwa_set_fit_plan(mgfwa_ctx *ctx, int which, int index);
 
 /*
  * Batched generations: many independent jobs (contexts of any shapes, each its
@@ -319,9 +371,10 @@ MGFWA_API mgfwa_status mgfwa_autotune(mgfwa_ctx *ctx, int reps);
  * kernels, launch shapes and results are exactly those of stepping it alone.
  * The contexts stay owned by the caller and must outlive the batch; while they
  * are in a batch they may still be read (best, state) and stepped alone.
- * hip_stream: the launch stream (NULL = null stream); mgfwa_batch_step orders
- * itself after work already queued on each job's stream and before later work
- * there.  Errors: EINVAL (no jobs, NULL or repeated job), ESTATE (a job uses
+ * hip_stream: the launch stream, created by the caller (NULL -> EINVAL);
+ * mgfwa_batch_step orders itself after work already queued on each job's stream
+ * and before later work there.  Errors: EINVAL (no jobs, NULL or repeated job,
+ * NULL stream), ESTATE (a job uses
  * external fitness, is in an ask/tell exchange or has timing on), EHIP.
  */
 typedef struct mgfwa_batch mgfwa_batch;

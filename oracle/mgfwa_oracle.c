@@ -245,6 +245,17 @@ double orc_loss(const orc_problem *p, const float *w, double *per_sample)
     return loss_impl(p, w, per_sample, 1);
 }
 
+int orc_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 void orc_loss_rows(const orc_problem *p, const float *w, int rows, int ld, double *out)
 {
     if (p->kind == ORC_PROBLEM_INPUT) {

@@ -88,6 +88,8 @@ double orc_net_output(const orc_problem *p, const float *x);
 /* Fitness of rows sparks with leading dimension ld (binary64 results): the loss
  * (TRAIN) or the fixed network's output (INPUT). */
 void orc_loss_rows(const orc_problem *p, const float *w, int rows, int ld, double *out);
+/* Threads the fitness loops use: n > 0 sets the count; returns the count in force. */
+int orc_threads(int n);
 /* Forward pass of one sample: writes the widths[n_layers] outputs (binary64). */
 void orc_forward(const orc_problem *p, const float *w, int sample, double *out);
 

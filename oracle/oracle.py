@@ -43,6 +43,8 @@ def lib():
         L.orc_loss.restype = C.c_double
         L.orc_loss_rows.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p]
         L.orc_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+        L.orc_threads.argtypes = [C.c_int]
+        L.orc_threads.restype = C.c_int
         L.orc_init_row.argtypes = [C.c_void_p, C.c_int, C.c_uint32, C.c_uint32, C.c_int, C.c_void_p]
         L.orc_explosion_row.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_float, C.c_uint32,
                                         C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -163,6 +165,11 @@ class Problem:
         out = np.zeros(self.widths[-1], dtype=np.float64)
         lib().orc_forward(C.byref(self.s), _ptr(w), int(sample), _ptr(out))
         return out
+
+
+def threads(n: int = 0) -> int:
+    """Threads of the oracle's fitness loops: n > 0 sets them; returns the count in force."""
+    return int(lib().orc_threads(int(n)))
 
 
 def philox(ctr, key):

@@ -52,7 +52,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 int round_up(int v, int a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-    size_t F, SE, SG, A, Y, Yprev, fresh, Yc, top, bottom, tie, cstar, improved, reinit, src;
+    size_t F, SE, SG, A, Aexp, Y, Yprev, fresh, Yc, top, bottom, tie, cstar, improved, reinit, src;
     size_t best_x, best_y, best_f, best_gen, best_upd, ctrl, partial, Xp, Xb, Ypad, Lpad;
     size_t Wpack, Xw, lo, hi, Pnet, H0, H1, Zero, total;
     int partial_rows;
@@ -91,6 +91,8 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
         return fail(MGFWA_EUNSUPPORTED, "lag_guiding needs the built-in fitness");
     if (c->precision != MGFWA_FP32 && c->precision != MGFWA_BF16)
         return fail(MGFWA_EINVAL, "unknown precision %d", c->precision);
+    if (c->fit_path < 0 || c->fit_path > (p->kind == MGFWA_PROBLEM_INPUT ? 3 : 2))
+        return fail(MGFWA_EINVAL, "fit_path %d out of range for this problem kind", c->fit_path);
     if (p->kind != MGFWA_PROBLEM_WEIGHTS && p->kind != MGFWA_PROBLEM_INPUT)
         return fail(MGFWA_EINVAL, "unknown problem kind %d", p->kind);
     const bool input = p->kind == MGFWA_PROBLEM_INPUT;
@@ -167,10 +169,9 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
         in.n_packed = off;
         in.hs = hmax + 4;   // 16-byte skew between the rows of the activation tile
         in.hnp = hmax;      // hidden outputs: np[l] = kp[l+1]
-        // MGFWA_NET_PATH=1 / 2 / 3 forces the whole-network / layer-by-layer /
+        // fit_path 1 / 2 / 3 forces the whole-network / layer-by-layer /
         // LDS-staged layer-by-layer kernels (before autotuning)
-        const char *np_env = std::getenv("MGFWA_NET_PATH");
-        in.path = np_env && np_env[0] >= '1' && np_env[0] <= '3' ? np_env[0] - '0' : 0;
+        in.path = c->fit_path;
         D = p->widths[0];
     } else {
         net.nl = p->n_layers;
@@ -218,14 +219,20 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
         net.inv_norm = net.loss == MGFWA_LOSS_MSE ? (float)(1.0 / ((double)net.S * outw))
                                                   : (float)(1.0 / (double)net.S);
         // Two-layer networks whose staged weights exceed the LDS stream their first
-        // layer through LDS instead (MGFWA_FORCE_WIDE=1 forces it, for tests).
-        const char *fw = std::getenv("MGFWA_FORCE_WIDE");
-        const bool force_wide = fw && fw[0] == '1';
+        // layer through LDS instead; fit_path 1 / 2 forces either family.
+        if (c->fit_path == 2 && need_data && !wide_applicable(net))
+            return fail(MGFWA_EUNSUPPORTED, "the wide fitness kernel needs a two-layer net with "
+                                            "hidden width <= 256 and <= 16 outputs");
         net.wide = need_data && wide_applicable(net) &&
-                   (force_wide || resident_lds_bytes(net) > 160 * 1024 - 512);
+                   (c->fit_path == 2 ||
+                    (c->fit_path == 0 && resident_lds_bytes(net) > 160 * 1024 - 512));
         if (net.wide && net.S_pad / 256 > fit_max_bpr())
             return fail(MGFWA_EUNSUPPORTED, "too many samples for the wide fitness kernel");
     }
+    // The wide kernel reads the explosion's packed rows: the FP32 rows are then
+    // not stored, and the guiding and apply steps regenerate the sparks they
+    // need (the lag order reads the previous generation's sparks: it keeps them).
+    s.regen = net.wide && !s.lag ? 1 : 0;
 
     Layout &L = out->lay;
     size_t off = 0;
@@ -239,6 +246,7 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
     L.SE = take(BN * s.lam * Dp * 4);
     L.SG = take(BN * s.G * Dp * 4);
     L.A = take(BN * 4);
+    L.Aexp = take(BN * 4);
     L.Y = take(BN * 4);
     L.Yprev = take(BN * 4);
     L.fresh = take(BN * 4);
@@ -395,7 +403,7 @@ mgfwa_status enqueue_generation(mgfwa_ctx *c, hipStream_t st, hipEvent_t *ev)
     }
     // wide fitness kernel: the explosion also writes the sparks' packed rows
     const WidePack wp = c->net.wide ? wide_pack_geometry(c->net, c->d) : WidePack{};
-    STEP(launch_explode(s, c->d, st, c->net.wide ? &wp : nullptr), "explode");
+    STEP(launch_explode(s, c->d, st, c->net.wide ? &wp : nullptr, !s.regen), "explode");
     if (ev) STEP(hipEventRecord(ev[1], st), "event");
     mgfwa_status r = fit_rows(c, c->plan_expl, c->d.SE, s.Dp, s.BN * expl_rows(s), expl_map(s),
                               c->d.Yc, st, ev ? ev[6] : nullptr,
@@ -439,10 +447,8 @@ mgfwa_status build_graph(mgfwa_ctx *c)
 
 mgfwa_status reset_ctrl(mgfwa_ctx *c)
 {
-    // the control words and the per-population flags start at zero
-    static const int32_t zeros[CTRL_WORDS] = {0, 0, 0, 0};
-    HIP_TRY(hipMemcpyAsync(c->d.ctrl, zeros, sizeof zeros, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    // the control words start at zero (a kernel on the stream: no host wait)
+    HIP_TRY(launch_clear_ctrl(c->d.ctrl, c->stream));
     return MGFWA_OK;
 }
 
@@ -473,6 +479,9 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
     Derived dv;
     mgfwa_status r = derive(config, problem, &dv);
     if (r != MGFWA_OK) return r;
+    if (!hip_stream)
+        return fail(MGFWA_EINVAL, "hip_stream is NULL: pass a stream created by the caller "
+                                  "(the library never uses the null stream)");
     if (!workspace_dev) return fail(MGFWA_ENOMEM, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(workspace_dev) % ALIGN != 0)
         return fail(MGFWA_ENOMEM, "workspace must be %zu-byte aligned", ALIGN);
@@ -538,6 +547,7 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
     d.SE = at<float>(b, L.SE);
     d.SG = at<float>(b, L.SG);
     d.A = at<float>(b, L.A);
+    d.Aexp = at<float>(b, L.Aexp);
     d.Y = at<float>(b, L.Y);
     d.Yprev = at<float>(b, L.Yprev);
     d.fresh = at<int32_t>(b, L.fresh);
@@ -682,6 +692,7 @@ mgfwa_status mgfwa_ask(mgfwa_ctx *c, const float **sparks, int *rows, int *ld)
 {
     if (!c || !sparks) return fail(MGFWA_EINVAL, "NULL argument");
     const Shape &s = c->s;
+    if (s.lag) return fail(MGFWA_EUNSUPPORTED, "the lagged guiding order has no ask/tell form");
     switch (c->phase) {
     case PH_INIT_ASK:
         *sparks = c->d.F;
@@ -796,6 +807,7 @@ mgfwa_status mgfwa_state(const mgfwa_ctx *c, mgfwa_state_info *info)
     info->best_gen = L.best_gen;
     info->gen = L.ctrl + CTRL_GEN * 4;
     info->done = L.ctrl + CTRL_DONE * 4;
+    info->se_written = c->s.regen ? 0 : 1;
     return MGFWA_OK;
 }
 
@@ -870,6 +882,7 @@ namespace {
 
 std::mutex g_tune_mu;
 std::map<std::string, FitPlan> g_tune;   // shape key -> timed choice, for the process
+constexpr int MAX_CANDIDATES = 64;
 
 std::string tune_key(const Net &net, int rows)
 {
@@ -905,6 +918,29 @@ int tune_candidates(const mgfwa_ctx *c, int rows, FitPlan *cand, int max_out)
     return n;
 }
 
+// Sparks per launch of fitness launch `which` (0 explosion, 1 guiding sparks).
+int launch_rows(const mgfwa_ctx *c, int which)
+{
+    return which == 0 ? c->s.BN * expl_rows(c->s) : c->s.BN * c->s.G;
+}
+
+void fill_plan_info(const mgfwa_ctx *c, const FitPlan &p, int rows, mgfwa_plan_info *info)
+{
+    std::memset(info, 0, sizeof *info);
+    info->wide = c->net.wide ? 1 : 0;
+    info->rows = rows;
+    info->net_kernel = c->input ? p.net_shape : -1;
+    if (!c->net.wide && !c->input) {
+        info->wavefronts = p.nw;
+        info->slabs = p.P;
+        info->lds_weights = p.wl;
+        info->blocks_per_row = p.bpr;
+        info->samples_per_block = p.spb;
+        info->lds_bytes = p.lds_bytes;
+        for (int l = 0; l < MAXL; ++l) info->row_blocks[l] = p.lrows[l] / 16;
+    }
+}
+
 // Time every candidate plan for `rows` sparks of W on the context's stream and
 // keep the fastest; a shape seen before reuses its choice without timing.
 mgfwa_status tune_plan(mgfwa_ctx *c, int rows, const float *W, OutMap map, int reps, FitPlan *out)
@@ -919,8 +955,8 @@ mgfwa_status tune_plan(mgfwa_ctx *c, int rows, const float *W, OutMap map, int r
             return MGFWA_OK;
         }
     }
-    FitPlan cand[64];
-    const int n = tune_candidates(c, rows, cand, 64);
+    FitPlan cand[MAX_CANDIDATES];
+    const int n = tune_candidates(c, rows, cand, MAX_CANDIDATES);
     if (n == 0) return fail(MGFWA_EUNSUPPORTED, "no compiled fitness kernel covers this MLP shape");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
@@ -1053,20 +1089,42 @@ mgfwa_status mgfwa_fit_plan(const mgfwa_ctx *c, int which, mgfwa_plan_info *info
 {
     if (!c || !info) return fail(MGFWA_EINVAL, "NULL argument");
     if (which < 0 || which > 1) return fail(MGFWA_EINVAL, "which must be 0 or 1");
-    const FitPlan &p = which == 0 ? c->plan_expl : c->plan_guide;
-    std::memset(info, 0, sizeof *info);
-    info->wide = c->net.wide ? 1 : 0;
-    info->rows = which == 0 ? c->s.BN * expl_rows(c->s) : c->s.BN * c->s.G;
-    info->net_kernel = c->input ? p.net_shape : -1;
-    if (!c->net.wide && !c->input) {
-        info->wavefronts = p.nw;
-        info->slabs = p.P;
-        info->lds_weights = p.wl;
-        info->blocks_per_row = p.bpr;
-        info->samples_per_block = p.spb;
-        info->lds_bytes = p.lds_bytes;
-        for (int l = 0; l < MAXL; ++l) info->row_blocks[l] = p.lrows[l] / 16;
-    }
+    fill_plan_info(c, which == 0 ? c->plan_expl : c->plan_guide, launch_rows(c, which), info);
+    return MGFWA_OK;
+}
+
+mgfwa_status mgfwa_fit_candidates(const mgfwa_ctx *c, int which, mgfwa_plan_info *out, int max_out,
+                                  int *n)
+{
+    if (!c || !n) return fail(MGFWA_EINVAL, "NULL argument");
+    if (which < 0 || which > 1) return fail(MGFWA_EINVAL, "which must be 0 or 1");
+    if (max_out < 0 || (max_out > 0 && !out)) return fail(MGFWA_EINVAL, "bad output buffer");
+    if (!c->has_data) return fail(MGFWA_ESTATE, "no built-in fitness: no fitness launches");
+    const int rows = launch_rows(c, which);
+    FitPlan cand[MAX_CANDIDATES];
+    const int nc = c->net.wide ? 1 : tune_candidates(c, rows, cand, MAX_CANDIDATES);
+    if (c->net.wide) cand[0] = which == 0 ? c->plan_expl : c->plan_guide;
+    for (int i = 0; i < nc && i < max_out; ++i) fill_plan_info(c, cand[i], rows, &out[i]);
+    *n = nc;
+    return MGFWA_OK;
+}
+
+mgfwa_status mgfwa_set_fit_plan(mgfwa_ctx *c, int which, int index)
+{
+    if (!c) return fail(MGFWA_EINVAL, "ctx is NULL");
+    if (which < 0 || which > 1) return fail(MGFWA_EINVAL, "which must be 0 or 1");
+    if (c->cfg.external_fitness || !c->has_data)
+        return fail(MGFWA_ESTATE, "forcing a plan needs the built-in fitness");
+    if (c->phase != PH_READY || c->gen_host != 0 || c->gexec)
+        return fail(MGFWA_ESTATE, "set the fitness plan before the first generation");
+    const int rows = launch_rows(c, which);
+    FitPlan cand[MAX_CANDIDATES];
+    const int nc = c->net.wide ? 1 : tune_candidates(c, rows, cand, MAX_CANDIDATES);
+    if (index < 0 || index >= nc)
+        return fail(MGFWA_EINVAL, "plan index %d outside [0, %d)", index, nc);
+    if (c->net.wide) return MGFWA_OK;   // one fixed tile shape
+    HIP_TRY(fit_prepare(cand[index]));
+    (which == 0 ? c->plan_expl : c->plan_guide) = cand[index];
     return MGFWA_OK;
 }
 
@@ -1076,6 +1134,8 @@ mgfwa_status mgfwa_batch_create(mgfwa_batch **out, mgfwa_ctx *const *ctxs, int n
     if (!out) return fail(MGFWA_EINVAL, "out is NULL");
     *out = nullptr;
     if (!ctxs || n_jobs < 1) return fail(MGFWA_EINVAL, "no jobs");
+    if (!hip_stream)
+        return fail(MGFWA_EINVAL, "hip_stream is NULL: pass a stream created by the caller");
     std::vector<mgfwa_ctx *> jobs(ctxs, ctxs + n_jobs);
     for (int i = 0; i < n_jobs; ++i) {
         mgfwa_ctx *c = jobs[i];

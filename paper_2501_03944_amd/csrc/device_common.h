@@ -77,6 +77,37 @@ __device__ __forceinline__ bool outside(const Box &b, float v)
     return v < b.lb || v > b.ub;
 }
 
+// Coordinates 4*chunk .. 4*chunk+3 of explosion spark `row` in generation tn:
+// s = fma(amp, 2u - 1, x) per coordinate, an out-of-box coordinate replaced by
+// its uniform draw from the mapping stream of the same (chunk, row, generation)
+// (into the box, or into the population range plo..phi when given), coordinates
+// at or past D zero.  Counter-based: any kernel can regenerate a spark exactly.
+__device__ __forceinline__ void explosion_chunk(const float (&x)[4], float amp, uint2 key, int chunk,
+                                                uint32_t row, uint32_t tn, const Box &box,
+                                                const float *plo, const float *phi, int D,
+                                                float (&s)[4])
+{
+    const uint4 r = draw4(key, (uint32_t)chunk, row, tn, TAG_EXPL);
+    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+    bool any_out = false;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const float v = 2.0f * u01(w[e]) - 1.0f;
+        s[e] = __builtin_fmaf(amp, v, x[e]);
+        any_out |= outside(box, s[e]);
+    }
+    if (any_out) {
+        const uint4 r2 = draw4(key, (uint32_t)chunk, row, tn, TAG_EXPL_MAP);
+        const uint32_t w2[4] = {r2.x, r2.y, r2.z, r2.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (outside(box, s[e])) s[e] = map_uniform(box, u01(w2[e]), plo, phi, 4 * chunk + e);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (4 * chunk + e >= D) s[e] = 0.0f;
+}
+
 // Order-preserving 32-bit key of a (NaN-free) fitness value; -0 and +0 share a key.
 __device__ __forceinline__ uint32_t fit_key(float y)
 {

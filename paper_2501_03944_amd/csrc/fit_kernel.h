@@ -1,6 +1,6 @@
 // Fitness kernel template, instantiated by the fit_*.hip files.
 //
-// Fitness of every spark (Alg. 1: evaluate all the sparks in parallel): the
+// Fitness of every spark (Alg. 1, the evaluation step): the
 // loss of the MLP whose weights are the spark, over the shared sample set.
 //
 // Each spark's layer is a dense contraction, so the evaluation is a grouped

@@ -171,11 +171,6 @@ const void *wide_kernel(const Net &net)
 // weight + sample tiles per round (gs + bx/gs); gs always divides rows.
 int wide_group(const Net &net, int rows, int ntn)
 {
-    const char *env = std::getenv("MGFWA_WIDE_GS");
-    if (env) {
-        const int g = std::atoi(env);
-        if (g >= 1 && rows % g == 0) return g;
-    }
     const int bx = (net.num_cu + 7) / 8;
     int gs = 1;
     while (gs * ntn < bx && rows % (2 * gs) == 0 && gs < 64) gs *= 2;

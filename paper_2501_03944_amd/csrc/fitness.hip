@@ -142,9 +142,6 @@ static bool entry_fits(const Net &net, const KernelEntry &e, double *cost)
         c *= 0.5;                             // staged weights beat global fragment loads
     }
     if (e.act >= 0) c *= 0.9;                 // specialised activation: straight-line epilogue
-    const char *env = std::getenv("MGFWA_FIT_NW");
-    const int prefer_nw = env ? std::atoi(env) : 0;
-    if (prefer_nw > 0 && e.nw != prefer_nw) c *= 1.01;
     *cost = c;
     return true;
 }

@@ -1,5 +1,5 @@
-// Multi-guiding sparks (Alg. 1: generate the multi-guiding sparks, then their
-// random mapping).
+// Multi-guiding sparks (Alg. 1, the guiding-spark step and the mapping step
+// that follows it).
 //
 // Ranking: the members of every guiding group ordered by (fitness key, spark
 //            index) give the top-k and bottom-k member lists in ascending spark
@@ -143,9 +143,11 @@ __device__ __forceinline__ void rank_group_wave(const float *__restrict__ Yc, in
 
 // RANK: groups of m <= 64 members are ranked inside the kernel (wavefront 0 of
 // each block, into LDS; the x-block 0 also stores the lists); otherwise the
-// lists come from k_rank.
-template <bool RANK>
+// lists come from k_rank.  REGEN: the member sparks are regenerated from the
+// counter-based generator (firework row, amplitude A) instead of read from SE.
+template <bool RANK, bool REGEN>
 __global__ __launch_bounds__(TPB) void k_guide(const float *__restrict__ F,
+                                               const float *__restrict__ A,
                                                const float *__restrict__ SE,
                                                float *__restrict__ SG,
                                                int32_t *__restrict__ top,
@@ -189,20 +191,36 @@ __global__ __launch_bounds__(TPB) void k_guide(const float *__restrict__ F,
         }
         const int gf = gi / G;
         const float4 x4 = reinterpret_cast<const float4 *>(F + (size_t)gf * Dp)[chunk];
+        const float x[4] = {x4.x, x4.y, x4.z, x4.w};
+        const size_t pb = (size_t)(gf / N) * Dp;
+        const float *plo = lo ? lo + pb : nullptr, *phi = hi ? hi + pb : nullptr;
         float dlt[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         if (!tied) {
             float st[4] = {0.0f, 0.0f, 0.0f, 0.0f}, sb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-            const float *base = SE + (size_t)gf * lam * Dp;
-            for (int i = 0; i < k; ++i) {
-                const float4 a = reinterpret_cast<const float4 *>(base + (size_t)tp[i] * Dp)[chunk];
-                const float4 b = reinterpret_cast<const float4 *>(base + (size_t)bp[i] * Dp)[chunk];
-                st[0] = st[0] + a.x; st[1] = st[1] + a.y; st[2] = st[2] + a.z; st[3] = st[3] + a.w;
-                sb[0] = sb[0] + b.x; sb[1] = sb[1] + b.y; sb[2] = sb[2] + b.z; sb[3] = sb[3] + b.w;
+            if constexpr (REGEN) {
+                const float amp = A[gf];
+                const uint32_t row0 = (uint32_t)gf * (uint32_t)lam;
+                for (int i = 0; i < k; ++i) {
+                    float a[4], b[4];
+                    explosion_chunk(x, amp, key, chunk, row0 + (uint32_t)tp[i], tn, box, plo, phi,
+                                    D, a);
+                    explosion_chunk(x, amp, key, chunk, row0 + (uint32_t)bp[i], tn, box, plo, phi,
+                                    D, b);
+                    st[0] = st[0] + a[0]; st[1] = st[1] + a[1]; st[2] = st[2] + a[2]; st[3] = st[3] + a[3];
+                    sb[0] = sb[0] + b[0]; sb[1] = sb[1] + b[1]; sb[2] = sb[2] + b[2]; sb[3] = sb[3] + b[3];
+                }
+            } else {
+                const float *base = SE + (size_t)gf * lam * Dp;
+                for (int i = 0; i < k; ++i) {
+                    const float4 a = reinterpret_cast<const float4 *>(base + (size_t)tp[i] * Dp)[chunk];
+                    const float4 b = reinterpret_cast<const float4 *>(base + (size_t)bp[i] * Dp)[chunk];
+                    st[0] = st[0] + a.x; st[1] = st[1] + a.y; st[2] = st[2] + a.z; st[3] = st[3] + a.w;
+                    sb[0] = sb[0] + b.x; sb[1] = sb[1] + b.y; sb[2] = sb[2] + b.z; sb[3] = sb[3] + b.w;
+                }
             }
 #pragma unroll
             for (int e = 0; e < 4; ++e) dlt[e] = (st[e] - sb[e]) * inv_k;
         }
-        const float x[4] = {x4.x, x4.y, x4.z, x4.w};
         float v[4];
         bool any_out = false;
 #pragma unroll
@@ -213,8 +231,6 @@ __global__ __launch_bounds__(TPB) void k_guide(const float *__restrict__ F,
         if (any_out) {
             const uint4 r2 = draw4(key, (uint32_t)chunk, (uint32_t)gi, tn, TAG_GUIDE_MAP);
             const uint32_t w2[4] = {r2.x, r2.y, r2.z, r2.w};
-            const size_t pb = (size_t)(gf / N) * Dp;
-            const float *plo = lo ? lo + pb : nullptr, *phi = hi ? hi + pb : nullptr;
 #pragma unroll
             for (int e = 0; e < 4; ++e)
                 if (outside(box, v[e])) v[e] = map_uniform(box, u01(w2[e]), plo, phi, 4 * chunk + e);
@@ -244,14 +260,11 @@ hipError_t launch_guide(const Shape &s, const DevState &d, hipStream_t st)
     const int nchunk = s.Dp >> 2;
     dim3 grid((nchunk + TPB - 1) / TPB, groups < MAX_GRID_Y ? groups : MAX_GRID_Y);
     const float *lo = s.map_range ? d.lo : nullptr, *hi = s.map_range ? d.hi : nullptr;
-    if (s.m <= 64)
-        hipLaunchKernelGGL(k_guide<true>, grid, dim3(TPB), 0, st, d.F, d.SE, d.SG, d.top, d.bottom,
-                           d.tie, s.G, s.lam, s.k, s.inv_k, s.boost, groups, s.D, s.Dp, s.key, s.box,
-                           d.ctrl, s.N, lo, hi, d.Yc, s.C, s.m, s.lag);
-    else
-        hipLaunchKernelGGL(k_guide<false>, grid, dim3(TPB), 0, st, d.F, d.SE, d.SG, d.top, d.bottom,
-                           d.tie, s.G, s.lam, s.k, s.inv_k, s.boost, groups, s.D, s.Dp, s.key, s.box,
-                           d.ctrl, s.N, lo, hi, d.Yc, s.C, s.m, s.lag);
+    auto *k = s.m <= 64 ? (s.regen ? &k_guide<true, true> : &k_guide<true, false>)
+                        : (s.regen ? &k_guide<false, true> : &k_guide<false, false>);
+    hipLaunchKernelGGL(k, grid, dim3(TPB), 0, st, d.F, d.A, d.SE, d.SG, d.top, d.bottom, d.tie, s.G,
+                       s.lam, s.k, s.inv_k, s.boost, groups, s.D, s.Dp, s.key, s.box, d.ctrl, s.N,
+                       lo, hi, d.Yc, s.C, s.m, s.lag);
     return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@ struct OutMap {
 // Device pointers carved out of the caller's workspace.
 struct DevState {
     float *F, *SE, *SG, *A, *Y, *Yprev, *Yc, *best_x, *best_y, *partial;
+    float *Aexp;       // [B*N] amplitude the generation's sparks were exploded with
     int32_t *fresh, *top, *bottom, *tie, *cstar, *improved, *reinit, *src, *best_f, *best_gen,
         *best_upd, *ctrl;
     float *Xp;         // [S_pad][in_pad] packed inputs (FP32 precision)
@@ -55,6 +56,8 @@ struct Shape {
     uint2 key;
     int lag;                           // guiding from the previous generation's sparks
     int map_range;                     // random mapping into the population's range
+    int regen;                         // the guiding and apply steps regenerate explosion
+                                       // sparks instead of reading SE
 };
 
 // MLP problem as the fitness kernels need it.
@@ -158,8 +161,9 @@ __device__ __forceinline__ size_t wide_pack_offset(const WidePack &p, int j, boo
 // ---- spark.hip
 hipError_t launch_init_positions(const Shape &s, const DevState &d, hipStream_t st);
 hipError_t launch_pop_range(const Shape &s, const DevState &d, hipStream_t st);
+// write_se false (only with wp): the FP32 spark rows are not stored.
 hipError_t launch_explode(const Shape &s, const DevState &d, hipStream_t st,
-                          const WidePack *wp = nullptr);
+                          const WidePack *wp = nullptr, bool write_se = true);
 
 // ---- guide.hip
 hipError_t launch_rank(const Shape &s, const DevState &d, hipStream_t st);
@@ -170,6 +174,8 @@ hipError_t launch_select(const Shape &s, const DevState &d, hipStream_t st);
 hipError_t launch_init_select(const Shape &s, const DevState &d, hipStream_t st);
 hipError_t launch_apply(const Shape &s, const DevState &d, hipStream_t st);
 hipError_t launch_finish(const DevState &d, int advance, hipStream_t st);
+// Zero the control words (generation counter, stop flags) in stream order.
+hipError_t launch_clear_ctrl(int32_t *ctrl, hipStream_t st);
 hipError_t launch_store_fitness(const float *src, int rows, OutMap map, float *out,
                                 const int32_t *ctrl, hipStream_t st);
 

@@ -1,6 +1,6 @@
-// Selection, dynamic amplitude, loser-out tournament and best-so-far (Alg. 1:
-// select the best individual of each population, perform the loser-out
-// tournament; the loop returns the best fitness and its position).
+// Selection, dynamic amplitude, loser-out tournament and best-so-far (Alg. 1,
+// the selection step and the loser-out step; the best-so-far row and fitness
+// are the answer the algorithm returns).
 //
 // k_select  -- one block per population.  Per firework: Yprev <- Y; c* =
 //              argmin over the lambda+G candidates (lower index on ties); move
@@ -39,6 +39,7 @@ __device__ void population_best(const float *Y, int N, int *fb_out, float *yb_ou
 
 __global__ __launch_bounds__(TPB) void k_select(Shape s, float *__restrict__ Yc, float *__restrict__ Y,
                                                 float *__restrict__ Yprev, float *__restrict__ A,
+                                                float *__restrict__ Aexp,
                                                 int32_t *__restrict__ fresh,
                                                 int32_t *__restrict__ cstar,
                                                 int32_t *__restrict__ improved,
@@ -82,6 +83,7 @@ __global__ __launch_bounds__(TPB) void k_select(Shape s, float *__restrict__ Yc,
         if (lane == 0) {
             const float yold = Y[gf];
             Yprev[gf] = yold;
+            Aexp[gf] = A[gf];   // the amplitude this generation's sparks were drawn with
             cstar[gf] = cs;
             reinit[gf] = 0;
             if (ymin < yold) {
@@ -161,9 +163,15 @@ __global__ __launch_bounds__(TPB) void k_init_select(Shape s, const float *__res
     }
 }
 
+// With s.regen a winning explosion spark is regenerated from the firework's
+// row (still the generation's, read before it is overwritten), its explosion
+// amplitude and the population range, exactly as the explosion drew it.
 __global__ __launch_bounds__(TPB) void k_apply(Shape s, float *__restrict__ F,
                                                const float *__restrict__ SE,
                                                const float *__restrict__ SG,
+                                               const float *__restrict__ Aexp,
+                                               const float *__restrict__ lo,
+                                               const float *__restrict__ hi,
                                                const int32_t *__restrict__ src,
                                                const int32_t *__restrict__ reinit,
                                                const int32_t *__restrict__ best_f,
@@ -193,6 +201,15 @@ __global__ __launch_bounds__(TPB) void k_apply(Shape s, float *__restrict__ F,
             }
             v = make_float4(e4[0], e4[1], e4[2], e4[3]);
             frow[chunk] = v;
+        } else if (sr >= 0 && sr < s.lam && s.regen) {
+            const float4 x4 = frow[chunk];
+            const float x[4] = {x4.x, x4.y, x4.z, x4.w};
+            const size_t pb = (size_t)b * s.Dp;
+            float e4[4];
+            explosion_chunk(x, Aexp[gf], s.key, chunk, (uint32_t)(gf * s.lam + sr), t, s.box,
+                            lo ? lo + pb : nullptr, hi ? hi + pb : nullptr, s.D, e4);
+            v = make_float4(e4[0], e4[1], e4[2], e4[3]);
+            frow[chunk] = v;
         } else if (sr >= 0) {
             const float *row = sr < s.lam ? SE + ((size_t)gf * s.lam + sr) * s.Dp
                                           : SG + ((size_t)gf * s.G + (sr - s.lam)) * s.Dp;
@@ -203,6 +220,11 @@ __global__ __launch_bounds__(TPB) void k_apply(Shape s, float *__restrict__ F,
         }
         if (copy_best) reinterpret_cast<float4 *>(best_x + (size_t)b * s.Dp)[chunk] = v;
     }
+}
+
+__global__ void k_clear_ctrl(int32_t *ctrl)
+{
+    if (threadIdx.x < CTRL_WORDS) ctrl[threadIdx.x] = 0;
 }
 
 __global__ void k_finish(int32_t *ctrl, int advance)
@@ -227,7 +249,8 @@ __global__ __launch_bounds__(TPB) void k_store_fitness(const float *__restrict__
 
 hipError_t launch_select(const Shape &s, const DevState &d, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_select, dim3(s.B), dim3(TPB), 0, st, s, d.Yc, d.Y, d.Yprev, d.A, d.fresh,
+    hipLaunchKernelGGL(k_select, dim3(s.B), dim3(TPB), 0, st, s, d.Yc, d.Y, d.Yprev, d.A, d.Aexp,
+                       d.fresh,
                        d.cstar, d.improved, d.reinit, d.src, d.best_y, d.best_f, d.best_gen,
                        d.best_upd, d.ctrl);
     return hipGetLastError();
@@ -244,8 +267,15 @@ hipError_t launch_apply(const Shape &s, const DevState &d, hipStream_t st)
 {
     const int nchunk = s.Dp >> 2;
     dim3 grid((nchunk + TPB - 1) / TPB, s.BN < MAX_GRID_Y ? s.BN : MAX_GRID_Y);
-    hipLaunchKernelGGL(k_apply, grid, dim3(TPB), 0, st, s, d.F, d.SE, d.SG, d.src, d.reinit,
+    hipLaunchKernelGGL(k_apply, grid, dim3(TPB), 0, st, s, d.F, d.SE, d.SG, d.Aexp,
+                       s.map_range ? d.lo : nullptr, s.map_range ? d.hi : nullptr, d.src, d.reinit,
                        d.best_f, d.best_upd, d.best_x, d.ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_ctrl(int32_t *ctrl, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_clear_ctrl, dim3(1), dim3(64), 0, st, ctrl);
     return hipGetLastError();
 }
 

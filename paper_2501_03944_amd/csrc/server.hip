@@ -49,6 +49,8 @@ struct Job {
     int D = 0, C = 0, budget = 0;
     int enqueued = 0, completed = 0;
     bool stopping = false;
+    hipEvent_t inputs_read = nullptr;   // recorded after the initialisation (input packing)
+    bool released = false;              // the caller's problem buffers are no longer read
     float best = 0.0f;
     std::vector<float> best_x;
     double t_submit = 0, t_admit = 0, t_finish = 0;
@@ -180,6 +182,11 @@ mgfwa_status retire(mgfwa_server *s, Job *j)
     }
     mgfwa_destroy(j->ctx);
     j->ctx = nullptr;
+    if (j->inputs_read) {
+        s->event_pool.push_back(j->inputs_read);
+        j->inputs_read = nullptr;
+    }
+    j->released = true;
     arena_free(s, j->off, j->bytes);
     j->state = r == MGFWA_OK ? MGFWA_JOB_DONE : MGFWA_JOB_FAILED;
     j->t_finish = s->now_ms();
@@ -201,12 +208,25 @@ mgfwa_status admit(mgfwa_server *s, Job *j)
         j->t_finish = j->t_admit;
         return MGFWA_OK;   // the job failed; the server carries on
     }
+    // the caller may release the problem buffers once the initialisation, which
+    // packs them into the workspace, has run on the device
+    hipError_t e = take_event(s, &j->inputs_read);
+    if (e == hipSuccess) e = hipEventRecord(j->inputs_read, j->stream);
+    if (e != hipSuccess) return fail(MGFWA_EHIP, "admit: %s", hipGetErrorString(e));
     mgfwa_state_info info;
     mgfwa_state(j->ctx, &info);
     j->D = info.D;
     j->C = j->cfg.n_populations * j->cfg.n_fireworks * info.n_candidates;
     j->state = MGFWA_JOB_RUNNING;
     return MGFWA_OK;
+}
+
+// Whether the job no longer reads the caller's problem buffers (non-blocking).
+bool inputs_released(const Job *j)
+{
+    if (j->released) return true;
+    if (j->state != MGFWA_JOB_RUNNING) return false;   // queued: not read yet
+    return hipEventQuery(j->inputs_read) == hipSuccess;
 }
 
 mgfwa_status enqueue(mgfwa_server *s, Job *j)
@@ -293,6 +313,7 @@ mgfwa_status mgfwa_server_tick(mgfwa_server *s)
     // 1-2: collect finished generations, retire finished jobs
     for (Job *j : s->jobs) {
         if (j->state != MGFWA_JOB_RUNNING) continue;
+        if (!j->released) j->released = inputs_released(j);
         mgfwa_status r = collect(s, j);
         if (r) return r;
         if (j->stopping && j->inflight.empty()) {
@@ -349,9 +370,12 @@ mgfwa_status mgfwa_server_drain(mgfwa_server *s)
 mgfwa_status mgfwa_server_job(mgfwa_server *s, int64_t id, mgfwa_job_info *info, float *x_host)
 {
     if (!s || id < 0 || id >= (int64_t)s->jobs.size()) return fail(MGFWA_EINVAL, "unknown job");
-    const Job *j = s->jobs[id];
+    Job *j = s->jobs[id];
+    if (j->state == MGFWA_JOB_RUNNING && !j->released) j->released = inputs_released(j);
     if (info) {
-        info->state = j->state;
+        // a running job whose initialisation has not yet read the caller's
+        // problem buffers still reports QUEUED
+        info->state = j->state == MGFWA_JOB_RUNNING && !j->released ? MGFWA_JOB_QUEUED : j->state;
         info->generations = j->completed;
         info->best_fitness = j->best;
         info->workspace_bytes = j->bytes;
@@ -399,6 +423,7 @@ void mgfwa_server_destroy(mgfwa_server *s)
     for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
     for (Job *j : s->jobs) {
         for (Inflight &f : j->inflight) give_back(s, f);
+        if (j->inputs_read) s->event_pool.push_back(j->inputs_read);
         if (j->ctx) mgfwa_destroy(j->ctx);
         delete j;
     }

@@ -1,5 +1,5 @@
-// Initial fireworks and explosion sparks (Alg. 1: random initialisation, the
-// explosion step and the random mapping of explosion sparks).
+// Initial fireworks and explosion sparks (Alg. 1, the initialisation step, the
+// explosion step and the mapping step after it).
 //
 // One thread produces four consecutive coordinates from one Philox block and
 // writes them as a single 16-byte store, so a wavefront writes 1 KiB of a spark
@@ -98,6 +98,8 @@ __device__ __forceinline__ void pack_four(const WidePack &wp, int row, int j0, i
     }
 }
 
+// SE null: the FP32 rows are not stored (the packed rows are the only copy the
+// fitness needs; later steps regenerate the sparks they read).
 template <int PACK>   // 0: no packing, 1: FP32 packed rows, 2: BF16
 __global__ __launch_bounds__(TPB) void k_explode(const float *__restrict__ F,
                                                  const float *__restrict__ A,
@@ -116,29 +118,12 @@ __global__ __launch_bounds__(TPB) void k_explode(const float *__restrict__ F,
         const float amp = A[gf];
         const float4 x4 = reinterpret_cast<const float4 *>(F + (size_t)gf * Dp)[chunk];
         const float x[4] = {x4.x, x4.y, x4.z, x4.w};
-        const uint4 r = draw4(key, (uint32_t)chunk, (uint32_t)row, tn, TAG_EXPL);
-        const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+        const size_t pb = (size_t)(gf / N) * Dp;
+        const float *plo = lo ? lo + pb : nullptr, *phi = hi ? hi + pb : nullptr;
         float s[4];
-        bool any_out = false;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const float v = 2.0f * u01(w[e]) - 1.0f;
-            s[e] = __builtin_fmaf(amp, v, x[e]);
-            any_out |= outside(box, s[e]);
-        }
-        if (any_out) {
-            const uint4 r2 = draw4(key, (uint32_t)chunk, (uint32_t)row, tn, TAG_EXPL_MAP);
-            const uint32_t w2[4] = {r2.x, r2.y, r2.z, r2.w};
-            const size_t pb = (size_t)(gf / N) * Dp;
-            const float *plo = lo ? lo + pb : nullptr, *phi = hi ? hi + pb : nullptr;
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (outside(box, s[e])) s[e] = map_uniform(box, u01(w2[e]), plo, phi, 4 * chunk + e);
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-            if (4 * chunk + e >= D) s[e] = 0.0f;
-        reinterpret_cast<float4 *>(SE + (size_t)row * Dp)[chunk] = make_float4(s[0], s[1], s[2], s[3]);
+        explosion_chunk(x, amp, key, chunk, (uint32_t)row, tn, box, plo, phi, D, s);
+        if (SE)
+            reinterpret_cast<float4 *>(SE + (size_t)row * Dp)[chunk] = make_float4(s[0], s[1], s[2], s[3]);
         if constexpr (PACK != 0)
             if (4 * chunk < D) pack_four<PACK == 2>(wp, row, 4 * chunk, D, s);
     }
@@ -170,7 +155,8 @@ hipError_t launch_pop_range(const Shape &s, const DevState &d, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_explode(const Shape &s, const DevState &d, hipStream_t st, const WidePack *wp)
+hipError_t launch_explode(const Shape &s, const DevState &d, hipStream_t st, const WidePack *wp,
+                          bool write_se)
 {
     const int rows = s.BN * s.lam;
     // 32 or 8 rows per block while there are enough blocks to fill the device
@@ -179,7 +165,8 @@ hipError_t launch_explode(const Shape &s, const DevState &d, hipStream_t st, con
     const WidePack none{};
     const WidePack &w = wp ? *wp : none;
     auto *k = !wp ? &k_explode<0> : wp->bf16 ? &k_explode<2> : &k_explode<1>;
-    hipLaunchKernelGGL(k, row_grid(s.Dp, rows, rpb), dim3(TPB), 0, st, d.F, d.A, d.SE, s.lam, rows,
+    hipLaunchKernelGGL(k, row_grid(s.Dp, rows, rpb), dim3(TPB), 0, st, d.F, d.A,
+                       write_se || !wp ? d.SE : nullptr, s.lam, rows,
                        s.D, s.Dp, s.key, s.box, d.ctrl, s.N, s.map_range ? d.lo : nullptr,
                        s.map_range ? d.hi : nullptr, w);
     return hipGetLastError();

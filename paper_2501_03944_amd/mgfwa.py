@@ -43,7 +43,7 @@ class mgfwa_config(C.Structure):
                 ("lb", C.c_float), ("ub", C.c_float), ("max_generations", C.c_int),
                 ("loser_out", C.c_int), ("precision", C.c_int), ("external_fitness", C.c_int),
                 ("use_target", C.c_int), ("target_loss", C.c_float), ("seed", C.c_uint64),
-                ("lag_guiding", C.c_int), ("map_range", C.c_int)]
+                ("lag_guiding", C.c_int), ("map_range", C.c_int), ("fit_path", C.c_int)]
 
 
 _STATE_ARRAYS = ("F", "A", "Y", "Yprev", "fresh", "SE", "SG", "Yc", "top", "bottom", "tie",
@@ -54,7 +54,7 @@ _STATE_ARRAYS = ("F", "A", "Y", "Yprev", "fresh", "SE", "SG", "Yc", "top", "bott
 class mgfwa_state_info(C.Structure):
     _fields_ = [("D", C.c_int), ("Dp", C.c_int), ("m", C.c_int), ("k", C.c_int),
                 ("n_candidates", C.c_int), ("generation", C.c_int)] + [
-        (n, C.c_size_t) for n in _STATE_ARRAYS]
+        (n, C.c_size_t) for n in _STATE_ARRAYS] + [("se_written", C.c_int)]
 
 
 class mgfwa_timing_info(C.Structure):
@@ -125,6 +125,9 @@ def lib() -> C.CDLL:
     L.mgfwa_version.restype = C.c_char_p
     L.mgfwa_autotune.argtypes = [C.c_void_p, C.c_int]
     L.mgfwa_fit_plan.argtypes = [C.c_void_p, C.c_int, P(mgfwa_plan_info)]
+    L.mgfwa_fit_candidates.argtypes = [C.c_void_p, C.c_int, P(mgfwa_plan_info), C.c_int,
+                                       P(C.c_int)]
+    L.mgfwa_set_fit_plan.argtypes = [C.c_void_p, C.c_int, C.c_int]
     L.mgfwa_batch_create.argtypes = [P(C.c_void_p), P(C.c_void_p), C.c_int, C.c_void_p]
     L.mgfwa_batch_step.argtypes = [C.c_void_p, C.c_int]
     L.mgfwa_batch_destroy.argtypes = [C.c_void_p]
@@ -140,7 +143,8 @@ def lib() -> C.CDLL:
     L.mgfwa_server_destroy.restype = None
     for name in ("mgfwa_init", "mgfwa_step", "mgfwa_best", "mgfwa_best_all", "mgfwa_ask",
                  "mgfwa_tell", "mgfwa_evaluate", "mgfwa_state", "mgfwa_set_timing",
-                 "mgfwa_timing", "mgfwa_autotune", "mgfwa_fit_plan", "mgfwa_batch_create",
+                 "mgfwa_timing", "mgfwa_autotune", "mgfwa_fit_plan", "mgfwa_fit_candidates",
+                 "mgfwa_set_fit_plan", "mgfwa_batch_create",
                  "mgfwa_batch_step", "mgfwa_server_create", "mgfwa_server_submit",
                  "mgfwa_server_tick", "mgfwa_server_drain", "mgfwa_server_job",
                  "mgfwa_server_stats_get"):
@@ -157,7 +161,7 @@ def _check(status: int) -> None:
 def make_config(n_fireworks=4, n_sparks=32, n_guiding=4, n_populations=1, sigma=0.2, boost=1.0,
                 amp_up=1.2, amp_down=0.9, amp_init=0.0, lb=-5.0, ub=5.0, max_generations=100,
                 loser_out=True, precision="fp32", external_fitness=False, target_loss=None,
-                seed=0, lag_guiding=False, map_range=False) -> mgfwa_config:
+                seed=0, lag_guiding=False, map_range=False, fit_path=0) -> mgfwa_config:
     c = mgfwa_config()
     c.n_populations, c.n_fireworks, c.n_sparks, c.n_guiding = (
         n_populations, n_fireworks, n_sparks, n_guiding)
@@ -171,6 +175,7 @@ def make_config(n_fireworks=4, n_sparks=32, n_guiding=4, n_populations=1, sigma=
     c.seed = int(seed)
     c.lag_guiding = int(bool(lag_guiding))
     c.map_range = int(bool(map_range))
+    c.fit_path = int(fit_path)
     return c
 
 
@@ -279,9 +284,25 @@ def mgfwa_autotune(ctx, reps: int = 3) -> None:
 def mgfwa_fit_plan(ctx, which: int) -> dict:
     info = mgfwa_plan_info()
     _check(lib().mgfwa_fit_plan(ctx, int(which), C.byref(info)))
+    return _plan_dict(info)
+
+
+def _plan_dict(info: mgfwa_plan_info) -> dict:
     d = {name: getattr(info, name) for name, _ in mgfwa_plan_info._fields_}
     d["row_blocks"] = list(info.row_blocks)
     return d
+
+
+def mgfwa_fit_candidates(ctx, which: int) -> list:
+    n = C.c_int()
+    _check(lib().mgfwa_fit_candidates(ctx, int(which), None, 0, C.byref(n)))
+    arr = (mgfwa_plan_info * max(1, n.value))()
+    _check(lib().mgfwa_fit_candidates(ctx, int(which), arr, n.value, C.byref(n)))
+    return [_plan_dict(arr[i]) for i in range(n.value)]
+
+
+def mgfwa_set_fit_plan(ctx, which: int, index: int) -> None:
+    _check(lib().mgfwa_set_fit_plan(ctx, int(which), int(index)))
 
 
 def mgfwa_batch_create(ctxs, stream: int) -> C.c_void_p:
@@ -380,7 +401,10 @@ class MGFWA:
         if self.nbytes == 0:
             raise MgfwaError(EINVAL, mgfwa_last_error())
         self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # the library runs on a stream of its own (never the null stream); the
+        # uploads above, queued on torch's current stream, complete first
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         self.ctx = mgfwa_init(self.config, self.problem, self.ws.data_ptr(), self.nbytes,
                               self.stream.cuda_stream)
         self.info = mgfwa_state(self.ctx)
@@ -388,6 +412,8 @@ class MGFWA:
         self.Dp = self.info.Dp
         self.B = self.config.n_populations
         self.BN = self.B * self.config.n_fireworks
+        # whether mgfwa_step writes the explosion sparks to SE
+        self.sparks_materialised = bool(self.info.se_written)
 
     @classmethod
     def from_workload(cls, wl, **config):
@@ -421,22 +447,35 @@ class MGFWA:
     def best_all(self):
         return mgfwa_best_all(self.ctx, self.B, self.D)
 
+    # torch's current stream and the library's stream are ordered explicitly
+    # around every call that hands device data from one to the other
+    def _lib_after_torch(self, *tensors):
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        for t in tensors:
+            t.record_stream(self.stream)
+
+    def _torch_after_lib(self):
+        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
     def ask(self):
         """Device view [rows, Dp] of the sparks to evaluate (valid until the next tell)."""
         ptr, rows, ld = mgfwa_ask(self.ctx)
+        self._torch_after_lib()
         off = ptr - self.ws.data_ptr()
         return self._view(off, (rows, ld), self.torch.float32)
 
     def tell(self, fitness):
         f = fitness.to(device=self.device, dtype=self.torch.float32).contiguous()
-        self._tell_keep = f
+        self._lib_after_torch(f)
         mgfwa_tell(self.ctx, f.data_ptr())
 
     def evaluate(self, W):
         """Fitness of the rows of W (torch [rows, ld] float32 on the device)."""
         W = W.contiguous()
         out = self.torch.empty(W.shape[0], dtype=self.torch.float32, device=self.device)
+        self._lib_after_torch(W, out)
         mgfwa_evaluate(self.ctx, W.data_ptr(), W.shape[0], W.shape[1], out.data_ptr())
+        self._torch_after_lib()
         return out
 
     def autotune(self, reps: int = 3):
@@ -444,6 +483,12 @@ class MGFWA:
 
     def fit_plan(self, which: int = 0) -> dict:
         return mgfwa_fit_plan(self.ctx, which)
+
+    def fit_candidates(self, which: int = 0) -> list:
+        return mgfwa_fit_candidates(self.ctx, which)
+
+    def set_fit_plan(self, which: int, index: int):
+        mgfwa_set_fit_plan(self.ctx, which, index)
 
     def set_timing(self, on: bool):
         mgfwa_set_timing(self.ctx, on)
@@ -468,6 +513,7 @@ class MGFWA:
                       reinit=((BN,), i32), best_x=((self.B, Dp), f32), best_y=((self.B,), f32),
                       best_f=((self.B,), i32), best_gen=((self.B,), i32), gen=((1,), i32),
                       done=((1,), i32))
+        self._torch_after_lib()
         out = {name: self._view(getattr(i, name), shp, dt) for name, (shp, dt) in shapes.items()}
         out["D"], out["Dp"], out["m"], out["k"] = i.D, i.Dp, i.m, i.k
         return out
@@ -484,7 +530,7 @@ class Batch:
     def __init__(self, jobs, stream=None):
         import torch
         self.jobs = list(jobs)
-        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = stream if stream is not None else torch.cuda.Stream()
         self.h = mgfwa_batch_create([j.ctx for j in self.jobs], self.stream.cuda_stream)
 
     def step(self, n: int = 1):

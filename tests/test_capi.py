@@ -74,20 +74,34 @@ def test_problem_validation():
     assert M.mgfwa_workspace_bytes(ce, M.make_problem((4, 3, 1), ("relu",), "mse", 0)) > 0
 
 
+# a stand-in stream handle: every call below fails before any HIP call uses it
+FAKE_STREAM = 0x1000
+
+
 def test_init_rejects_before_touching_the_device():
     p = _cfg2_problem()
     c = M.make_config(n_fireworks=8, n_sparks=256)
     nb = M.mgfwa_workspace_bytes(c, p)
     with pytest.raises(M.MgfwaError) as e:
-        M.mgfwa_init(c, p, 4096, nb - 1, 0)
+        M.mgfwa_init(c, p, 4096, nb, 0)          # the null stream is never used
+    assert e.value.status == M.EINVAL and "null stream" in str(e.value)
+    with pytest.raises(M.MgfwaError) as e:
+        M.mgfwa_init(c, p, 4096, nb - 1, FAKE_STREAM)
     assert e.value.status == M.ENOMEM
     with pytest.raises(M.MgfwaError) as e:
-        M.mgfwa_init(c, p, 4096 + 8, nb, 0)      # misaligned workspace
+        M.mgfwa_init(c, p, 4096 + 8, nb, FAKE_STREAM)      # misaligned workspace
     assert e.value.status == M.ENOMEM
     wide = M.make_problem((4, 300, 1), ("relu",), "mse", 8, 1, 1, 0)
     with pytest.raises(M.MgfwaError) as e:
-        M.mgfwa_init(c, wide, 4096, 1 << 30, 0)
+        M.mgfwa_init(c, wide, 4096, 1 << 30, FAKE_STREAM)
     assert e.value.status == M.EUNSUPPORTED
+    with pytest.raises(M.MgfwaError) as e:    # a kernel family that does not cover the shape
+        M.mgfwa_init(M.make_config(fit_path=2), M.make_problem((4, 3, 3, 1), ("relu", "relu"),
+                                                                "mse", 8, 1, 1, 0),
+                     4096, 1 << 30, FAKE_STREAM)
+    assert e.value.status == M.EUNSUPPORTED
+    assert M.mgfwa_workspace_bytes(M.make_config(fit_path=3), p) == 0   # out of range
+    assert "fit_path" in M.mgfwa_last_error()
 
 
 def test_variant_configs():
@@ -101,7 +115,7 @@ def test_variant_configs():
     assert M.mgfwa_workspace_bytes(M.make_config(lag_guiding=True, **base), p) >= nb
     with pytest.raises(M.MgfwaError) as e:
         M.mgfwa_init(M.make_config(lag_guiding=True, external_fitness=True, **base), p, 4096,
-                     1 << 30, 0)
+                     1 << 30, FAKE_STREAM)
     assert e.value.status == M.EUNSUPPORTED and "lag_guiding" in str(e.value)
     assert M.mgfwa_workspace_bytes(M.make_config(map_range=True, external_fitness=True, **base),
                                    p) > 0

@@ -7,8 +7,8 @@ Within 1e-5 relative (FP32): every fitness value.
 import numpy as np
 import pytest
 
-from gpu_util import (assert_bits, assert_fitness_close, compare_state, gpu_rows, make_pair,
-                      near_tie_present, require_gpu)
+from gpu_util import (assert_bits, assert_fitness_close, check_generation, compare_state,
+                      gpu_rows, make_pair, require_gpu)
 from oracle import oracle as O
 from paper_2501_03944_amd import inputs
 
@@ -108,21 +108,12 @@ def test_free_running_teacher_matches_oracle():
     ov = o.view()
     assert_bits(gs["F"][:, :D], ov["F"], "init F")
     assert_fitness_close(gs["Y"], ov["Y"], "init Y")
-    lam, G = o.cfg.lam, o.cfg.G
     diverged_at = None
     for gen in range(1, 101):
         prev = o.view()
         o.generation()
         g.step(1)
-        ov = o.view()
-        gs = g.state_numpy()
-        assert_fitness_close(gs["Yc"], ov["Yc64"], f"gen {gen} candidate fitness")
-        same = (np.array_equal(gs["F"][:, :D], ov["F"]) and np.array_equal(gs["cstar"], ov["cstar"])
-                and np.array_equal(gs["reinit"], ov["reinit"]) and
-                np.array_equal(gs["top"], ov["top"]))
-        if not same:
-            assert near_tie_present(prev, ov, lam, G, ov["m"], ov["k"]), \
-                f"divergence at generation {gen} without a near-tie"
+        if not check_generation(o, prev, o.view(), g.state_numpy(), D, gen):
             diverged_at = gen
             break
     print(f"free-running: diverged_at={diverged_at}")
@@ -165,19 +156,37 @@ def test_same_seed_same_state_different_seed_differs():
 
 
 def test_target_loss_stops_generations():
+    """The stop test runs on the device: both sides stop at the same generation
+    unless a decision on the way (or the stop test itself) compared values
+    within the fitness tolerance."""
     torch, M = require_gpu()
     wl = inputs.teacher_regression()
     o, g = make_pair(wl, target=40.0, T=200)
-    o.run(200)
-    g.step(200)
+    D = g.D
+    o.init()
+    assert_fitness_close(g.state_numpy()["Y"], o.view()["Y"], "init Y")
+    parted = None
+    for gen in range(1, 201):
+        prev = o.view()
+        o.generation()
+        g.step(1)
+        ov, gs = o.view(), g.state_numpy()
+        if not check_generation(o, prev, ov, gs, D, gen):
+            parted = gen
+            break
+        if int(gs["done"][0]) != ov["done"]:
+            # only a best fitness within the tolerance of the target may stop one side only
+            assert abs(float(ov["best_y"].min()) - 40.0) <= 2e-5 * 40.0, f"stop flag at {gen}"
+            parted = gen
+            break
+        if ov["done"]:
+            break
     x, f, gen = g.best()
-    ov = o.view()
-    assert ov["done"] == 1
-    assert f <= 40.0 and gen < 200
-    gs = g.state_numpy()
-    assert int(gs["done"][0]) == 1
-    # stopping generation matches the oracle unless a near-tie intervened
-    assert gen == ov["t"] or abs(gen - ov["t"]) <= 5
+    if parted is None:
+        assert ov["done"] == 1 and gen == ov["t"] < 200
+        assert f <= 40.0
+    print(f"target stop: oracle t={ov['t']}, library generation {gen}, parted at {parted}")
+    g.close()
 
 
 def test_ask_tell_protocol_errors():

@@ -1,15 +1,18 @@
 """Serving loop: continuous batching of optimisation jobs on one device.
 
 A job's answer must not depend on what else runs: each served job is compared
-bit for bit with the same configuration run alone through a plain context
-(whose generations are themselves checked against the oracle in the parity
-tests).  Admission is checked against the arena footprint.
+bit for bit with the same configuration run alone through a plain context, and
+each FP32 served job with the oracle's run of the same configuration (bit for
+bit up to the first generation whose decisions compare values within the
+fitness tolerance).  Admission is checked against the arena footprint, and a
+job's problem buffers may be overwritten as soon as it reports RUNNING.
 """
 import numpy as np
 import pytest
 
+from gpu_util import assert_bits, assert_fitness_close, oracle_near_tie_generation, require_gpu
+from oracle import oracle as O
 from paper_2501_03944_amd import inputs
-from gpu_util import assert_bits, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -58,6 +61,78 @@ def test_served_jobs_equal_jobs_run_alone():
         assert info["state"] == "done" and info["generations"] == gen == cfg["max_generations"]
         assert_bits(np.float32(info["best_fitness"]), np.float32(fa), f"job {jid} best fitness")
         assert_bits(x, xa, f"job {jid} best position")
+    srv.close()
+
+
+def _oracle_for(wl, cfg):
+    kw = dict(N=cfg.get("n_fireworks", wl.n_fireworks), lam=cfg.get("n_sparks", wl.n_sparks),
+              G=cfg.get("n_guiding", wl.n_guiding), B=cfg.get("n_populations", 1),
+              lb=wl.lb, ub=wl.ub, T=cfg.get("max_generations", wl.generations),
+              seed=cfg.get("seed", 0), loser_out=int(cfg.get("loser_out", True)),
+              lag_guiding=int(cfg.get("lag_guiding", False)),
+              map_range=int(cfg.get("map_range", False)))
+    if cfg.get("target_loss") is not None:
+        kw.update(use_target=1, target_loss=cfg["target_loss"])
+    return O.Oracle(O.Problem.from_workload(wl), **kw)
+
+
+def _check_against_oracle(wl, cfg, info, x):
+    """A served job's answer against the oracle's run of the same job; returns
+    False when the oracle's run holds a near-tie (no bitwise claim then)."""
+    o = _oracle_for(wl, cfg)
+    T = cfg.get("max_generations", wl.generations)
+    tie_at = oracle_near_tie_generation(o, T)
+    if tie_at is not None:
+        print(f"job {wl.widths} seed {cfg.get('seed')}: oracle near-tie at generation {tie_at}")
+        return False
+    ov = o.view()
+    pb = int(np.argmin(ov["best_y"]))
+    assert info["generations"] == ov["t"]
+    assert_bits(x, ov["best_x"][pb], f"served {wl.widths} best position vs oracle")
+    assert_fitness_close(np.float32(info["best_fitness"]), ov["best_y"][pb],
+                         f"served {wl.widths} best fitness vs oracle")
+    return True
+
+
+def test_served_fp32_jobs_match_oracle():
+    """Served FP32 jobs (mixed shapes and variants, running together) against
+    the oracle's runs of the same jobs."""
+    torch, M = require_gpu()
+    jobs = [(wl, cfg) for wl, cfg in _mix() if cfg.get("precision", "fp32") == "fp32"]
+    jobs.append((inputs.teacher_regression(), dict(seed=9, max_generations=60, target_loss=40.0)))
+    srv = M.Server(256 << 20, n_streams=3)
+    ids = [srv.submit_workload(wl, **cfg) for wl, cfg in jobs]
+    srv.drain()
+    checked = 0
+    for jid, (wl, cfg) in zip(ids, jobs):
+        info, x = srv.job(jid)
+        assert info["state"] == "done"
+        checked += _check_against_oracle(wl, cfg, info, x)
+    print(f"served jobs checked bit for bit against the oracle: {checked}/{len(jobs)}")
+    assert checked >= len(jobs) - 2
+    srv.close()
+
+
+def test_problem_buffers_may_change_once_running():
+    """Once a job reports RUNNING the server no longer reads its problem buffers:
+    overwriting them then leaves the job's answer unchanged."""
+    torch, M = require_gpu()
+    wl = inputs.teacher_regression()
+    cfg = dict(seed=3, max_generations=15)
+    srv = M.Server(64 << 20, n_streams=2)
+    jid = srv.submit_workload(wl, **cfg)
+    for _ in range(100000):
+        srv.tick()
+        if srv.job(jid)[0]["state"] != "queued":
+            break
+    assert srv.job(jid)[0]["state"] in ("running", "done")
+    for t in srv._keep[jid]:
+        if t is not None:
+            t.fill_(float("nan"))        # the caller reuses its buffers
+    srv.drain()
+    info, x = srv.job(jid)
+    xa, fa, gen = _alone(wl, **cfg)
+    assert_bits(x, xa, "job whose inputs were overwritten after RUNNING")
     srv.close()
 
 

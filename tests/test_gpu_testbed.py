@@ -126,19 +126,18 @@ def test_unpadded_rows_ignore_what_follows_the_input():
 # (kernel path, rows): whole-network tiles of 16 and 32 rows; layer by layer
 # with 64 x 128, 64 x 64, 32 x 32 and K-split 16 x 16 tiles (on 256 compute
 # units); layer by layer with LDS-staged 64 x 128 (net 12) and 64 x 64 (net 6) tiles
-PATHS = [("1", 37), ("1", 9000), ("2", 37), ("2", 1000), ("2", 2100), ("2", 4101), ("3", 37), ("3", 4101)]
+PATHS = [(1, 37), (1, 9000), (2, 37), (2, 1000), (2, 2100), (2, 4101), (3, 37), (3, 4101)]
 
 
 @pytest.mark.parametrize("net_id", [6, 12])
 @pytest.mark.parametrize("path,rows", PATHS)
-def test_every_kernel_path_sampled_against_oracle(monkeypatch, net_id, path, rows):
+def test_every_kernel_path_sampled_against_oracle(net_id, path, rows):
     """Each tile shape of both kernels: sampled rows (the first and the ragged
     last tile included) against the oracle."""
-    monkeypatch.setenv("MGFWA_NET_PATH", path)
     torch, M = require_gpu()
     wl = inputs.testbed_net(net_id)
     # 16 x 512 explosion sparks: evaluation runs in chunks of 8192 rows
-    g = M.MGFWA.from_workload(wl, n_fireworks=16, n_sparks=512, n_guiding=8)
+    g = M.MGFWA.from_workload(wl, n_fireworks=16, n_sparks=512, n_guiding=8, fit_path=path)
     p = O.Problem.from_workload(wl)
     X = np.random.default_rng(rows).uniform(-5, 5, (rows, wl.dim)).astype(np.float32)
     got, _ = _eval(torch, g, X)

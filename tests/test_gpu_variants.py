@@ -13,16 +13,13 @@
 import numpy as np
 import pytest
 
-from gpu_util import (assert_bits, assert_fitness_close, make_pair, near_tie_present,
+from gpu_util import (assert_bits, assert_fitness_close, check_generation, make_pair,
                       require_gpu)
 from oracle import oracle as O
 from paper_2501_03944_amd import inputs
 from test_gpu_parity import _lockstep
 
 pytestmark = pytest.mark.gpu
-
-EXACT_KEYS = ("F", "A", "cstar", "reinit", "top", "bottom", "tie")
-
 
 def _free_run(wl, gens, **cfg):
     """Step the library and the oracle one generation at a time; returns the
@@ -35,34 +32,18 @@ def _free_run(wl, gens, **cfg):
     gs, ov = g.state_numpy(), o.view()
     assert_bits(gs["F"][:, :D], ov["F"], "init F")
     assert_fitness_close(gs["Y"], ov["Y"], "init Y")
-    lam, G = o.cfg.lam, o.cfg.G
+    G = o.cfg.G
     try:
         for gen in range(1, gens + 1):
             prev = o.view()
             o.generation()
             g.step(1)
             ov, gs = o.view(), g.state_numpy()
-            assert_fitness_close(gs["Yc"], ov["Yc64"], f"gen {gen} candidate fitness")
-            assert_fitness_close(gs["Y"], ov["Y"], f"gen {gen} firework fitness")
             if gen == 1 and lag:
                 assert np.all(gs["tie"] == 1), "first lagged guiding vectors must be zero"
                 assert_bits(gs["SG"][:, :D], np.repeat(prev["F"], G, axis=0), "gen 1 SG")
-            F = gs["F"][:, :D]
-            same = np.array_equal(F, ov["F"]) and all(
-                np.array_equal(gs[k], ov[k]) for k in EXACT_KEYS if k != "F")
-            if not same:
-                diff = [k for k in EXACT_KEYS if not np.array_equal(gs[k][:, :D] if k == "F"
-                                                                    else gs[k], ov[k])]
-                print(f"gen {gen}: {diff} differ")
-                assert near_tie_present(prev, ov, lam, G, ov["m"], ov["k"],
-                                        guide_yc=prev["Yc"] if lag else None,
-                                        check_guide=not (lag and gen == 1)), \
-                    f"divergence at generation {gen} without a near-tie"
+            if not check_generation(o, prev, ov, gs, D, gen, lag=lag, sparks=g.sparks_materialised):
                 return gen
-            # while every decision agrees the sparks agree bit for bit
-            assert_bits(gs["SE"][:, :D], ov["SE"], f"gen {gen} SE")
-            assert_bits(gs["SG"][:, :D], ov["SG"], f"gen {gen} SG")
-            assert int(gs["gen"][0]) == gen
         return None
     finally:
         g.close()
@@ -90,13 +71,12 @@ def test_free_running_variants_match_oracle(cfg):
     print(f"{cfg}: diverged_at={at}")
 
 
-def test_lag_order_through_the_wide_kernel(monkeypatch):
+def test_lag_order_through_the_wide_kernel():
     """The combined explosion + guiding launch routed to the wide-first-layer
     kernel writes each row's fitness to its own candidate slot."""
-    monkeypatch.setenv("MGFWA_FORCE_WIDE", "1")
     wl = inputs.random_mlp_problem((40, 64, 5), ("relu",), "ce", 300, seed=3)
     at = _free_run(wl, 8, lag_guiding=True, n_fireworks=3, n_sparks=16, n_guiding=2, seed=5,
-                   T=30)
+                   T=30, fit_path=2)
     print(f"wide lag: diverged_at={at}")
 
 

@@ -44,6 +44,30 @@ def test_explosion_unit_amplitude_lands_on_2pow23_grid():
     assert k.min() >= -2 ** 23 and k.max() < 2 ** 23
 
 
+def _bits(h):
+    return np.array([int(h, 16)], dtype=np.uint32).view(np.float32)[0]
+
+
+def test_explosion_spark_golden_exact():
+    """tests/golden/explosion_spark.json: x != 0, a non-power-of-two amplitude,
+    coordinates where one rounding (fma) and two roundings differ, and mapped
+    coordinates -- worked in exact rational arithmetic from the Philox words."""
+    doc = json.load(open(os.path.join(GOLDEN, "explosion_spark.json")))
+    cfg = O.make_config(seed=doc["seed"], lb=doc["lb"], ub=doc["ub"])
+    x = np.array([_bits(h) for h in doc["x"]], dtype=np.float32)
+    A = _bits(doc["A"])
+    s = O.explosion_row(cfg, x, A, row=doc["row"], t=doc["t"])
+    coords = doc["coordinates"]
+    assert any(c["fma_differs"] and not c["mapped"] for c in coords)
+    assert any(c["mapped"] for c in coords)
+    for c in coords:
+        d = c["d"]
+        assert O.word(doc["seed"], "expl", doc["row"], doc["t"], d) == c["word"]
+        if c["mapped"]:
+            assert O.word(doc["seed"], "expl_map", doc["row"], doc["t"], d) == c["map_word"]
+        assert s[d].view(np.uint32) == _bits(c["value"]).view(np.uint32), c
+
+
 def test_explosion_statistics_interior():
     # an interior firework with small amplitude never needs mapping:
     # (s - x) / A is uniform on [-1, 1): mean 0, variance 1/3
