@@ -4,13 +4,19 @@
 A step is one full MGFWA generation (explosion sparks, their fitness, ranking
 and multi-guiding sparks, their fitness, selection, amplitude update, loser-out)
 over the whole population, with every input already resident in HBM.  The
-default workload is the 64-128-128-10 ReLU cross-entropy network (D = 26,122)
-on 4096 Gaussian-mixture samples, 8 fireworks x 256 sparks + 4 guiding sparks.
+default workload is the 784-256-10 ReLU cross-entropy network (D = 203,530) on
+8192 sparse prototype samples, 16 fireworks x 256 sparks + 4 guiding sparks,
+with FP32 fitness; the same workload with BF16 fitness (FP32 accumulation, FP32
+re-check of each firework's selection winner) is reported beside it.
 
 value     = candidate evaluations per second over the timed steps
 roofline  = the explosion-spark fitness kernel (the dominant kernel): algorithmic
             matmul FLOP per launch / its average duration from HIP events
-cpu_baseline = the CPU oracle on a bounded sample of the same workload
+bf16      = the same workload with BF16 fitness: throughput, its own roofline,
+            and its error and top-k agreement against the oracle's binary64
+            fitness of sampled guiding groups (computed in the CPU-baseline leg)
+cpu_baseline = the CPU oracle on a bounded sample of the same workload, on all
+            host threads and on one
 """
 from __future__ import annotations
 
@@ -40,18 +46,22 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="mlp64-128-128-10", choices=sorted(WORKLOAD_TAG))
+    ap.add_argument("--workload", default="mlp784-256-10", choices=sorted(WORKLOAD_TAG))
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16"])
-    ap.add_argument("--cpu-baseline", type=int, default=1, help="1: time the oracle (rank 0)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="approximate CPU time budget of the oracle sample")
-    ap.add_argument("--precision-study", type=int, default=1,
-                    help="1: also run the 784-256-10 workload in BF16 and FP32 and compare")
+    ap.add_argument("--cpu-baseline", type=int, default=1,
+                    help="1: time the oracle on sampled guiding groups (all threads and one)")
+    ap.add_argument("--bf16", type=int, default=1,
+                    help="1: also run the workload with BF16 fitness (its own roofline, its "
+                         "error and top-k agreement against the oracle)")
+    ap.add_argument("--gmm-study", type=int, default=1,
+                    help="1: also run the 64-128-128-10 workload in FP32")
+    ap.add_argument("--latency-study", type=int, default=1,
+                    help="1: per-generation latency of the 8-16-1 workload (graph replays)")
     ap.add_argument("--batch-study", type=int, default=1,
                     help="1: also run 64 mixed-shape BF16 jobs as one batched graph per generation")
     ap.add_argument("--serving-study", type=int, default=1,
                     help="1: also run a Poisson stream of mixed jobs through the serving loop")
-    ap.add_argument("--serve-seconds", type=float, default=8.0, help="arrival window of that study")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of that study")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: autotune the fitness launches before timing (mgfwa_autotune)")
     ap.add_argument("--testbed-study", type=int, default=1,
@@ -139,105 +149,170 @@ def run_gpu(wl, precision, steps, warmup, seed, autotune=True):
     torch.cuda.synchronize()
     graph_ms = gs.elapsed_time(ge)
     x, best, gen = g.best()
+    se_written = g.sparks_materialised
     g.close()
-    return dict(C=C, ms=ms, wall=wall, timing=tinfo, graph_ms=graph_ms, best=best, gen=gen)
+    return dict(C=C, ms=ms, wall=wall, timing=tinfo, graph_ms=graph_ms, best=best, gen=gen,
+                se_written=se_written)
 
 
-def cpu_baseline(wl, seconds, seed):
-    """Oracle on a bounded sample: initial fireworks, then generation-1 explosion
-    sparks and their binary64 fitness, in chunks until the time budget is spent."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# guiding groups (firework, group) whose sparks are scored by the oracle: one per
+# quarter of the population, a different group index each
+SAMPLE_GROUPS = ((0, 0), (5, 1), (10, 2), (15, 3))
+
+
+def sample_generation(wl, seed, gens=3):
+    """The explosion sparks of generation gens+1 of an FP32 run (the library's
+    ask writes them to the workspace), with their fitness from the library's FP32
+    and BF16 kernels; host copies of the rows of SAMPLE_GROUPS for the oracle."""
+    import numpy as np
+    import torch
+
+    from paper_2501_03944_amd import mgfwa as M
+
+    lam, G = wl.n_sparks, wl.n_guiding
+    m = lam // G
+    g32 = M.MGFWA.from_workload(wl, precision="fp32", seed=seed)
+    g32.step(gens)
+    W = g32.ask()
+    y32 = g32.evaluate(W)
+    g16 = M.MGFWA.from_workload(wl, precision="bf16", seed=seed)
+    y16 = g16.evaluate(W)
+    torch.cuda.synchronize()
+    groups = [(f, g) for f, g in SAMPLE_GROUPS if f < wl.n_fireworks and g < G]
+    idx = np.concatenate([np.arange(f * lam + g * m, f * lam + (g + 1) * m) for f, g in groups])
+    rows = W[torch.from_numpy(idx).to(W.device)][:, :wl.dim].cpu().numpy()
+    out = dict(t=gens + 1, groups=groups, idx=idx, rows=rows, m=m,
+               y32=y32.cpu().numpy().reshape(-1, lam), y16=y16.cpu().numpy().reshape(-1, lam))
+    g16.close()
+    g32.close()
+    return out
+
+
+def cpu_baseline(wl, sample, one_core_rows=4):
+    """The oracle on a bounded sample: the binary64 fitness of the sampled guiding
+    groups' sparks on all host threads, and of a few of them on one thread.  The
+    values also measure the GPU paths' error (returned beside the timing)."""
     import numpy as np
 
     from oracle import oracle as O
 
     p = O.Problem.from_workload(wl)
-    cfg = O.make_config(N=wl.n_fireworks, lam=wl.n_sparks, G=wl.n_guiding, lb=wl.lb, ub=wl.ub,
-                        T=wl.generations, seed=seed)
-    D = wl.dim
-    a0 = np.float32(cfg.ub) - np.float32(cfg.lb)
+    rows = sample["rows"]
+    nthreads = O.threads(0)
     t0 = time.perf_counter()
-    F = np.stack([O.init_row(cfg, D, f, 0) for f in range(wl.n_fireworks)])
-    evals = 0
-    chunk = 16
-    rows_total = wl.n_fireworks * wl.n_sparks
-    while evals < rows_total:
-        rows = range(evals, min(evals + chunk, rows_total))
-        S = np.stack([O.explosion_row(cfg, F[r // wl.n_sparks], a0, r, 1) for r in rows])
-        p.loss_rows(S)
-        evals += len(rows)
-        if time.perf_counter() - t0 > seconds:
-            break
+    y64 = p.loss_rows(rows)
     dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=evals / dt, unit="spark-evals/s", cores=threads, kind="oracle",
-                sample=f"{evals} generation-1 explosion sparks of the same workload (plus the "
-                       f"initial fireworks), binary64 fitness, {dt:.1f} s")
+    n1 = min(one_core_rows, len(rows))
+    O.threads(1)
+    t1 = time.perf_counter()
+    y1 = p.loss_rows(rows[:n1])
+    dt1 = time.perf_counter() - t1
+    O.threads(nthreads)
+    assert np.array_equal(y1, y64[:n1]), "oracle fitness depends on its thread count"
+    what = (f"{len(rows)} explosion sparks of generation {sample['t']} of the same workload "
+            f"({len(sample['groups'])} guiding groups of {sample['m']}), binary64 fitness")
+    rec = dict(value=len(rows) / dt, unit="spark-evals/s", cores=nthreads, kind="oracle",
+               sample=f"{what}, {dt:.1f} s", cpu_model=cpu_model(), host_cpus=os.cpu_count(),
+               one_core=dict(value=n1 / dt1, unit="spark-evals/s", cores=1,
+                             sample=f"the first {n1} of those sparks, {dt1:.1f} s"))
+    return rec, y64
 
 
-def topk_agreement(y_run, y_ref, lam, G, sigma):
-    """Guiding-group decisions (top and bottom k members of each group of m sparks)
-    taken on y_run against those taken on y_ref, both [fireworks, lam] numpy."""
+def group_agreement(y_run, y_ref, m, k):
+    """Guiding-group decisions taken on y_run against those taken on y_ref (both
+    [groups, m]): top-k and bottom-k members, whole sets, and the group's best."""
     import numpy as np
 
-    m = lam // G
+    overlap = same = best = 0
+    for a, b in zip(y_run, y_ref):
+        oa, ob = np.argsort(a, kind="stable"), np.argsort(b, kind="stable")
+        ta, tb, ba, bb = set(oa[:k]), set(ob[:k]), set(oa[-k:]), set(ob[-k:])
+        overlap += len(ta & tb) + len(ba & bb)
+        same += (ta == tb) and (ba == bb)
+        best += oa[0] == ob[0]
+    n = len(y_run)
+    return dict(topk_member_agreement=overlap / (2.0 * k * n), topk_groups_identical=same / n,
+                group_best_agreement=best / n, groups=n, k=k, m=m)
+
+
+def error_stats(y_run, y_ref):
+    import numpy as np
+
+    y_run, y_ref = np.asarray(y_run, np.float64).ravel(), np.asarray(y_ref, np.float64).ravel()
+    rel = np.abs(y_run - y_ref) / np.maximum(np.abs(y_ref), 1e-30)
+    return dict(sparks=int(rel.size), rel_err_max=float(rel.max()),
+                rel_err_median=float(np.median(rel)))
+
+
+def vs_reference(y_run, y_ref, m, sigma=0.2):
+    """Error and guiding-group agreement of y_run ([groups, m]) against y_ref."""
     k = max(1, int(sigma * m))
-    same_sets = overlap = groups = 0
-    for f in range(y_run.shape[0]):
-        for g in range(G):
-            a, b = y_run[f, g * m:(g + 1) * m], y_ref[f, g * m:(g + 1) * m]
-            oa, ob = np.argsort(a, kind="stable"), np.argsort(b, kind="stable")
-            ta, tb = set(oa[:k]), set(ob[:k])
-            ba, bb = set(oa[-k:]), set(ob[-k:])
-            overlap += len(ta & tb) + len(ba & bb)
-            same_sets += (ta == tb) and (ba == bb)
-            groups += 1
-    best_same = float(np.mean(np.argmin(y_run, axis=1) == np.argmin(y_ref, axis=1)))
-    return dict(member_agreement=overlap / (2.0 * k * groups),
-                groups_identical=same_sets / groups, best_spark_agreement=best_same, k=k, m=m)
+    return dict(**error_stats(y_run, y_ref), **group_agreement(y_run, y_ref, m, k))
 
 
-def precision_study(steps, seed, gens=3):
-    """784-256-10 in BF16 and FP32: throughput of each, and for the sparks of the
-    first generations of the BF16 run, the BF16 fitness against the FP32 fitness
-    of the same sparks (relative error, guiding top/bottom-k and best-spark
-    agreement)."""
+def sampled_groups(y, sample, lam):
+    """[groups, m] fitness of the sampled guiding groups from a [fireworks, lam] array."""
     import numpy as np
-    import torch
 
-    from paper_2501_03944_amd import inputs
-    from paper_2501_03944_amd import mgfwa as M
+    m = sample["m"]
+    return np.stack([y[f, g * m:(g + 1) * m] for f, g in sample["groups"]])
 
-    wl = inputs.workload("mlp784-256-10")
+
+def kernel_roofline(wl, precision, fit_ms, workload_name):
+    """Roofline record of the explosion-spark fitness kernel from its average
+    launch duration (HIP events on the library's stream)."""
+    rows = wl.n_fireworks * wl.n_sparks
+    flops = wl.flops_per_eval() * rows
+    achieved = flops / (fit_ms / 1e3) / 1e12
+    peak = PEAK_TFLOPS[precision]
+    traffic, traffic_src = measured_traffic(workload_name, precision)
+    es = 4 if precision == "fp32" else 2
+    wide = workload_name == "mlp784-256-10"
+    testbed = getattr(wl, "net", None) is not None
+    if testbed:   # every spark (the network input) once, the fixed parameters once
+        alg_bytes = rows * wl.dim * 4 + wl.n_params * 4
+        kernel = "k_net_input / k_net_layer (explosion-spark fitness, fixed network)"
+    else:         # every spark's weights once (the wide kernel reads them packed in its
+        # own precision), the samples once
+        alg_bytes = rows * wl.dim * (es if wide else 4) + wl.n_samples * wl.widths[0] * es
+        kernel = ("k_fit_wide_pipe" if precision == "bf16" else "k_fit_wide") if wide else "k_fit"
+        kernel += " (explosion-spark fitness)"
+    return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": traffic, "traffic_source": traffic_src,
+            "algorithmic_bytes": alg_bytes, "kernel": kernel, "flop_per_launch": flops,
+            "avg_launch_ms": fit_ms}
+
+
+def phase_hbm(wl, precision, timing, steps, se_written, wide):
+    """HBM rate of the state-path phases from their algorithmic bytes per
+    generation: explosion (writes every spark once in the layout the fitness reads,
+    plus the FP32 rows when they are stored; reads each firework row), guiding
+    (writes the guiding sparks; reads each firework row, and the 2k member rows of
+    every group when they are stored rather than regenerated), selection (at most
+    one candidate row read and one firework row written per firework, plus the
+    best row)."""
+    BN, lam, G, D = wl.n_fireworks, wl.n_sparks, wl.n_guiding, wl.dim
+    k = max(1, int(0.2 * (lam // G)))
+    es = (4 if precision == "fp32" else 2) if wide else 4
+    expl = BN * lam * D * es + (BN * lam * D * 4 if wide and se_written else 0) + BN * D * 4
+    guide = BN * G * D * 4 + BN * D * 4 + (0 if not se_written else BN * G * 2 * k * D * 4)
+    select = 2 * BN * D * 4 + D * 4
     out = {}
-    for prec in ("bf16", "fp32"):
-        r = run_gpu(wl, prec, steps, 1, seed)
-        out[prec] = dict(spark_evals_per_s=r["C"] * steps / (r["ms"] / 1e3),
-                         ms_per_step=r["ms"] / steps,
-                         fit_kernel_tflops=wl.flops_per_eval() * wl.n_fireworks * wl.n_sparks
-                         / (r["timing"]["fit_kernel_ms"] / steps / 1e3) / 1e12)
-    g16 = M.MGFWA.from_workload(wl, precision="bf16", seed=seed)
-    g32 = M.MGFWA.from_workload(wl, precision="fp32", seed=seed)
-    lam, N = wl.n_sparks, wl.n_fireworks
-    rel, agree = [], []
-    for _ in range(gens):
-        g16.step(1)
-        st = g16.state()
-        y16 = st["Yc"][:, :lam].float().cpu().numpy()
-        y32 = g32.evaluate(st["SE"]).view(N, lam).cpu().numpy()
-        rel.append(np.abs(y16 - y32) / np.maximum(np.abs(y32), 1e-30))
-        agree.append(topk_agreement(y16, y32, lam, wl.n_guiding, 0.2))
-    torch.cuda.synchronize()
-    g16.close()
-    g32.close()
-    rel = np.concatenate([r.ravel() for r in rel])
-    out["bf16_vs_fp32"] = dict(
-        generations=gens, sparks=int(rel.size),
-        rel_err_max=float(rel.max()), rel_err_median=float(np.median(rel)),
-        topk_member_agreement=float(np.mean([a["member_agreement"] for a in agree])),
-        topk_groups_identical=float(np.mean([a["groups_identical"] for a in agree])),
-        best_spark_agreement=float(np.mean([a["best_spark_agreement"] for a in agree])),
-        k=agree[0]["k"], group_size=agree[0]["m"])
-    out["bf16_speedup"] = out["bf16"]["spark_evals_per_s"] / out["fp32"]["spark_evals_per_s"]
+    for name, phase, nbytes in (("explosion", "explosion", expl), ("guiding", "guiding", guide),
+                                ("selection", "selection", select)):
+        ms = timing["phase_ms"][phase] / steps
+        out[name] = dict(bytes=nbytes, ms=ms, GB_s=nbytes / (ms / 1e3) / 1e9,
+                         frac_of_8TB_s=nbytes / (ms / 1e3) / 8e12)
     return out
 
 
@@ -416,6 +491,58 @@ def testbed_study(steps, seed, warmup=3):
     return {"fireworks": 8, "sparks": 512, "guiding": 8, "steps": steps, "nets": out}
 
 
+def latency_study(seed, gens=100, warmup=5):
+    """Per-generation latency of the 8-16-1 workload (4 fireworks x 32 sparks): each
+    generation one HIP graph replay, bracketed by its own events."""
+    import numpy as np
+    import torch
+
+    from paper_2501_03944_amd import inputs
+    from paper_2501_03944_amd import mgfwa as M
+
+    wl = inputs.workload("mlp8-16-1")
+    g = M.MGFWA.from_workload(wl, seed=seed, max_generations=gens + warmup)
+    g.step(warmup)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(gens)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(g.stream)
+        g.step(1)
+        b.record(g.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    _, best, gen = g.best()
+    g.close()
+    C = wl.n_fireworks * (wl.n_sparks + wl.n_guiding)
+    return dict(workload=WORKLOAD_TAG["mlp8-16-1"], generations=gens,
+                gen_latency_ms={"p50": float(np.percentile(ms, 50)),
+                                "p99": float(np.percentile(ms, 99)), "mean": float(ms.mean())},
+                host_ms_per_generation=wall / gens * 1e3,
+                spark_evals_per_s=C * gens / wall, best_fitness=best)
+
+
+def workload_record(name, precision, steps, warmup, seed, autotune):
+    """Throughput and fitness-kernel roofline of one workload at one precision."""
+    from paper_2501_03944_amd import inputs
+
+    wl = inputs.workload(name)
+    r = run_gpu(wl, precision, steps, warmup, seed, autotune)
+    t = r["timing"]
+    rec = dict(workload=WORKLOAD_TAG[name], precision=precision,
+               value=r["C"] * steps / (r["ms"] / 1e3), unit="spark-evals/s",
+               ms_per_step=r["ms"] / steps,
+               roofline=kernel_roofline(wl, precision, t["fit_kernel_ms"] / steps, name),
+               gen_latency_ms={"p50": t["gen_ms_p50"], "p99": t["gen_ms_p99"]},
+               phase_ms_per_step={k: v / steps for k, v in t["phase_ms"].items()},
+               graph_ms_per_step=r["graph_ms"] / steps, best_fitness=r["best"])
+    if precision == "bf16":
+        rec["check_fit_ms_per_step"] = t["check_fit_ms"] / steps
+    return rec, r, wl
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -426,29 +553,15 @@ def main():
 
     wl = inputs.workload(args.workload)
     precision = args.precision or "fp32"
+    testbed = getattr(wl, "net", None) is not None
     calibration_copy(args.calib_copy_mib)
     r = run_gpu(wl, precision, args.steps, args.warmup, args.seed, bool(args.autotune))
     K = args.steps
-    value = r["C"] * K / (r["ms"] / 1e3)
     t = r["timing"]
-    rows = wl.n_fireworks * wl.n_sparks
-    flops = wl.flops_per_eval() * rows
-    fit_ms = t["fit_kernel_ms"] / K
-    achieved = flops / (fit_ms / 1e3) / 1e12
-    peak = PEAK_TFLOPS[precision]
-    traffic, traffic_src = measured_traffic(args.workload, precision)
-    # algorithmic bytes of one launch: every spark's weights once (the wide kernel
-    # reads them packed in its own precision), the samples once
-    es = 4 if precision == "fp32" else 2
     wide = args.workload == "mlp784-256-10"
-    testbed = getattr(wl, "net", None) is not None
-    if testbed:   # every spark (the network input) once, the fixed parameters once
-        alg_bytes = rows * wl.dim * 4 + wl.n_params * 4
-    else:
-        alg_bytes = rows * wl.dim * (es if wide else 4) + wl.n_samples * wl.widths[0] * es
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": r["C"] * K / (r["ms"] / 1e3),
         "unit": "spark-evals/s",
         "n_gpus": 1,
         "steps": K,
@@ -464,30 +577,52 @@ def main():
                    "samples": 0 if testbed else wl.n_samples,
                    "D": wl.dim, "precision": precision, "autotuned": bool(args.autotune),
                    "parallelism": "single-gpu"},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": traffic, "traffic_source": traffic_src,
-                     "algorithmic_bytes": alg_bytes,
-                     "kernel": ("k_net_input (explosion-spark fitness, fixed network)" if testbed
-                                else "k_fit (explosion-spark fitness)"),
-                     "flop_per_launch": flops, "avg_launch_ms": fit_ms},
-        "mfma_pct_peak": 100.0 * achieved / peak,
+        "roofline": kernel_roofline(wl, precision, t["fit_kernel_ms"] / K, args.workload),
         "gen_latency_ms": {"p50": t["gen_ms_p50"], "p99": t["gen_ms_p99"],
                            "mean": t["gen_ms_mean"]},
         "phase_ms_per_step": {k: v / K for k, v in t["phase_ms"].items()},
+        "state_path_hbm": None if testbed else phase_hbm(wl, precision, t, K, r["se_written"], wide),
         "graph_ms_per_step": r["graph_ms"] / K,
         "best_fitness": r["best"],
         "generations_run": r["gen"],
     }
-    if args.precision_study:
-        line["precision_study"] = precision_study(max(2, min(K, 5)), args.seed)
+    line["mfma_pct_peak"] = 100.0 * line["roofline"]["frac"]
+    bf16 = None
+    if args.bf16 and precision == "fp32" and not testbed:
+        bf16, rb, _ = workload_record(args.workload, "bf16", K, args.warmup, args.seed,
+                                      bool(args.autotune))
+        bf16["dtype"] = "bf16"
+        bf16["state_path_hbm"] = phase_hbm(wl, "bf16", rb["timing"], K, rb["se_written"], wide)
+        bf16["speedup_vs_fp32"] = bf16["value"] / line["value"]
+        line["bf16"] = bf16
+    sample = None
+    if not testbed and (bf16 is not None or args.cpu_baseline):
+        sample = sample_generation(wl, args.seed)
+        if bf16 is not None:   # every explosion spark of the sampled generation: BF16 vs FP32
+            m = sample["m"]
+            y16 = sample["y16"].reshape(-1, m)
+            y32 = sample["y32"].reshape(-1, m)
+            bf16["vs_fp32_gpu"] = dict(generation=sample["t"], **vs_reference(y16, y32, m))
+    if args.gmm_study and args.workload != "mlp64-128-128-10":
+        line["gmm_study"], _, _ = workload_record("mlp64-128-128-10", "fp32", K, args.warmup,
+                                                  args.seed, bool(args.autotune))
+    if args.latency_study:
+        line["latency_study"] = latency_study(args.seed)
     if args.serving_study:
         line["serving_study"] = serving_study(args.serve_seconds, args.seed)
     if args.batch_study:
         line["batch_study"] = batch_study(max(2, min(K, 10)), args.seed)
     if args.testbed_study:
         line["testbed_study"] = testbed_study(max(2, min(K, 20)), args.seed)
-    if args.cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds, args.seed)
+    if args.cpu_baseline and sample is not None:
+        rec, y64 = cpu_baseline(wl, sample)
+        line["cpu_baseline"] = rec
+        y64 = y64.reshape(-1, sample["m"])
+        line["fp32_vs_oracle"] = dict(generation=sample["t"], **vs_reference(
+            sampled_groups(sample["y32"], sample, wl.n_sparks), y64, sample["m"]))
+        if bf16 is not None:
+            bf16["vs_oracle"] = dict(generation=sample["t"], **vs_reference(
+                sampled_groups(sample["y16"], sample, wl.n_sparks), y64, sample["m"]))
     print(json.dumps(line), flush=True)
 
 

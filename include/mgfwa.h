@@ -119,7 +119,12 @@ typedef struct {
  *   lb, ub    search box [lb, ub]^D
  *   max_generations   T, the budget the loser-out prediction uses (>= 1)
  *   loser_out 1 enables the loser-out tournament
- *   precision fitness GEMMs in FP32, or BF16 operands with FP32 accumulation
+ *   precision fitness GEMMs in FP32, or BF16 operands with FP32 accumulation.
+ *             With BF16 the candidates are ranked on their BF16 fitness (guiding
+ *             groups, each firework's best candidate), and that best candidate is
+ *             re-evaluated in FP32 before the selection compares it with its
+ *             firework (Alg. 1, selection step), so the firework, initial and
+ *             best-so-far fitness are FP32 values in every run
  *   external_fitness  1: no fitness kernels, the caller tells every fitness
  *   use_target, target_loss  stop once a population's best <= target_loss
  *   seed      key of the counter-based generator
@@ -214,6 +219,8 @@ typedef struct {
     double gen_ms_p50, gen_ms_p99, gen_ms_mean; /* whole-generation device time */
     double fit_kernel_ms;       /* explosion-spark fitness GEMM kernel(s) alone (subset of
                                    ms[1]; the layer-by-layer launches of an input problem) */
+    double check_fit_ms;        /* BF16 runs: the FP32 fitness launch of the selection
+                                   re-check (subset of ms[4]); 0 otherwise */
     int generations;            /* generations measured since timing was switched on */
 } mgfwa_timing_info;
 

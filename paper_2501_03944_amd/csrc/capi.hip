@@ -54,7 +54,9 @@ int round_up(int v, int a) { return (v + a - 1) / a * a; }
 struct Layout {
     size_t F, SE, SG, A, Aexp, Y, Yprev, fresh, Yc, top, bottom, tie, cstar, improved, reinit, src;
     size_t best_x, best_y, best_f, best_gen, best_upd, ctrl, partial, Xp, Xb, Ypad, Lpad;
-    size_t Wpack, Xw, lo, hi, Pnet, H0, H1, Zero, total;
+    size_t Wpack, Xw, lo, hi, Pnet, H0, H1, Zero;
+    size_t Wstar, Ystar, Xp32, Wpack32, Xw32;   // FP32 re-check of BF16 selection winners
+    size_t total;
     int partial_rows;
 };
 
@@ -63,6 +65,7 @@ enum Phase { PH_READY, PH_INIT_ASK, PH_INIT_TELL, PH_EXPL_TELL, PH_GUIDE_ASK, PH
 struct Derived {
     Shape s;
     Net net;
+    Net net32;       // BF16 runs: the same network in FP32 (selection re-check)
     InNet in;        // input problems: the fixed network
     bool input;
     Layout lay;
@@ -233,6 +236,16 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
     // not stored, and the guiding and apply steps regenerate the sparks they
     // need (the lag order reads the previous generation's sparks: it keeps them).
     s.regen = net.wide && !s.lag ? 1 : 0;
+    // BF16 fitness ranks the candidates; the winner of each firework is
+    // re-evaluated in FP32 before the selection compares it, so the firework and
+    // best-so-far fitness stay FP32 (and so does the initial fitness)
+    s.recheck = !input && net.bf16 && need_data ? 1 : 0;
+    Net &net32 = out->net32;
+    net32 = net;
+    if (s.recheck) {
+        net32.bf16 = 0;
+        net32.in_pad = round_up(net.fi[0], 16);
+    }
 
     Layout &L = out->lay;
     size_t off = 0;
@@ -282,6 +295,11 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
     L.H0 = take(hbytes);
     L.H1 = take(hbytes);
     L.Zero = take(input && need_data ? 256 : 0);
+    L.Wstar = take(s.recheck ? BN * Dp * 4 : 0);
+    L.Ystar = take(s.recheck ? BN * 4 : 0);
+    L.Xp32 = take(s.recheck && !net.wide ? (size_t)net32.S_pad * net32.in_pad * 4 : 0);
+    L.Wpack32 = take(s.recheck && net.wide ? BN * wide_row_bytes(net32) : 0);
+    L.Xw32 = take(s.recheck && net.wide ? (size_t)net32.S_pad * wide_kp(net32) * 4 : 0);
     L.total = off;
     if (s.lag && L.SG != L.SE + BN * s.lam * Dp * 4)
         return fail(MGFWA_EINVAL, "internal: guiding sparks must follow the explosion sparks");
@@ -294,6 +312,9 @@ struct mgfwa_ctx {
     mgfwa_config cfg;
     Shape s;
     Net net;
+    Net net32;          // BF16 runs: the FP32 network of the selection re-check
+    DevState d32;       // ... and its FP32 sample buffers (shares the rest of d)
+    FitPlan plan_check; // ... and its launch over the B*N gathered rows
     InNet in;
     bool input = false;
     Layout lay;
@@ -316,6 +337,7 @@ struct mgfwa_ctx {
     std::vector<double> gen_ms;
     double phase_ms[MGFWA_N_PHASES] = {0, 0, 0, 0, 0};
     double fit_kernel_ms = 0.0;
+    double check_ms = 0.0;
 };
 
 namespace {
@@ -340,6 +362,7 @@ mgfwa_status check(mgfwa_ctx *c, hipError_t e, const char *what)
     } while (0)
 
 const OutMap kFlat = {1, 1, 0};
+constexpr int N_EVENTS = 10;   // per timed generation (enqueue_generation)
 
 // The explosion-fitness launch: BN*lambda explosion sparks into the first
 // lambda candidate slots or, in the lag order, those followed by the BN*G
@@ -372,6 +395,19 @@ mgfwa_status fit_rows(mgfwa_ctx *c, const FitPlan &plan, const float *W, size_t 
     return MGFWA_OK;
 }
 
+// FP32 fitness of `rows` rows of W (leading dimension Dp) into out[0..rows): the
+// selection re-check of a BF16 run (the FP32 network and sample buffers).
+mgfwa_status fit_check(mgfwa_ctx *c, const float *W, int rows, float *out, hipStream_t st)
+{
+    if (c->net32.wide)
+        STEP(launch_fitness_wide(c->net32, c->d32, W, c->s.Dp, rows, kFlat, out, st),
+             "fitness_check_wide");
+    else
+        STEP(launch_fitness(c->net32, c->plan_check, c->d32, W, c->s.Dp, rows, kFlat, out, st),
+             "fitness_check");
+    return MGFWA_OK;
+}
+
 hipEvent_t take_event(mgfwa_ctx *c)
 {
     if (!c->pool.empty()) {
@@ -384,9 +420,10 @@ hipEvent_t take_event(mgfwa_ctx *c)
     return e;
 }
 
-// Enqueue one generation on `st`; ev (7 events) brackets the five phases when
-// non-null, ev[6] marks the end of the explosion-fitness GEMM kernel and ev[7]
-// its start (after the wide kernel's packing; ev[1] serves otherwise).
+// Enqueue one generation on `st`; ev (N_EVENTS events) brackets the five phases
+// when non-null, ev[6] marks the end of the explosion-fitness GEMM kernel and
+// ev[7] its start (after the wide kernel's packing; ev[1] serves otherwise);
+// ev[8] and ev[9] bracket the FP32 re-check launch of a BF16 run.
 //
 // The lag order (Alg. 1 as printed) builds the guiding sparks from the sparks
 // and fitness the previous generation left in SE and Yc before exploding, then
@@ -421,8 +458,16 @@ mgfwa_status enqueue_generation(mgfwa_ctx *c, hipStream_t st, hipEvent_t *ev)
         if (r) return r;
     }
     if (ev) STEP(hipEventRecord(ev[4], st), "event");
-    STEP(launch_select(s, c->d, st), "select");
-    STEP(launch_apply(s, c->d, st), "apply");
+    if (s.recheck) {
+        // each firework's best candidate by its BF16 fitness, re-evaluated in FP32
+        STEP(launch_gather_best(s, c->d, st), "gather_best");
+        if (ev) STEP(hipEventRecord(ev[8], st), "event");
+        r = fit_check(c, c->d.Wstar, s.BN, c->d.Ystar, st);
+        if (r) return r;
+        if (ev) STEP(hipEventRecord(ev[9], st), "event");
+    }
+    STEP(launch_select(s, c->d, st, s.recheck), "select");
+    STEP(launch_apply(s, c->d, st, s.recheck), "apply");
     STEP(launch_finish(c->d, 1, st), "finish");
     if (ev) STEP(hipEventRecord(ev[5], st), "event");
     return MGFWA_OK;
@@ -521,6 +566,21 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
             return fail(MGFWA_EUNSUPPORTED, "no compiled fitness kernel covers this MLP shape");
         for (const FitPlan *fp : {&pi, &pe, &pg, &pv}) HIP_TRY(fit_prepare(*fp));
     }
+    FitPlan pc{};
+    if (dv.s.recheck) {
+        dv.net32.lds_max = dv.net.lds_max;
+        dv.net32.num_cu = dv.net.num_cu;
+        if (dv.net32.wide) {
+            if (wide_lds_bytes(dv.net32) > lds_max - 64)
+                return fail(MGFWA_EUNSUPPORTED, "device LDS too small for the FP32 wide kernel");
+            HIP_TRY(wide_prepare(dv.net32));
+        } else {
+            if (!fit_select(dv.net32, dv.s.BN, &pc))
+                return fail(MGFWA_EUNSUPPORTED, "no compiled FP32 fitness kernel covers this MLP "
+                                                "shape (needed to re-check BF16 selections)");
+            HIP_TRY(fit_prepare(pc));
+        }
+    }
 
     mgfwa_ctx *c = new mgfwa_ctx();
     c->cfg = *config;
@@ -536,6 +596,8 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
     c->plan_expl = pe;
     c->plan_guide = pg;
     c->plan_eval = pv;
+    c->net32 = dv.net32;
+    c->plan_check = pc;
     const char *ev = std::getenv("MGFWA_NO_GRAPH");
     c->use_graph = !(ev && ev[0] == '1');
     ev = std::getenv("MGFWA_SYNC_DEBUG");
@@ -578,6 +640,16 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
     d.H0 = c->input && has_data ? at<float>(b, L.H0) : nullptr;
     d.H1 = c->input && has_data ? at<float>(b, L.H1) : nullptr;
     d.zero = c->input && has_data ? at<float>(b, L.Zero) : nullptr;
+    d.Wstar = c->s.recheck ? at<float>(b, L.Wstar) : nullptr;
+    d.Ystar = c->s.recheck ? at<float>(b, L.Ystar) : nullptr;
+    // the re-check's FP32 view: its own packed samples and spark rows
+    c->d32 = d;
+    if (c->s.recheck) {
+        c->d32.Xb = nullptr;
+        c->d32.Xp = c->net32.wide ? nullptr : at<float>(b, L.Xp32);
+        c->d32.Wpack = c->net32.wide ? at<char>(b, L.Wpack32) : nullptr;
+        c->d32.Xw = c->net32.wide ? at<char>(b, L.Xw32) : nullptr;
+    }
 
     auto bail = [&](mgfwa_status st) {
         mgfwa_destroy(c);
@@ -603,13 +675,24 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
                                         c->stream), "zero Wpack");
             if (r) return bail(r);
         }
+        if (c->s.recheck) {   // FP32 samples of the selection re-check
+            r = c->net32.wide
+                    ? check(c, launch_pack_wide_x(c->net32, problem->x_dev, c->d32.Xw, c->stream),
+                            "pack_x32")
+                    : check(c, launch_pack_problem(c->net32, problem->x_dev, problem->y_dev,
+                                                   problem->labels_dev, c->d32, c->stream),
+                            "pack32");
+            if (r) return bail(r);
+        }
     }
     r = check(c, launch_init_positions(c->s, d, c->stream), "init_positions");
     if (r) return bail(r);
     if (config->external_fitness) {
         c->phase = PH_INIT_ASK;
     } else {
-        r = fit_rows(c, c->plan_init, d.F, c->s.Dp, c->s.BN, kFlat, d.Y, c->stream);
+        // the firework fitness is FP32 in every run (BF16 runs: the re-check's launch)
+        r = c->s.recheck ? fit_check(c, d.F, c->s.BN, d.Y, c->stream)
+                         : fit_rows(c, c->plan_init, d.F, c->s.Dp, c->s.BN, kFlat, d.Y, c->stream);
         if (r) return bail(r);
         r = finish_init(c);
         if (r) return bail(r);
@@ -627,7 +710,7 @@ mgfwa_status mgfwa_step(mgfwa_ctx *c, int n)
     if (c->phase != PH_READY) return fail(MGFWA_ESTATE, "an ask/tell exchange is in progress");
     for (int i = 0; i < n; ++i) {
         if (c->timing) {
-            std::vector<hipEvent_t> ev(8);
+            std::vector<hipEvent_t> ev(N_EVENTS);
             for (auto &e : ev) {
                 e = take_event(c);
                 if (!e) return fail(MGFWA_EHIP, "hipEventCreate failed");
@@ -821,6 +904,7 @@ mgfwa_status mgfwa_set_timing(mgfwa_ctx *c, int on)
     c->gen_ms.clear();
     for (double &v : c->phase_ms) v = 0.0;
     c->fit_kernel_ms = 0.0;
+    c->check_ms = 0.0;
     c->timing = on != 0;
     return MGFWA_OK;
 }
@@ -837,6 +921,10 @@ mgfwa_status mgfwa_timing(mgfwa_ctx *c, mgfwa_timing_info *info)
         }
         HIP_TRY(hipEventElapsedTime(&ms, c->net.wide ? ev[7] : ev[1], ev[6]));
         c->fit_kernel_ms += ms;
+        if (c->s.recheck) {
+            HIP_TRY(hipEventElapsedTime(&ms, ev[8], ev[9]));
+            c->check_ms += ms;
+        }
         HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[MGFWA_N_PHASES]));
         c->gen_ms.push_back(ms);
         for (hipEvent_t e : ev) c->pool.push_back(e);
@@ -844,6 +932,7 @@ mgfwa_status mgfwa_timing(mgfwa_ctx *c, mgfwa_timing_info *info)
     c->pending.clear();
     for (int p = 0; p < MGFWA_N_PHASES; ++p) info->ms[p] = c->phase_ms[p];
     info->fit_kernel_ms = c->fit_kernel_ms;
+    info->check_fit_ms = c->check_ms;
     info->generations = (int)c->gen_ms.size();
     info->gen_ms_p50 = info->gen_ms_p99 = info->gen_ms_mean = 0.0;
     if (!c->gen_ms.empty()) {

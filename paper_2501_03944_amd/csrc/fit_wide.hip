@@ -184,6 +184,9 @@ int wide_group(const Net &net, int rows, int ntn)
             best_cost = cost;
         }
     }
+    // a small launch (e.g. one row per firework) gives every XCD a group while
+    // the groups still hold a tile per block
+    while (best > 1 && rows / best < 8 && (best / 2) * ntn >= bx) best /= 2;
     return best;
 }
 

@@ -43,6 +43,8 @@ struct DevState {
     float *Pnet;       // packed parameters of a fixed network (input problems)
     float *H0, *H1;    // [partial_rows][hnp] activations between layers (input problems)
     float *zero;       // 256 zero bytes (input problems)
+    float *Wstar;      // [B*N][Dp] each firework's best candidate (FP32 re-check of BF16 runs)
+    float *Ystar;      // [B*N] its FP32 fitness
 };
 
 // Population shape and algorithm constants as the kernels need them.
@@ -58,6 +60,8 @@ struct Shape {
     int map_range;                     // random mapping into the population's range
     int regen;                         // the guiding and apply steps regenerate explosion
                                        // sparks instead of reading SE
+    int recheck;                       // BF16 fitness: each firework's best candidate is
+                                       // re-evaluated in FP32 before the selection compares it
 };
 
 // MLP problem as the fitness kernels need it.
@@ -170,9 +174,16 @@ hipError_t launch_rank(const Shape &s, const DevState &d, hipStream_t st);
 hipError_t launch_guide(const Shape &s, const DevState &d, hipStream_t st);
 
 // ---- select.hip
-hipError_t launch_select(const Shape &s, const DevState &d, hipStream_t st);
+// checked: the best candidate of every firework was gathered into d.Wstar and its
+// FP32 fitness stored in d.Ystar (launch_gather_best); the selection compares
+// that value, and the apply step copies the gathered row.
+hipError_t launch_select(const Shape &s, const DevState &d, hipStream_t st, bool checked = false);
 hipError_t launch_init_select(const Shape &s, const DevState &d, hipStream_t st);
-hipError_t launch_apply(const Shape &s, const DevState &d, hipStream_t st);
+hipError_t launch_apply(const Shape &s, const DevState &d, hipStream_t st, bool checked = false);
+// Per firework: c* = argmin over its candidates' fitness (lower index on ties) into
+// d.cstar, and the candidate's row into d.Wstar (explosion sparks regenerated when
+// s.regen).
+hipError_t launch_gather_best(const Shape &s, const DevState &d, hipStream_t st);
 hipError_t launch_finish(const DevState &d, int advance, hipStream_t st);
 // Zero the control words (generation counter, stop flags) in stream order.
 hipError_t launch_clear_ctrl(int32_t *ctrl, hipStream_t st);

@@ -9,9 +9,15 @@
 //              in the previous generation is a loser when
 //              fma(-(Yprev - Y), max(T - t, 0), Y) > Y_b and restarts with A0 and
 //              fitness +inf.  Decisions go to src/reinit; rows move in k_apply.
+//              With BF16 fitness, c* is still taken on the BF16 values, but the
+//              comparison uses c*'s FP32 fitness (k_gather_best + an FP32 fitness
+//              launch), so firework and best-so-far fitness stay FP32.
 // k_apply   -- grid over (firework, 4-coordinate chunk): copies the chosen
 //              candidate row, or draws the restart position, and refreshes the
 //              best-so-far row.
+// k_gather_best -- (BF16 fitness) grid over (firework, 4-coordinate chunk):
+//              c* of every firework and that candidate's row, for its FP32
+//              re-evaluation before k_select compares it with the firework.
 // k_finish  -- one thread: advances the generation counter, raises the stop flag.
 #include "internal.h"
 
@@ -22,6 +28,34 @@ namespace {
 constexpr int TPB = 256;
 constexpr int MAX_GRID_Y = 65535;
 constexpr int SRC_NONE = -1;
+
+// Lowest candidate fitness of one firework and its index (lower index on ties),
+// over one wavefront: lanes scan strided candidates, then a (value, index)
+// butterfly; every lane returns the result.
+__device__ __forceinline__ void best_candidate(const float *yc, int C, int lane, float *ymin_out,
+                                               int *cs_out)
+{
+    float ymin = __int_as_float(0x7f800000);
+    int cs = 0x7fffffff;
+    for (int c = lane; c < C; c += 64) {
+        const float v = yc[c];
+        if (v < ymin || (v == ymin && c < cs)) {
+            ymin = v;
+            cs = c;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const float ov = __shfl_xor(ymin, off);
+        const int oc = __shfl_xor(cs, off);
+        if (ov < ymin || (ov == ymin && oc < cs)) {
+            ymin = ov;
+            cs = oc;
+        }
+    }
+    *ymin_out = ymin;
+    *cs_out = cs;
+}
 
 __device__ void population_best(const float *Y, int N, int *fb_out, float *yb_out)
 {
@@ -49,6 +83,7 @@ __global__ __launch_bounds__(TPB) void k_select(Shape s, float *__restrict__ Yc,
                                                 int32_t *__restrict__ best_f,
                                                 int32_t *__restrict__ best_gen,
                                                 int32_t *__restrict__ best_upd,
+                                                const float *__restrict__ ystar,
                                                 int32_t *__restrict__ ctrl)
 {
     if (ctrl[CTRL_DONE]) return;
@@ -56,29 +91,18 @@ __global__ __launch_bounds__(TPB) void k_select(Shape s, float *__restrict__ Yc,
     const int b = blockIdx.x, N = s.N;
     __shared__ int s_fb;
     __shared__ float s_yb;
-    // one wavefront per firework: lanes scan strided candidates, then a
-    // (value, index) butterfly keeps the lowest value and, on ties, the lowest index
+    // one wavefront per firework: c* and its fitness (with ystar, both come from
+    // the gather step: c* by the BF16 fitness, its value re-evaluated in FP32)
     const int lane = threadIdx.x & 63, nwave = blockDim.x >> 6;
     for (int f = threadIdx.x >> 6; f < N; f += nwave) {
         const int gf = b * N + f;
-        const float *yc = Yc + (size_t)gf * s.C;
-        float ymin = __int_as_float(0x7f800000);
-        int cs = 0x7fffffff;
-        for (int c = lane; c < s.C; c += 64) {
-            const float v = yc[c];
-            if (v < ymin || (v == ymin && c < cs)) {
-                ymin = v;
-                cs = c;
-            }
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const float ov = __shfl_xor(ymin, off);
-            const int oc = __shfl_xor(cs, off);
-            if (ov < ymin || (ov == ymin && oc < cs)) {
-                ymin = ov;
-                cs = oc;
-            }
+        float ymin;
+        int cs;
+        if (ystar) {
+            ymin = ystar[gf];
+            cs = cstar[gf];
+        } else {
+            best_candidate(Yc + (size_t)gf * s.C, s.C, lane, &ymin, &cs);
         }
         if (lane == 0) {
             const float yold = Y[gf];
@@ -165,7 +189,8 @@ __global__ __launch_bounds__(TPB) void k_init_select(Shape s, const float *__res
 
 // With s.regen a winning explosion spark is regenerated from the firework's
 // row (still the generation's, read before it is overwritten), its explosion
-// amplitude and the population range, exactly as the explosion drew it.
+// amplitude and the population range, exactly as the explosion drew it.  With
+// wstar the winner is the row k_gather_best stored there.
 __global__ __launch_bounds__(TPB) void k_apply(Shape s, float *__restrict__ F,
                                                const float *__restrict__ SE,
                                                const float *__restrict__ SG,
@@ -177,6 +202,7 @@ __global__ __launch_bounds__(TPB) void k_apply(Shape s, float *__restrict__ F,
                                                const int32_t *__restrict__ best_f,
                                                const int32_t *__restrict__ best_upd,
                                                float *__restrict__ best_x,
+                                               const float *__restrict__ wstar,
                                                const int32_t *__restrict__ ctrl)
 {
     if (ctrl[CTRL_DONE]) return;
@@ -201,6 +227,10 @@ __global__ __launch_bounds__(TPB) void k_apply(Shape s, float *__restrict__ F,
             }
             v = make_float4(e4[0], e4[1], e4[2], e4[3]);
             frow[chunk] = v;
+        } else if (sr >= 0 && wstar) {
+            // the gathered candidate row (the one its FP32 fitness was taken of)
+            v = reinterpret_cast<const float4 *>(wstar + (size_t)gf * s.Dp)[chunk];
+            frow[chunk] = v;
         } else if (sr >= 0 && sr < s.lam && s.regen) {
             const float4 x4 = frow[chunk];
             const float x[4] = {x4.x, x4.y, x4.z, x4.w};
@@ -219,6 +249,59 @@ __global__ __launch_bounds__(TPB) void k_apply(Shape s, float *__restrict__ F,
             v = frow[chunk];
         }
         if (copy_best) reinterpret_cast<float4 *>(best_x + (size_t)b * s.Dp)[chunk] = v;
+    }
+}
+
+// c* of firework blockIdx.y (every block recomputes it: C values, one
+// wavefront) and coordinates 4*chunk.. of its row: an explosion spark
+// (regenerated from the firework's row and amplitude when s.regen, as the
+// explosion drew it) or a guiding spark.  Runs before k_select, so F and A
+// still hold the generation's values.
+__global__ __launch_bounds__(TPB) void k_gather_best(Shape s, const float *__restrict__ Yc,
+                                                     const float *__restrict__ F,
+                                                     const float *__restrict__ A,
+                                                     const float *__restrict__ SE,
+                                                     const float *__restrict__ SG,
+                                                     const float *__restrict__ lo,
+                                                     const float *__restrict__ hi,
+                                                     int32_t *__restrict__ cstar,
+                                                     float *__restrict__ wstar,
+                                                     const int32_t *__restrict__ ctrl)
+{
+    if (ctrl[CTRL_DONE]) return;
+    const uint32_t t = (uint32_t)ctrl[CTRL_GEN] + 1u;
+    __shared__ int s_cs;
+    const int nchunk = s.Dp >> 2;
+    for (int gf = blockIdx.y; gf < s.BN; gf += gridDim.y) {
+        if (threadIdx.x < 64) {
+            float ymin;
+            int cs;
+            best_candidate(Yc + (size_t)gf * s.C, s.C, threadIdx.x, &ymin, &cs);
+            if (threadIdx.x == 0) {
+                s_cs = cs;
+                if (blockIdx.x == 0) cstar[gf] = cs;
+            }
+        }
+        __syncthreads();
+        const int cs = s_cs;
+        __syncthreads();   // s_cs is rewritten for the next firework
+        const int chunk = blockIdx.x * TPB + threadIdx.x;
+        if (chunk >= nchunk) continue;
+        float4 v;
+        if (cs < s.lam && s.regen) {
+            const float4 x4 = reinterpret_cast<const float4 *>(F + (size_t)gf * s.Dp)[chunk];
+            const float x[4] = {x4.x, x4.y, x4.z, x4.w};
+            const size_t pb = (size_t)(gf / s.N) * s.Dp;
+            float e4[4];
+            explosion_chunk(x, A[gf], s.key, chunk, (uint32_t)(gf * s.lam + cs), t, s.box,
+                            lo ? lo + pb : nullptr, hi ? hi + pb : nullptr, s.D, e4);
+            v = make_float4(e4[0], e4[1], e4[2], e4[3]);
+        } else {
+            const float *row = cs < s.lam ? SE + ((size_t)gf * s.lam + cs) * s.Dp
+                                          : SG + ((size_t)gf * s.G + (cs - s.lam)) * s.Dp;
+            v = reinterpret_cast<const float4 *>(row)[chunk];
+        }
+        reinterpret_cast<float4 *>(wstar + (size_t)gf * s.Dp)[chunk] = v;
     }
 }
 
@@ -247,12 +330,22 @@ __global__ __launch_bounds__(TPB) void k_store_fitness(const float *__restrict__
 
 }  // namespace
 
-hipError_t launch_select(const Shape &s, const DevState &d, hipStream_t st)
+hipError_t launch_select(const Shape &s, const DevState &d, hipStream_t st, bool checked)
 {
     hipLaunchKernelGGL(k_select, dim3(s.B), dim3(TPB), 0, st, s, d.Yc, d.Y, d.Yprev, d.A, d.Aexp,
                        d.fresh,
                        d.cstar, d.improved, d.reinit, d.src, d.best_y, d.best_f, d.best_gen,
-                       d.best_upd, d.ctrl);
+                       d.best_upd, checked ? d.Ystar : nullptr, d.ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_best(const Shape &s, const DevState &d, hipStream_t st)
+{
+    const int nchunk = s.Dp >> 2;
+    dim3 grid((nchunk + TPB - 1) / TPB, s.BN < MAX_GRID_Y ? s.BN : MAX_GRID_Y);
+    hipLaunchKernelGGL(k_gather_best, grid, dim3(TPB), 0, st, s, d.Yc, d.F, d.A, d.SE, d.SG,
+                       s.map_range ? d.lo : nullptr, s.map_range ? d.hi : nullptr, d.cstar,
+                       d.Wstar, d.ctrl);
     return hipGetLastError();
 }
 
@@ -263,13 +356,13 @@ hipError_t launch_init_select(const Shape &s, const DevState &d, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_apply(const Shape &s, const DevState &d, hipStream_t st)
+hipError_t launch_apply(const Shape &s, const DevState &d, hipStream_t st, bool checked)
 {
     const int nchunk = s.Dp >> 2;
     dim3 grid((nchunk + TPB - 1) / TPB, s.BN < MAX_GRID_Y ? s.BN : MAX_GRID_Y);
     hipLaunchKernelGGL(k_apply, grid, dim3(TPB), 0, st, s, d.F, d.SE, d.SG, d.Aexp,
                        s.map_range ? d.lo : nullptr, s.map_range ? d.hi : nullptr, d.src, d.reinit,
-                       d.best_f, d.best_upd, d.best_x, d.ctrl);
+                       d.best_f, d.best_upd, d.best_x, checked ? d.Wstar : nullptr, d.ctrl);
     return hipGetLastError();
 }
 

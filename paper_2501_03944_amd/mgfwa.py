@@ -60,7 +60,8 @@ class mgfwa_state_info(C.Structure):
 class mgfwa_timing_info(C.Structure):
     _fields_ = [("ms", C.c_double * N_PHASES), ("gen_ms_p50", C.c_double),
                 ("gen_ms_p99", C.c_double), ("gen_ms_mean", C.c_double),
-                ("fit_kernel_ms", C.c_double), ("generations", C.c_int)]
+                ("fit_kernel_ms", C.c_double), ("check_fit_ms", C.c_double),
+                ("generations", C.c_int)]
 
 
 class mgfwa_job_info(C.Structure):
@@ -261,7 +262,8 @@ def mgfwa_timing(ctx) -> dict:
     _check(lib().mgfwa_timing(ctx, C.byref(info)))
     return {"phase_ms": dict(zip(PHASES, list(info.ms))), "gen_ms_p50": info.gen_ms_p50,
             "gen_ms_p99": info.gen_ms_p99, "gen_ms_mean": info.gen_ms_mean,
-            "fit_kernel_ms": info.fit_kernel_ms, "generations": info.generations}
+            "fit_kernel_ms": info.fit_kernel_ms, "check_fit_ms": info.check_fit_ms,
+            "generations": info.generations}
 
 
 def mgfwa_destroy(ctx) -> None:
