@@ -61,7 +61,7 @@ def parse():
                     help="1: also run 64 mixed-shape BF16 jobs as one batched graph per generation")
     ap.add_argument("--serving-study", type=int, default=1,
                     help="1: also run a Poisson stream of mixed jobs through the serving loop")
-    ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of that study")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival window of that study")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: autotune the fitness launches before timing (mgfwa_autotune)")
     ap.add_argument("--testbed-study", type=int, default=1,
@@ -153,6 +153,14 @@ def run_gpu(wl, precision, steps, warmup, seed, autotune=True):
     g.close()
     return dict(C=C, ms=ms, wall=wall, timing=tinfo, graph_ms=graph_ms, best=best, gen=gen,
                 se_written=se_written)
+
+
+_T0 = time.perf_counter()
+
+
+def log(msg):
+    """Progress of the run on stderr (the JSON line alone goes to stdout)."""
+    print(f"bench [{time.perf_counter() - _T0:6.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def cpu_model():
@@ -337,7 +345,8 @@ def batch_study(steps, seed, n_jobs=64):
     C = sum(g.BN * (wl.n_sparks + wl.n_guiding) for g, wl in zip(jobs, wls))
     flops = sum(wl.flops_per_eval() * g.BN * (wl.n_sparks + wl.n_guiding)
                 for g, wl in zip(jobs, wls))
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()   # the library never takes the null stream
+    stream.wait_stream(torch.cuda.current_stream())
     b = M.Batch(jobs, stream=stream)
     b.step(1)
     for g in jobs:
@@ -372,16 +381,39 @@ def batch_study(steps, seed, n_jobs=64):
                 speedup_vs_sequential=sequential_ms / batched_ms)
 
 
-# serving mix: (workload, share of arrivals, precision, generation budget, target loss)
-SERVE_MIX = (("mlp8-16-1", 0.70, "fp32", 100, 40.0),
-             ("mlp64-128-128-10", 0.25, "fp32", 30, None),
-             ("mlp784-256-10", 0.05, "bf16", 10, None))
+# serving mix: (workload, share of arrivals, precision, generation budget, target loss).
+# Every job runs to its target loss or 300 generations.  The targets are losses the
+# shape's MGFWA runs reach at about 60 % of that budget (8-16-1: twice the noise
+# variance of its targets; the two cross-entropy shapes: 1.0, from ln 10 = 2.3 at
+# chance level and thousands at the random start).
+SERVE_MIX = (("mlp8-16-1", 0.70, "fp32", 300, 0.02),
+             ("mlp64-128-128-10", 0.25, "fp32", 300, 1.0),
+             ("mlp784-256-10", 0.05, "bf16", 300, 1.0))
+
+
+def alone_gen_ms(wl, precision, seed, gens=8):
+    """Device time of one generation of one job of this shape running alone."""
+    import torch
+
+    from paper_2501_03944_amd import mgfwa as M
+
+    g = M.MGFWA.from_workload(wl, precision=precision, seed=seed, max_generations=300)
+    g.step(2)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(g.stream)
+    g.step(gens)
+    b.record(g.stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / gens
+    g.close()
+    return ms
 
 
 def serving_study(seconds, seed, rate=20.0, arena_gib=64, n_streams=4):
     """Poisson arrivals (rate jobs/s over `seconds`) of the SERVE_MIX shapes into the
     continuous-batching server; per-generation device latency p50/p99, throughput,
-    and the offered load implied by the single-job generation times."""
+    admission wait, and the offered load against one GPU's capacity from the
+    single-job generation times."""
     import numpy as np
     import torch
 
@@ -397,9 +429,10 @@ def serving_study(seconds, seed, rate=20.0, arena_gib=64, n_streams=4):
         arrivals.append(t)
     shares = np.array([m[1] for m in SERVE_MIX])
     kinds = rng.choice(len(SERVE_MIX), size=len(arrivals), p=shares / shares.sum())
-    wls = []
-    for name, _, _, _, _ in SERVE_MIX:
+    wls, gen_ms = [], []
+    for name, _, prec, _, _ in SERVE_MIX:
         wl = inputs.workload(name)
+        gen_ms.append(alone_gen_ms(wl, prec, seed))
         # device copies once; every job of the kind shares them
         wl.x = torch.from_numpy(wl.x).cuda()
         wl.y = None if wl.y is None else torch.from_numpy(wl.y).cuda()
@@ -429,12 +462,24 @@ def serving_study(seconds, seed, rate=20.0, arena_gib=64, n_streams=4):
     waits = [x["admit_ms"] - x["submit_ms"] for x in infos]
     turn = [x["finish_ms"] - x["submit_ms"] for x in infos]
     counts = {SERVE_MIX[k][0]: int((kinds == k).sum()) for k in range(len(SERVE_MIX))}
-    # offered matrix work: every arrived job run to its full generation budget
+    gens_run = {m[0]: [x["generations"] for x, k in zip(infos, kinds) if k == j]
+                for j, m in enumerate(SERVE_MIX)}
+    stopped = {m[0]: sum(1 for x, k in zip(infos, kinds) if k == j and x["generations"] < m[3])
+               for j, m in enumerate(SERVE_MIX)}
+    # offered load in GPU-seconds per second: every arrived job at its full budget
+    # (and at the generations it actually ran), each generation at its alone time
+    offered_full = sum(counts[m[0]] * m[3] * ms for m, ms in zip(SERVE_MIX, gen_ms)) / 1e3 / seconds
+    offered_run = sum(sum(gens_run[m[0]]) * ms for m, ms in zip(SERVE_MIX, gen_ms)) / 1e3 / seconds
     offered = sum(counts[m[0]] * m[3] * wl.n_fireworks * (wl.n_sparks + wl.n_guiding)
                   * wl.flops_per_eval() for m, wl in zip(SERVE_MIX, wls)) / seconds
     return dict(arrival_rate_jobs_per_s=rate, arrival_window_s=seconds, jobs=len(ids),
-                mix={m[0]: dict(share=m[1], precision=m[2], generations=m[3],
-                                target_loss=m[4], arrived=counts[m[0]]) for m in SERVE_MIX},
+                mix={m[0]: dict(share=m[1], precision=m[2], generation_budget=m[3],
+                                target_loss=m[4], arrived=counts[m[0]],
+                                stopped_at_target=stopped[m[0]],
+                                mean_generations=float(np.mean(gens_run[m[0]]))
+                                if gens_run[m[0]] else 0.0,
+                                alone_ms_per_generation=ms)
+                     for m, ms in zip(SERVE_MIX, gen_ms)},
                 done=st["done"], failed=st["failed"], generations=st["generations"],
                 gen_latency_ms={"p50": st["gen_ms_p50"], "p99": st["gen_ms_p99"]},
                 spark_evals_per_s=st["spark_evals_per_s"], wall_s=wall,
@@ -442,6 +487,9 @@ def serving_study(seconds, seed, rate=20.0, arena_gib=64, n_streams=4):
                                    "p99": float(np.percentile(waits, 99))},
                 turnaround_ms={"p50": float(np.percentile(turn, 50)),
                                "p99": float(np.percentile(turn, 99))},
+                offered_load_gpu_s_per_s={"at_full_budgets": offered_full,
+                                          "at_generations_run": offered_run},
+                served_gpu_s_per_s=offered_run * seconds / wall,
                 offered_tflops_at_full_budgets=offered / 1e12,
                 arena_gib=arena_gib, arena_peak_gib=st["arena_peak"] / 2**30, streams=n_streams)
 
@@ -556,6 +604,7 @@ def main():
     testbed = getattr(wl, "net", None) is not None
     calibration_copy(args.calib_copy_mib)
     r = run_gpu(wl, precision, args.steps, args.warmup, args.seed, bool(args.autotune))
+    log(f"{args.workload} {precision}: {r['ms'] / args.steps:.3f} ms per generation")
     K = args.steps
     t = r["timing"]
     wide = args.workload == "mlp784-256-10"
@@ -595,9 +644,11 @@ def main():
         bf16["state_path_hbm"] = phase_hbm(wl, "bf16", rb["timing"], K, rb["se_written"], wide)
         bf16["speedup_vs_fp32"] = bf16["value"] / line["value"]
         line["bf16"] = bf16
+        log(f"{args.workload} bf16: {bf16['ms_per_step']:.3f} ms per generation")
     sample = None
     if not testbed and (bf16 is not None or args.cpu_baseline):
         sample = sample_generation(wl, args.seed)
+        log("sampled generation taken")
         if bf16 is not None:   # every explosion spark of the sampled generation: BF16 vs FP32
             m = sample["m"]
             y16 = sample["y16"].reshape(-1, m)
@@ -606,17 +657,23 @@ def main():
     if args.gmm_study and args.workload != "mlp64-128-128-10":
         line["gmm_study"], _, _ = workload_record("mlp64-128-128-10", "fp32", K, args.warmup,
                                                   args.seed, bool(args.autotune))
+        log("64-128-128-10 study done")
     if args.latency_study:
         line["latency_study"] = latency_study(args.seed)
+        log("latency study done")
     if args.serving_study:
         line["serving_study"] = serving_study(args.serve_seconds, args.seed)
+        log("serving study done")
     if args.batch_study:
         line["batch_study"] = batch_study(max(2, min(K, 10)), args.seed)
+        log("batch study done")
     if args.testbed_study:
         line["testbed_study"] = testbed_study(max(2, min(K, 20)), args.seed)
+        log("testbed study done")
     if args.cpu_baseline and sample is not None:
         rec, y64 = cpu_baseline(wl, sample)
         line["cpu_baseline"] = rec
+        log("cpu baseline done")
         y64 = y64.reshape(-1, sample["m"])
         line["fp32_vs_oracle"] = dict(generation=sample["t"], **vs_reference(
             sampled_groups(sample["y32"], sample, wl.n_sparks), y64, sample["m"]))

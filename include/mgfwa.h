@@ -151,6 +151,16 @@ typedef struct {
  *             width <= 256 and <= 16 outputs); input problems 1 = whole-network
  *             tiles, 2 = layer by layer, 3 = layer by layer with LDS-staged
  *             tiles.  EUNSUPPORTED when the family does not cover the shape.
+ *   regen_sparks  1: the explosion sparks are not stored; the fitness kernel
+ *             regenerates each spark from the counter-based generator as it
+ *             stages the spark's weights in LDS, and the guiding, selection and
+ *             best-so-far steps regenerate the sparks they read (the sparks are
+ *             counter-based, so every step sees the same values).  Takes effect
+ *             when the explosion-fitness plan stages its weights in LDS and the
+ *             order is not lag_guiding; otherwise the sparks are stored as usual.
+ *             The wide fitness kernel never stores the FP32 rows (its explosion
+ *             writes the packed rows it reads).  mgfwa_state_info.se_written
+ *             tells which applies.
  */
 typedef struct {
     int n_populations;      /* B >= 1 */
@@ -174,6 +184,7 @@ typedef struct {
     int lag_guiding;
     int map_range;
     int fit_path;
+    int regen_sparks;
 } mgfwa_config;
 
 /* Layout of the device state inside the workspace, for inspection: byte

@@ -56,6 +56,7 @@ struct Layout {
     size_t best_x, best_y, best_f, best_gen, best_upd, ctrl, partial, Xp, Xb, Ypad, Lpad;
     size_t Wpack, Xw, lo, hi, Pnet, H0, H1, Zero;
     size_t Wstar, Ystar, Xp32, Wpack32, Xw32;   // FP32 re-check of BF16 selection winners
+    size_t desc;                                // the job's descriptor for grouped launches
     size_t total;
     int partial_rows;
 };
@@ -300,6 +301,7 @@ mgfwa_status derive(const mgfwa_config *c, const mgfwa_problem *p, Derived *out)
     L.Xp32 = take(s.recheck && !net.wide ? (size_t)net32.S_pad * net32.in_pad * 4 : 0);
     L.Wpack32 = take(s.recheck && net.wide ? BN * wide_row_bytes(net32) : 0);
     L.Xw32 = take(s.recheck && net.wide ? (size_t)net32.S_pad * wide_kp(net32) * 4 : 0);
+    L.desc = take(sizeof(JobDesc));
     L.total = off;
     if (s.lag && L.SG != L.SE + BN * s.lam * Dp * 4)
         return fail(MGFWA_EINVAL, "internal: guiding sparks must follow the explosion sparks");
@@ -314,6 +316,7 @@ struct mgfwa_ctx {
     Net net;
     Net net32;          // BF16 runs: the FP32 network of the selection re-check
     DevState d32;       // ... and its FP32 sample buffers (shares the rest of d)
+    JobDesc *desc_dev = nullptr;   // descriptor for grouped (batched) launches, in the workspace
     FitPlan plan_check; // ... and its launch over the B*N gathered rows
     InNet in;
     bool input = false;
@@ -378,9 +381,38 @@ OutMap expl_map(const Shape &s)
     return m;
 }
 
+// Whether mgfwa_step leaves the explosion sparks unstored: the wide kernel reads
+// the explosion's packed rows; with regen_sparks an LDS-staged register-chain
+// plan regenerates them.  The lag order reads the previous generation's sparks.
+bool sparks_regenerated(const mgfwa_ctx *c)
+{
+    if (c->s.lag || c->input || !c->has_data) return false;
+    if (c->net.wide) return true;
+    return c->cfg.regen_sparks && c->plan_expl.wl;
+}
+
+// The explosion-fitness launch's source when its sparks are regenerated.
+SparkRegen spark_regen(const mgfwa_ctx *c)
+{
+    const Shape &s = c->s;
+    SparkRegen g;
+    g.F = c->d.F;
+    g.A = c->d.A;
+    g.lo = s.map_range ? c->d.lo : nullptr;
+    g.hi = s.map_range ? c->d.hi : nullptr;
+    g.ctrl = c->d.ctrl;
+    g.key = s.key;
+    g.box = s.box;
+    g.lam = s.lam;
+    g.N = s.N;
+    g.D = s.D;
+    g.Dp = s.Dp;
+    return g;
+}
+
 mgfwa_status fit_rows(mgfwa_ctx *c, const FitPlan &plan, const float *W, size_t ld, int rows,
                       OutMap map, float *out, hipStream_t st, hipEvent_t mid = nullptr,
-                      hipEvent_t pre = nullptr, int prepacked = 0)
+                      hipEvent_t pre = nullptr, int prepacked = 0, const SparkRegen *rg = nullptr)
 {
     if (c->input) {
         STEP(launch_net_input(c->in, plan.net_shape, c->d.Pnet, W, ld, rows, map, out, c->d.H0,
@@ -391,7 +423,7 @@ mgfwa_status fit_rows(mgfwa_ctx *c, const FitPlan &plan, const float *W, size_t 
         STEP(launch_fitness_wide(c->net, c->d, W, ld, rows, map, out, st, mid, pre, prepacked),
              "fitness_wide");
     else
-        STEP(launch_fitness(c->net, plan, c->d, W, ld, rows, map, out, st, mid), "fitness");
+        STEP(launch_fitness(c->net, plan, c->d, W, ld, rows, map, out, st, mid, rg), "fitness");
     return MGFWA_OK;
 }
 
@@ -438,13 +470,19 @@ mgfwa_status enqueue_generation(mgfwa_ctx *c, hipStream_t st, hipEvent_t *ev)
         STEP(launch_rank(s, c->d, st), "rank");
         STEP(launch_guide(s, c->d, st), "guide");
     }
-    // wide fitness kernel: the explosion also writes the sparks' packed rows
+    // wide fitness kernel: the explosion writes the sparks' packed rows (only
+    // those when they are regenerated later); regenerating register-chain plans
+    // need no explosion launch at all
     const WidePack wp = c->net.wide ? wide_pack_geometry(c->net, c->d) : WidePack{};
-    STEP(launch_explode(s, c->d, st, c->net.wide ? &wp : nullptr, !s.regen), "explode");
+    const bool regen_fit = s.regen && !c->net.wide;
+    if (!regen_fit)
+        STEP(launch_explode(s, c->d, st, c->net.wide ? &wp : nullptr, !s.regen), "explode");
     if (ev) STEP(hipEventRecord(ev[1], st), "event");
+    const SparkRegen rg = spark_regen(c);
     mgfwa_status r = fit_rows(c, c->plan_expl, c->d.SE, s.Dp, s.BN * expl_rows(s), expl_map(s),
                               c->d.Yc, st, ev ? ev[6] : nullptr,
-                              ev && c->net.wide ? ev[7] : nullptr, c->net.wide ? s.BN * s.lam : 0);
+                              ev && c->net.wide ? ev[7] : nullptr, c->net.wide ? s.BN * s.lam : 0,
+                              regen_fit ? &rg : nullptr);
     if (r) return r;
     if (ev) STEP(hipEventRecord(ev[2], st), "event");
     if (!s.lag) {
@@ -598,6 +636,7 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
     c->plan_eval = pv;
     c->net32 = dv.net32;
     c->plan_check = pc;
+    c->s.regen = sparks_regenerated(c) ? 1 : 0;
     const char *ev = std::getenv("MGFWA_NO_GRAPH");
     c->use_graph = !(ev && ev[0] == '1');
     ev = std::getenv("MGFWA_SYNC_DEBUG");
@@ -640,6 +679,7 @@ mgfwa_status mgfwa_init(mgfwa_ctx **out, const mgfwa_config *config, const mgfwa
     d.H0 = c->input && has_data ? at<float>(b, L.H0) : nullptr;
     d.H1 = c->input && has_data ? at<float>(b, L.H1) : nullptr;
     d.zero = c->input && has_data ? at<float>(b, L.Zero) : nullptr;
+    c->desc_dev = at<JobDesc>(b, L.desc);
     d.Wstar = c->s.recheck ? at<float>(b, L.Wstar) : nullptr;
     d.Ystar = c->s.recheck ? at<float>(b, L.Ystar) : nullptr;
     // the re-check's FP32 view: its own packed samples and spark rows
@@ -1101,11 +1141,200 @@ struct mgfwa_batch {
     hipEvent_t done = nullptr;               // end of the last batch step
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    std::vector<int> grouped, solo;          // jobs run by grouped launches / as branches
+    std::vector<JobDesc> desc;               // host copies of the grouped jobs' descriptors
 };
+
+void mgfwa::group_table(const JobDesc *const *jobs, const dim3 *grid, int n, GroupTable *t)
+{
+    int acc = 0;
+    t->njobs = n;
+    for (int i = 0; i < n; ++i) {
+        t->start[i] = acc;
+        t->gx[i] = (int)grid[i].x;
+        t->gy[i] = (int)grid[i].y;
+        t->job[i] = jobs[i];
+        acc += (int)(grid[i].x * grid[i].y);
+    }
+    t->start[n] = acc;
+}
 
 namespace {
 
 constexpr int MAX_BRANCHES = 16;
+
+// Jobs whose whole generation runs as grouped launches: weights problems on the
+// register-chain kernels in the default order.  (The wide kernel is persistent
+// over the device already; input problems and the lag order keep their own
+// sequences as graph branches.)
+bool groupable(const mgfwa_ctx *c)
+{
+    return !c->input && c->has_data && !c->net.wide && !c->s.lag && !c->cfg.external_fitness;
+}
+
+JobDesc job_desc(const mgfwa_ctx *c)
+{
+    JobDesc j;
+    std::memset(&j, 0, sizeof j);
+    const Shape &s = c->s;
+    j.s = s;
+    j.d = c->d;
+    const SparkRegen rg = spark_regen(c);
+    j.fit[0] = fit_launch_args(c->net, c->plan_expl, c->d, c->d.SE, s.Dp, s.BN * s.lam, expl_map(s),
+                               c->d.Yc, s.regen ? &rg : nullptr);
+    j.fit[1] = fit_launch_args(c->net, c->plan_guide, c->d, c->d.SG, s.Dp, s.BN * s.G,
+                               OutMap{s.G, s.C, s.lam}, c->d.Yc);
+    if (s.recheck)
+        j.fit[2] = fit_launch_args(c->net32, c->plan_check, c->d32, c->d.Wstar, s.Dp, s.BN, kFlat,
+                                   c->d.Ystar);
+    return j;
+}
+
+const FitPlan &job_plan(const mgfwa_ctx *c, int which)
+{
+    return which == 0 ? c->plan_expl : which == 1 ? c->plan_guide : c->plan_check;
+}
+
+// Sparks of fitness launch `which` of a grouped job (as in job_desc).
+int job_fit_rows(const mgfwa_ctx *c, int which)
+{
+    return which == 0 ? c->s.BN * c->s.lam : which == 1 ? c->s.BN * c->s.G : c->s.BN;
+}
+
+// One grouped launch per GROUP_MAX jobs among the grouped jobs that `take` selects,
+// each with its own grid from `grid`.
+template <class Take, class Grid, class Launch>
+mgfwa_status group_run(mgfwa_batch *b, Take take, Grid grid, Launch launch)
+{
+    std::vector<const JobDesc *> jd;
+    std::vector<dim3> gr;
+    for (int i : b->grouped) {
+        const mgfwa_ctx *c = b->jobs[i];
+        if (!take(c)) continue;
+        const dim3 g = grid(c);
+        if (g.x * g.y == 0) continue;
+        jd.push_back(c->desc_dev);
+        gr.push_back(g);
+    }
+    for (size_t o = 0; o < jd.size(); o += GROUP_MAX) {
+        const int m = (int)std::min<size_t>(GROUP_MAX, jd.size() - o);
+        GroupTable t;
+        group_table(jd.data() + o, gr.data() + o, m, &t);
+        const hipError_t e = launch(t);
+        if (e != hipSuccess) return fail(MGFWA_EHIP, "grouped launch: %s", hipGetErrorString(e));
+    }
+    return MGFWA_OK;
+}
+
+// Fitness launch `which` of the grouped jobs: one grouped launch per kernel
+// instance, then one grouped finalisation.
+mgfwa_status group_fitness(mgfwa_batch *b, int which, bool (*take)(const mgfwa_ctx *),
+                           hipStream_t st)
+{
+    std::vector<const void *> kernels;
+    for (int i : b->grouped) {
+        const mgfwa_ctx *c = b->jobs[i];
+        if (!take(c)) continue;
+        const void *k = job_plan(c, which).gkernel;
+        if (std::find(kernels.begin(), kernels.end(), k) == kernels.end()) kernels.push_back(k);
+    }
+    for (const void *k : kernels) {
+        int lds = 0, nw = 0;
+        for (int i : b->grouped) {
+            const mgfwa_ctx *c = b->jobs[i];
+            if (!take(c) || job_plan(c, which).gkernel != k) continue;
+            lds = std::max(lds, job_plan(c, which).lds_bytes);
+            nw = job_plan(c, which).nw;
+        }
+        mgfwa_status r = group_run(
+            b, [&](const mgfwa_ctx *c) { return take(c) && job_plan(c, which).gkernel == k; },
+            [&](const mgfwa_ctx *c) {
+                return dim3((unsigned)(job_fit_rows(c, which) * job_plan(c, which).bpr));
+            },
+            [&](const GroupTable &t) { return launch_fitness_group(t, k, nw, lds, which, st); });
+        if (r) return r;
+    }
+    return group_run(
+        b, take, [&](const mgfwa_ctx *c) { return dim3((unsigned)((job_fit_rows(c, which) + 255) / 256)); },
+        [&](const GroupTable &t) { return launch_finalize_group(t, which, st); });
+}
+
+bool take_all(const mgfwa_ctx *) { return true; }
+bool take_recheck(const mgfwa_ctx *c) { return c->s.recheck != 0; }
+
+// One generation of every grouped job as grouped launches, in the order of
+// enqueue_generation (default order, register-chain kernels).
+mgfwa_status enqueue_grouped(mgfwa_batch *b, hipStream_t st)
+{
+    mgfwa_status r = group_run(
+        b, [](const mgfwa_ctx *c) { return c->s.map_range != 0; },
+        [](const mgfwa_ctx *c) { return pop_range_grid(c->s); },
+        [&](const GroupTable &t) { return launch_pop_range_group(t, st); });
+    if (!r)
+        r = group_run(
+            b, [](const mgfwa_ctx *c) { return c->s.regen == 0; },
+            [](const mgfwa_ctx *c) { return explode_grid(c->s); },
+            [&](const GroupTable &t) { return launch_explode_group(t, st); });
+    if (!r) r = group_fitness(b, 0, take_all, st);
+    int max_lam = 0;
+    for (int i : b->grouped) max_lam = std::max(max_lam, b->jobs[i]->s.lam);
+    if (!r)
+        r = group_run(
+            b, [](const mgfwa_ctx *c) { return c->s.m > 64; },
+            [](const mgfwa_ctx *c) { return rank_grid(c->s); },
+            [&](const GroupTable &t) { return launch_rank_group(t, max_lam, st); });
+    if (!r)
+        r = group_run(
+            b, take_all, [](const mgfwa_ctx *c) { return guide_grid(c->s); },
+            [&](const GroupTable &t) { return launch_guide_group(t, st); });
+    if (!r) r = group_fitness(b, 1, take_all, st);
+    if (!r)
+        r = group_run(
+            b, take_recheck, [](const mgfwa_ctx *c) { return firework_row_grid(c->s); },
+            [&](const GroupTable &t) { return launch_gather_best_group(t, st); });
+    if (!r) r = group_fitness(b, 2, take_recheck, st);
+    if (!r)
+        r = group_run(
+            b, take_all, [](const mgfwa_ctx *c) { return select_grid(c->s); },
+            [&](const GroupTable &t) { return launch_select_group(t, st); });
+    if (!r)
+        r = group_run(
+            b, take_all, [](const mgfwa_ctx *c) { return firework_row_grid(c->s); },
+            [&](const GroupTable &t) { return launch_apply_group(t, st); });
+    if (!r)
+        r = group_run(
+            b, take_all, [](const mgfwa_ctx *) { return dim3(1); },
+            [&](const GroupTable &t) { return launch_finish_group(t, st); });
+    return r;
+}
+
+// Descriptors of the grouped jobs written to their workspaces (on each job's
+// stream, which the batch orders itself after), and the LDS limits of the
+// grouped fitness kernels raised to what their jobs need.
+mgfwa_status group_setup(mgfwa_batch *b)
+{
+    for (int i = 0; i < (int)b->jobs.size(); ++i)
+        (groupable(b->jobs[i]) ? b->grouped : b->solo).push_back(i);
+    b->desc.resize(b->grouped.size());
+    for (size_t k = 0; k < b->grouped.size(); ++k) {
+        mgfwa_ctx *c = b->jobs[b->grouped[k]];
+        b->desc[k] = job_desc(c);
+        HIP_TRY(hipMemcpyAsync(c->desc_dev, &b->desc[k], sizeof(JobDesc), hipMemcpyHostToDevice,
+                               c->stream));
+    }
+    std::map<const void *, int> lds;   // grouped kernel -> the most LDS any of its launches takes
+    for (int i : b->grouped) {
+        const mgfwa_ctx *c = b->jobs[i];
+        for (int which = 0; which < (c->s.recheck ? 3 : 2); ++which) {
+            const FitPlan &p = job_plan(c, which);
+            int &v = lds[p.gkernel];
+            v = std::max(v, p.lds_bytes);
+        }
+    }
+    for (const auto &kv : lds) HIP_TRY(fit_group_prepare(kv.first, kv.second));
+    return MGFWA_OK;
+}
+
 
 hipEvent_t batch_event(mgfwa_batch *b)
 {
@@ -1117,7 +1346,9 @@ hipEvent_t batch_event(mgfwa_batch *b)
 
 mgfwa_status batch_capture(mgfwa_batch *b)
 {
-    const int n = (int)b->jobs.size();
+    mgfwa_status r0 = group_setup(b);
+    if (r0) return r0;
+    const int n = (int)b->solo.size();
     const int nb = std::min(n, MAX_BRANCHES);
     HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
     for (int i = 0; i < nb; ++i) {
@@ -1135,9 +1366,12 @@ mgfwa_status batch_capture(mgfwa_batch *b)
     hipError_t e = hipEventRecord(fork, b->cap);
     for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamWaitEvent(b->branch[i], fork, 0);
     if (e != hipSuccess) r = fail(MGFWA_EHIP, "batch capture: %s", hipGetErrorString(e));
-    // jobs go round-robin over the branches; a branch runs its jobs in order
+    // jobs that cannot be grouped go round-robin over the branches (a branch
+    // runs its jobs in order); the grouped jobs' generation is one sequence of
+    // grouped launches on the capture stream, beside them
     for (int i = 0; i < n && r == MGFWA_OK; ++i)
-        r = enqueue_generation(b->jobs[i], b->branch[i % nb], nullptr);
+        r = enqueue_generation(b->jobs[b->solo[i]], b->branch[i % nb], nullptr);
+    if (r == MGFWA_OK && !b->grouped.empty()) r = enqueue_grouped(b, b->cap);
     for (int i = 0; i < nb && r == MGFWA_OK; ++i) {
         e = hipEventRecord(join[i], b->branch[i]);
         if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, join[i], 0);
@@ -1171,6 +1405,7 @@ mgfwa_status mgfwa_autotune(mgfwa_ctx *c, int reps)
     const Shape &s = c->s;
     mgfwa_status r = tune_plan(c, s.BN * expl_rows(s), c->d.SE, expl_map(s), reps, &c->plan_expl);
     if (r) return r;
+    c->s.regen = sparks_regenerated(c) ? 1 : 0;   // the plan decides whether it can regenerate
     return tune_plan(c, s.BN * s.G, c->d.SG, OutMap{s.G, s.C, s.lam}, reps, &c->plan_guide);
 }
 
@@ -1214,6 +1449,7 @@ mgfwa_status mgfwa_set_fit_plan(mgfwa_ctx *c, int which, int index)
     if (c->net.wide) return MGFWA_OK;   // one fixed tile shape
     HIP_TRY(fit_prepare(cand[index]));
     (which == 0 ? c->plan_expl : c->plan_guide) = cand[index];
+    c->s.regen = sparks_regenerated(c) ? 1 : 0;
     return MGFWA_OK;
 }
 

@@ -51,25 +51,8 @@ namespace fit {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-struct FitArgs {
-    const float *W;        // spark rows
-    size_t ld;             // row pitch (floats)
-    int rows;
-    const float *X;        // [S_pad][in_pad] (FP32 kernels)
-    const uint16_t *Xb;    // [S_pad][in_pad] bf16 bits (BF16 kernels)
-    int in_pad, S, S_pad;
-    int nl;
-    int fi[MAXL], fo[MAXL], woff[MAXL], boff[MAXL], act[MAXL], vec[MAXL];
-    // LDS layout (WL kernels), per layer: weight offset and row pitch in
-    // elements of the storage type, padded rows and columns, bias offset (floats)
-    int lw[MAXL], lpitch[MAXL], lrows[MAXL], lcols[MAXL], lb[MAXL];
-    int lbias_byte;        // start of the FP32 bias area
-    int loss;
-    const float *Y;        // [S_pad][out]
-    const int32_t *lab;    // [S_pad]
-    int bpr, spb;
-    float *partial;        // [rows][bpr]
-};
+// FitArgs (the kernel's arguments) is declared in internal.h.
+
 
 __device__ __forceinline__ floatx4 zero4()
 {
@@ -213,12 +196,35 @@ struct WView {
     }
 };
 
+// Coordinates 4c..4c+3 of explosion spark r (the regenerating staging).
+__device__ __forceinline__ floatx4 regen_chunk(const SparkRegen &g, int r, int c)
+{
+    const int gf = r / g.lam;
+    const uint32_t t = (uint32_t)g.ctrl[CTRL_GEN] + 1u;
+    const float4 x4 = reinterpret_cast<const float4 *>(g.F + (size_t)gf * g.Dp)[c];
+    const float x[4] = {x4.x, x4.y, x4.z, x4.w};
+    const size_t pb = (size_t)(gf / g.N) * g.Dp;
+    float v[4];
+    explosion_chunk(x, g.A[gf], g.key, c, (uint32_t)r, t, g.box, g.lo ? g.lo + pb : nullptr,
+                    g.hi ? g.hi + pb : nullptr, g.D, v);
+    floatx4 out = {v[0], v[1], v[2], v[3]};
+    return out;
+}
+
+// Spark coordinate j of row r: read from w, or regenerated.
+__device__ __forceinline__ float spark_at(const FitArgs &a, const float *w, int r, int j)
+{
+    if (!a.rg.F) return w[j];
+    return regen_chunk(a.rg, r, j >> 2)[j & 3];
+}
+
 // Copy the spark's weights into LDS (zero-padded layout) and its biases into
-// the FP32 bias area.
+// the FP32 bias area; with a.rg.F the spark (row r) is regenerated instead of read.
 template <bool BF>
-__device__ __forceinline__ void stage_weights(const FitArgs &a, const float *w, char *smem)
+__device__ __forceinline__ void stage_weights(const FitArgs &a, const float *w, int r, char *smem)
 {
     float *bias = reinterpret_cast<float *>(smem + a.lbias_byte);
+    const bool regen = a.rg.F != nullptr;
     for (int l = 0; l < a.nl; ++l) {
         const int fo = a.fo[l], fi = a.fi[l], rows = a.lrows[l], cols = a.lcols[l];
         const int pitch = a.lpitch[l], base = a.lw[l];
@@ -236,9 +242,10 @@ __device__ __forceinline__ void stage_weights(const FitArgs &a, const float *w, 
                     const int idx = i0 + u * nt;
                     const int o = (4 * idx) / cols, k = 4 * idx - o * cols;
                     dst[u] = idx < n4 ? base + o * pitch + (BF ? k : k ^ ((o & 1) << 2)) : -1;
-                    v[u] = (idx < n4 && o < fo && k < fi)
-                               ? *reinterpret_cast<const floatx4 *>(src + (size_t)o * fi + k)
-                               : zero4();
+                    const bool live = idx < n4 && o < fo && k < fi;
+                    v[u] = !live ? zero4()
+                           : regen ? regen_chunk(a.rg, r, (a.woff[l] + o * fi + k) >> 2)
+                                   : *reinterpret_cast<const floatx4 *>(src + (size_t)o * fi + k);
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
@@ -256,13 +263,13 @@ __device__ __forceinline__ void stage_weights(const FitArgs &a, const float *w, 
                 }
             }
             for (int o = threadIdx.x; o < rows; o += blockDim.x)
-                bias[a.lb[l] + o] = o < fo ? w[a.boff[l] + o] : 0.0f;
+                bias[a.lb[l] + o] = o < fo ? spark_at(a, w, r, a.boff[l] + o) : 0.0f;
             continue;
         }
         const int n = rows * cols;
         for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
             const int o = idx / cols, k = idx - o * cols;
-            const float v = (o < fo && k < fi) ? src[(size_t)o * fi + k] : 0.0f;
+            const float v = (o < fo && k < fi) ? spark_at(a, w, r, a.woff[l] + o * fi + k) : 0.0f;
             if constexpr (BF)
                 reinterpret_cast<uint16_t *>(smem)[base + o * pitch + k] =
                     __builtin_bit_cast(uint16_t, (__bf16)v);
@@ -270,7 +277,7 @@ __device__ __forceinline__ void stage_weights(const FitArgs &a, const float *w, 
                 reinterpret_cast<float *>(smem)[base + o * pitch + (k ^ ((o & 1) << 2))] = v;
         }
         for (int o = threadIdx.x; o < rows; o += blockDim.x)
-            bias[a.lb[l] + o] = o < fo ? w[a.boff[l] + o] : 0.0f;
+            bias[a.lb[l] + o] = o < fo ? spark_at(a, w, r, a.boff[l] + o) : 0.0f;
     }
     __syncthreads();
 }
@@ -628,17 +635,17 @@ __device__ __forceinline__ float slab_loss(const FitArgs &a, int l, int s0, int 
     return total;
 }
 
-template <bool BF, bool WL, int NW, int P, int ACT, int R1, int R2, int R3, int R4, int SCHED = 1>
-__global__ __launch_bounds__(NW * 64) void k_fit(FitArgs a)
+// Block `bid` of a fitness launch: spark r = bid / bpr, sample range c = bid % bpr.
+template <bool BF, bool WL, int NW, int P, int ACT, int R1, int R2, int R3, int R4, int SCHED>
+__device__ __forceinline__ void fit_body(const FitArgs &a, int bid)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ float red[NW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int n = lane & 15, g = lane >> 4;
-    const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int r = bid / a.bpr, c = bid % a.bpr;
     const float *w = a.W + (size_t)r * a.ld;
-    if constexpr (WL) stage_weights<BF>(a, w, smem);
+    if constexpr (WL) stage_weights<BF>(a, w, r, smem);
     const WView<BF, WL> w0(a, w, smem, 0, n, g), w1(a, w, smem, 1, n, g);
     const WView<BF, WL> w2(a, w, smem, 2, n, g), w3(a, w, smem, 3, n, g);
     const int s_begin = c * a.spb;
@@ -700,17 +707,36 @@ __global__ __launch_bounds__(NW * 64) void k_fit(FitArgs a)
     }
 }
 
+template <bool BF, bool WL, int NW, int P, int ACT, int R1, int R2, int R3, int R4, int SCHED = 1>
+__global__ __launch_bounds__(NW * 64) void k_fit(FitArgs a)
+{
+    fit_body<BF, WL, NW, P, ACT, R1, R2, R3, R4, SCHED>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// The same kernel over the fitness launch `which` of many jobs that share it:
+// grouped block ids are spread over the XCDs as in a single launch, then each
+// block runs the block it would have been in its job's own launch.
+template <bool BF, bool WL, int NW, int P, int ACT, int R1, int R2, int R3, int R4, int SCHED = 1>
+__global__ __launch_bounds__(NW * 64) void k_fit_group(GroupTable t, int which)
+{
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int j = group_job(t, bid);
+    fit_body<BF, WL, NW, P, ACT, R1, R2, R3, R4, SCHED>(t.job[j]->fit[which].a, bid - t.start[j]);
+}
+
 // One compiled fitness kernel: precision, weight source, wavefronts per block,
 // slabs in flight, hidden activation (-1: chosen at run time), 16-row blocks
 // per layer.
 struct KernelEntry {
     int bf16, wl, nw, P, act, R[MAXL];
-    const void *fn;
+    const void *fn;         // k_fit
+    const void *gfn;        // k_fit_group of the same instance
 };
 
 #define FIT_ENTRY_SCHED(BF, WL, NW, P, ACT, SCHED, R1, R2, R3, R4)                          \
     {BF, WL, NW, P, ACT, {R1, R2, R3, R4},                                                   \
-     reinterpret_cast<const void *>(&::mgfwa::fit::k_fit<BF, WL, NW, P, ACT, R1, R2, R3, R4, SCHED>)}
+     reinterpret_cast<const void *>(&::mgfwa::fit::k_fit<BF, WL, NW, P, ACT, R1, R2, R3, R4, SCHED>), \
+     reinterpret_cast<const void *>(&::mgfwa::fit::k_fit_group<BF, WL, NW, P, ACT, R1, R2, R3, R4, SCHED>)}
 #define FIT_ENTRY_ACT(BF, WL, NW, P, ACT, R1, R2, R3, R4) \
     FIT_ENTRY_SCHED(BF, WL, NW, P, ACT, 1, R1, R2, R3, R4)
 #define FIT_ENTRY(BF, WL, NW, P, R1, R2, R3, R4) FIT_ENTRY_ACT(BF, WL, NW, P, -1, R1, R2, R3, R4)

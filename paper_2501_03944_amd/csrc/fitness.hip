@@ -29,15 +29,30 @@ using namespace fit;
 constexpr int MAX_BPR = 64;
 
 // Sum of a row's partials in order, scaled to the mean, NaN -> +inf, scattered.
-__global__ __launch_bounds__(256) void k_fit_finalize(const float *__restrict__ partial, int rows,
-                                                      int bpr, float inv_norm, OutMap map,
-                                                      float *__restrict__ out)
+__device__ __forceinline__ void finalize_body(const float *__restrict__ partial, int rows, int bpr,
+                                              float inv_norm, const OutMap &map,
+                                              float *__restrict__ out, Blk b)
 {
-    const int r = blockIdx.x * 256 + threadIdx.x;
+    const int r = b.x * 256 + threadIdx.x;
     if (r >= rows) return;
     float t = 0.0f;
     for (int c = 0; c < bpr; ++c) t += partial[(size_t)r * bpr + c];
     out[map.index(r)] = canon_fitness(t * inv_norm);
+}
+
+__global__ __launch_bounds__(256) void k_fit_finalize(const float *__restrict__ partial, int rows,
+                                                      int bpr, float inv_norm, OutMap map,
+                                                      float *__restrict__ out)
+{
+    finalize_body(partial, rows, bpr, inv_norm, map, out, own_block());
+}
+
+__global__ __launch_bounds__(256) void k_fit_finalize_group(GroupTable t, int which)
+{
+    const int j = group_job(t, blockIdx.x);
+    const FitLaunch &f = t.job[j]->fit[which];
+    finalize_body(f.a.partial, f.a.rows, f.a.bpr, f.inv_norm, f.map, f.out,
+                  group_block(t, j, blockIdx.x));
 }
 
 // Pack the problem data: X zero-padded to [S_pad][in_pad] (FP32 or bf16 RNE),
@@ -163,6 +178,7 @@ static int default_bpr(const Net &net, const KernelEntry &e, int rows)
 static void make_plan(const Net &net, const KernelEntry &e, int rows, int bpr, FitPlan *plan)
 {
     plan->kernel = e.fn;
+    plan->gkernel = e.gfn;
     plan->nw = e.nw;
     plan->P = e.P;
     plan->wl = e.wl;
@@ -228,12 +244,12 @@ hipError_t fit_prepare(const FitPlan &plan)
                                plan.lds_bytes);
 }
 
-hipError_t launch_fitness(const Net &net, const FitPlan &plan, const DevState &d, const float *W,
-                          size_t ld, int rows, OutMap map, float *out, hipStream_t st,
-                          hipEvent_t mid)
+FitLaunch fit_launch_args(const Net &net, const FitPlan &plan, const DevState &d, const float *W,
+                          size_t ld, int rows, OutMap map, float *out, const SparkRegen *rg)
 {
-    if (rows <= 0) return hipSuccess;
-    FitArgs a;
+    FitLaunch f;
+    FitArgs &a = f.a;
+    a.rg = rg ? *rg : SparkRegen{};
     a.W = W;
     a.ld = ld;
     a.rows = rows;
@@ -263,6 +279,23 @@ hipError_t launch_fitness(const Net &net, const FitPlan &plan, const DevState &d
     a.bpr = plan.bpr;
     a.spb = plan.spb;
     a.partial = d.partial;
+    f.inv_norm = net.inv_norm;
+    f.map = map;
+    f.out = out;
+    return f;
+}
+
+dim3 fitness_grid(const FitLaunch &f) { return dim3((unsigned)(f.a.rows * f.a.bpr)); }
+dim3 finalize_grid(const FitLaunch &f) { return dim3((unsigned)((f.a.rows + 255) / 256)); }
+
+hipError_t launch_fitness(const Net &net, const FitPlan &plan, const DevState &d, const float *W,
+                          size_t ld, int rows, OutMap map, float *out, hipStream_t st,
+                          hipEvent_t mid, const SparkRegen *rg)
+{
+    if (rows <= 0) return hipSuccess;
+    if (rg && !plan.wl) return hipErrorInvalidValue;   // only the staging regenerates
+    FitLaunch f = fit_launch_args(net, plan, d, W, ld, rows, map, out, rg);
+    FitArgs &a = f.a;
     void *args[] = {&a};
     hipError_t e = hipLaunchKernel(plan.kernel, dim3((unsigned)(rows * plan.bpr)),
                                    dim3(64 * plan.nw), args, (size_t)plan.lds_bytes, st);
@@ -271,8 +304,30 @@ hipError_t launch_fitness(const Net &net, const FitPlan &plan, const DevState &d
         e = hipEventRecord(mid, st);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_fit_finalize, dim3((rows + 255) / 256), dim3(256), 0, st, d.partial, rows,
+    hipLaunchKernelGGL(k_fit_finalize, finalize_grid(f), dim3(256), 0, st, d.partial, rows,
                        plan.bpr, net.inv_norm, map, out);
+    return hipGetLastError();
+}
+
+hipError_t fit_group_prepare(const void *gkernel, int lds_bytes)
+{
+    if (lds_bytes <= 0) return hipSuccess;
+    return hipFuncSetAttribute(gkernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+}
+
+hipError_t launch_fitness_group(const GroupTable &t, const void *gkernel, int nw, int lds_bytes,
+                                int which, hipStream_t st)
+{
+    GroupTable tt = t;
+    void *args[] = {&tt, &which};
+    return hipLaunchKernel(gkernel, dim3((unsigned)t.start[t.njobs]), dim3(64 * nw), args,
+                           (size_t)lds_bytes, st);
+}
+
+hipError_t launch_finalize_group(const GroupTable &t, int which, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fit_finalize_group, dim3((unsigned)t.start[t.njobs]), dim3(256), 0, st, t,
+                       which);
     return hipGetLastError();
 }
 

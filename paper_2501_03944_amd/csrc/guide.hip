@@ -21,16 +21,16 @@ namespace {
 constexpr int TPB = 256;
 constexpr int MAX_GRID_Y = 65535;
 
-__global__ __launch_bounds__(TPB) void k_rank(const float *__restrict__ Yc, int C, int lam, int G,
-                                              int m, int k, int32_t *__restrict__ top,
-                                              int32_t *__restrict__ bottom,
-                                              int32_t *__restrict__ tie,
-                                              const int32_t *__restrict__ ctrl, int lag)
+__device__ __forceinline__ void rank_body(const float *__restrict__ Yc, int C, int lam, int G, int m,
+                                          int k, int32_t *__restrict__ top,
+                                          int32_t *__restrict__ bottom, int32_t *__restrict__ tie,
+                                          const int32_t *__restrict__ ctrl, int lag, uint32_t *sh,
+                                          Blk b)
 {
     if (ctrl[CTRL_DONE]) return;
     if (lag && ctrl[CTRL_GEN] == 0) {
         // lagged guiding before any explosion: every guiding vector is zero
-        const int gf = blockIdx.x;
+        const int gf = b.x;
         for (int i = threadIdx.x; i < G * k; i += blockDim.x) {
             const int g = i / k, j = i % k;
             top[((size_t)gf * G + g) * k + j] = g * m + j;
@@ -39,10 +39,9 @@ __global__ __launch_bounds__(TPB) void k_rank(const float *__restrict__ Yc, int 
         for (int g = threadIdx.x; g < G; g += blockDim.x) tie[(size_t)gf * G + g] = 1;
         return;
     }
-    extern __shared__ uint32_t sh[];
     uint32_t *key = sh;               // [lam]
     int32_t *rank = (int32_t *)(sh + lam);  // [lam]
-    const int gf = blockIdx.x;
+    const int gf = b.x;
     for (int j = threadIdx.x; j < lam; j += blockDim.x) key[j] = fit_key(Yc[(size_t)gf * C + j]);
     __syncthreads();
     for (int j = threadIdx.x; j < lam; j += blockDim.x) {
@@ -77,6 +76,26 @@ __global__ __launch_bounds__(TPB) void k_rank(const float *__restrict__ Yc, int 
             tie[(size_t)gf * G + g] = (key[j] == kmax);
         }
     }
+}
+
+__global__ __launch_bounds__(TPB) void k_rank(const float *__restrict__ Yc, int C, int lam, int G,
+                                              int m, int k, int32_t *__restrict__ top,
+                                              int32_t *__restrict__ bottom,
+                                              int32_t *__restrict__ tie,
+                                              const int32_t *__restrict__ ctrl, int lag)
+{
+    extern __shared__ uint32_t sh[];
+    rank_body(Yc, C, lam, G, m, k, top, bottom, tie, ctrl, lag, sh, own_block());
+}
+
+__global__ __launch_bounds__(TPB) void k_rank_group(GroupTable t)
+{
+    extern __shared__ uint32_t sh[];
+    const int j = group_job(t, blockIdx.x);
+    const JobDesc &J = *t.job[j];
+    const Shape &s = J.s;
+    rank_body(J.d.Yc, s.C, s.lam, s.G, s.m, s.k, J.d.top, J.d.bottom, J.d.tie, J.d.ctrl, s.lag, sh,
+              group_block(t, j, blockIdx.x));
 }
 
 // Groups of m <= 64 members: the calling wavefront ranks group gi (g = gi % G
@@ -146,32 +165,29 @@ __device__ __forceinline__ void rank_group_wave(const float *__restrict__ Yc, in
 // lists come from k_rank.  REGEN: the member sparks are regenerated from the
 // counter-based generator (firework row, amplitude A) instead of read from SE.
 template <bool RANK, bool REGEN>
-__global__ __launch_bounds__(TPB) void k_guide(const float *__restrict__ F,
-                                               const float *__restrict__ A,
-                                               const float *__restrict__ SE,
-                                               float *__restrict__ SG,
-                                               int32_t *__restrict__ top,
-                                               int32_t *__restrict__ bottom,
-                                               int32_t *__restrict__ tie, int G, int lam,
-                                               int k, float inv_k, float boost, int groups, int D,
-                                               int Dp, uint2 key, Box box,
-                                               const int32_t *__restrict__ ctrl, int N,
-                                               const float *__restrict__ lo,
-                                               const float *__restrict__ hi,
-                                               const float *__restrict__ Yc, int C, int m, int lag)
+__device__ __forceinline__ void guide_body(const float *__restrict__ F, const float *__restrict__ A,
+                                           const float *__restrict__ SE, float *__restrict__ SG,
+                                           int32_t *__restrict__ top, int32_t *__restrict__ bottom,
+                                           int32_t *__restrict__ tie, int G, int lam, int k,
+                                           float inv_k, float boost, int groups, int D, int Dp,
+                                           uint2 key, Box box, const int32_t *__restrict__ ctrl,
+                                           int N, const float *__restrict__ lo,
+                                           const float *__restrict__ hi,
+                                           const float *__restrict__ Yc, int C, int m, int lag,
+                                           Blk b)
 {
     __shared__ int32_t s_top[64], s_bottom[64], s_tie;
     if (ctrl[CTRL_DONE]) return;
     const uint32_t tn = (uint32_t)ctrl[CTRL_GEN] + 1u;
-    const int chunk = blockIdx.x * TPB + threadIdx.x;
+    const int chunk = b.x * TPB + threadIdx.x;
     const bool active = chunk < (Dp >> 2);
     const bool zero_guide = lag && ctrl[CTRL_GEN] == 0;
-    for (int gi = blockIdx.y; gi < groups; gi += gridDim.y) {
+    for (int gi = b.y; gi < groups; gi += b.gy) {
         const int32_t *tp, *bp;
         int tied;
         if constexpr (RANK) {
             if (threadIdx.x < 64) {
-                const bool store = blockIdx.x == 0;
+                const bool store = b.x == 0;
                 rank_group_wave(Yc, C, G, m, k, gi, zero_guide, s_top, s_bottom, &s_tie,
                                 store ? top : nullptr, store ? bottom : nullptr,
                                 store ? tie : nullptr);
@@ -243,28 +259,74 @@ __global__ __launch_bounds__(TPB) void k_guide(const float *__restrict__ F,
     }
 }
 
+template <bool RANK, bool REGEN>
+__device__ __forceinline__ void guide_job(const Shape &s, const DevState &d, Blk b)
+{
+    guide_body<RANK, REGEN>(d.F, d.A, d.SE, d.SG, d.top, d.bottom, d.tie, s.G, s.lam, s.k, s.inv_k,
+                            s.boost, s.BN * s.G, s.D, s.Dp, s.key, s.box, d.ctrl, s.N,
+                            s.map_range ? d.lo : nullptr, s.map_range ? d.hi : nullptr, d.Yc, s.C,
+                            s.m, s.lag, b);
+}
+
+template <bool RANK, bool REGEN>
+__global__ __launch_bounds__(TPB) void k_guide(Shape s, DevState d)
+{
+    guide_job<RANK, REGEN>(s, d, own_block());
+}
+
+// The guiding step of many jobs; each job takes its own variant (in-kernel
+// ranking for groups of <= 64 members, regenerated member sparks).
+__global__ __launch_bounds__(TPB) void k_guide_group(GroupTable t)
+{
+    const int j = group_job(t, blockIdx.x);
+    const JobDesc &J = *t.job[j];
+    const Blk b = group_block(t, j, blockIdx.x);
+    if (J.s.m <= 64) {
+        if (J.s.regen) guide_job<true, true>(J.s, J.d, b);
+        else guide_job<true, false>(J.s, J.d, b);
+    } else {
+        if (J.s.regen) guide_job<false, true>(J.s, J.d, b);
+        else guide_job<false, false>(J.s, J.d, b);
+    }
+}
+
 }  // namespace
+
+dim3 rank_grid(const Shape &s) { return dim3(s.BN); }
+
+dim3 guide_grid(const Shape &s)
+{
+    const int groups = s.BN * s.G;
+    const int nchunk = s.Dp >> 2;
+    return dim3((nchunk + TPB - 1) / TPB, groups < MAX_GRID_Y ? groups : MAX_GRID_Y);
+}
 
 hipError_t launch_rank(const Shape &s, const DevState &d, hipStream_t st)
 {
     if (s.m <= 64) return hipSuccess;   // ranked inside k_guide
     const size_t shmem = (size_t)s.lam * 8;
-    hipLaunchKernelGGL(k_rank, dim3(s.BN), dim3(TPB), shmem, st, d.Yc, s.C, s.lam, s.G, s.m, s.k,
+    hipLaunchKernelGGL(k_rank, rank_grid(s), dim3(TPB), shmem, st, d.Yc, s.C, s.lam, s.G, s.m, s.k,
                        d.top, d.bottom, d.tie, d.ctrl, s.lag);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank_group(const GroupTable &t, int max_lam, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rank_group, dim3(t.start[t.njobs]), dim3(TPB), (size_t)max_lam * 8, st, t);
     return hipGetLastError();
 }
 
 hipError_t launch_guide(const Shape &s, const DevState &d, hipStream_t st)
 {
-    const int groups = s.BN * s.G;
-    const int nchunk = s.Dp >> 2;
-    dim3 grid((nchunk + TPB - 1) / TPB, groups < MAX_GRID_Y ? groups : MAX_GRID_Y);
-    const float *lo = s.map_range ? d.lo : nullptr, *hi = s.map_range ? d.hi : nullptr;
     auto *k = s.m <= 64 ? (s.regen ? &k_guide<true, true> : &k_guide<true, false>)
                         : (s.regen ? &k_guide<false, true> : &k_guide<false, false>);
-    hipLaunchKernelGGL(k, grid, dim3(TPB), 0, st, d.F, d.A, d.SE, d.SG, d.top, d.bottom, d.tie, s.G,
-                       s.lam, s.k, s.inv_k, s.boost, groups, s.D, s.Dp, s.key, s.box, d.ctrl, s.N,
-                       lo, hi, d.Yc, s.C, s.m, s.lag);
+    hipLaunchKernelGGL(k, guide_grid(s), dim3(TPB), 0, st, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_guide_group(const GroupTable &t, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_guide_group, dim3(t.start[t.njobs]), dim3(TPB), 0, st, t);
     return hipGetLastError();
 }
 

@@ -100,9 +100,46 @@ struct InNet {
                                        // layer, 3 layer by layer with LDS-staged tiles
 };
 
+// Explosion sparks of a fitness launch that are not stored: launch row r is
+// explosion row r of generation ctrl[CTRL_GEN] + 1, regenerated from its
+// firework's row and amplitude (and the population range) exactly as the
+// explosion kernel draws it.
+struct SparkRegen {
+    const float *F, *A, *lo, *hi;
+    const int32_t *ctrl;
+    uint2 key;
+    Box box;
+    int lam, N, D, Dp;
+};
+
+// Arguments of the register-chain fitness kernel (fit_kernel.h).
+struct FitArgs {
+    const float *W;        // spark rows
+    size_t ld;             // row pitch (floats)
+    int rows;
+    const float *X;        // [S_pad][in_pad] (FP32 kernels)
+    const uint16_t *Xb;    // [S_pad][in_pad] bf16 bits (BF16 kernels)
+    int in_pad, S, S_pad;
+    int nl;
+    int fi[MAXL], fo[MAXL], woff[MAXL], boff[MAXL], act[MAXL], vec[MAXL];
+    // LDS layout (WL kernels), per layer: weight offset and row pitch in
+    // elements of the storage type, padded rows and columns, bias offset (floats)
+    int lw[MAXL], lpitch[MAXL], lrows[MAXL], lcols[MAXL], lb[MAXL];
+    int lbias_byte;        // start of the FP32 bias area
+    int loss;
+    const float *Y;        // [S_pad][out]
+    const int32_t *lab;    // [S_pad]
+    int bpr, spb;
+    float *partial;        // [rows][bpr]
+    // Explosion sparks regenerated while staging (rg.F non-null, LDS-staged
+    // kernels only); W is then not read.
+    SparkRegen rg;
+};
+
 // A chosen fitness kernel and its launch geometry for a given row count.
 struct FitPlan {
     const void *kernel;   // __global__ function
+    const void *gkernel;  // its grouped form (k_fit_group)
     int nw;               // wavefronts per block
     int P;                // 16-sample slabs per wave in flight
     int wl;               // weights staged in LDS
@@ -162,6 +199,83 @@ __device__ __forceinline__ size_t wide_pack_offset(const WidePack &p, int j, boo
     return wide_w1_offset(o, k, es);
 }
 
+// ---- grouped launches (batched generations) --------------------------------
+// A kernel body works on one block of its launch: Blk is that block's index and
+// the grid of the job's own launch.  A grouped launch runs the blocks of many
+// jobs' launches of one kernel as a single 1-D grid and hands every body the
+// block (and the job arguments) it would have had in the job's own launch, so a
+// job computes exactly what it computes alone.
+struct Blk {
+    int x, y, gx, gy;
+};
+
+__device__ __forceinline__ Blk own_block()
+{
+    return Blk{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, (int)gridDim.y};
+}
+
+// One fitness launch of a job: the kernel's arguments and its finalisation.
+struct FitLaunch {
+    FitArgs a;              // a.rows sparks, a.bpr partials each
+    float inv_norm;
+    OutMap map;
+    float *out;
+};
+
+// Per-job arguments of the grouped kernels, in device memory (the job's workspace).
+struct JobDesc {
+    Shape s;
+    DevState d;
+    FitLaunch fit[3];       // explosion sparks, guiding sparks, FP32 re-check (BF16 jobs)
+};
+
+constexpr int GROUP_MAX = 64;   // jobs per grouped launch
+
+struct GroupTable {
+    int njobs;
+    int start[GROUP_MAX + 1];          // first grouped block of job j; start[njobs] = total
+    int gx[GROUP_MAX], gy[GROUP_MAX];  // the job's own grid
+    const JobDesc *job[GROUP_MAX];
+};
+
+// The job owning grouped block `bid` (binary search over start[]).
+__device__ __forceinline__ int group_job(const GroupTable &t, int bid)
+{
+    int lo = 0, hi = t.njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (t.start[mid] <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ Blk group_block(const GroupTable &t, int j, int bid)
+{
+    const int l = bid - t.start[j];
+    return Blk{l % t.gx[j], l / t.gx[j], t.gx[j], t.gy[j]};
+}
+
+// Host side: a grouped launch over jobs[0..n) whose own grids are grid[i].
+void group_table(const JobDesc *const *jobs, const dim3 *grid, int n, GroupTable *t);
+
+// Each kernel's own grid for a job (the solo launches use the same functions),
+// and its grouped launch over a table.
+dim3 pop_range_grid(const Shape &s);
+dim3 explode_grid(const Shape &s);
+dim3 rank_grid(const Shape &s);
+dim3 guide_grid(const Shape &s);
+dim3 select_grid(const Shape &s);
+dim3 firework_row_grid(const Shape &s);     // apply, gather_best
+hipError_t launch_pop_range_group(const GroupTable &t, hipStream_t st);
+hipError_t launch_explode_group(const GroupTable &t, hipStream_t st);   // stored FP32 sparks
+hipError_t launch_rank_group(const GroupTable &t, int max_lam, hipStream_t st);
+hipError_t launch_guide_group(const GroupTable &t, hipStream_t st);
+hipError_t launch_gather_best_group(const GroupTable &t, hipStream_t st);
+hipError_t launch_select_group(const GroupTable &t, hipStream_t st);
+hipError_t launch_apply_group(const GroupTable &t, hipStream_t st);
+hipError_t launch_finish_group(const GroupTable &t, hipStream_t st);    // one block per job
+
 // ---- spark.hip
 hipError_t launch_init_positions(const Shape &s, const DevState &d, hipStream_t st);
 hipError_t launch_pop_range(const Shape &s, const DevState &d, hipStream_t st);
@@ -201,9 +315,25 @@ hipError_t fit_prepare(const FitPlan &plan);
 // Fitness of `rows` sparks into out[map(row)]: the GEMM kernel writes one partial
 // per (row, block); the finalisation sums them in order.  `mid` (optional) is
 // recorded between the two launches.
+// rg (LDS-staged plans only): the sparks are regenerated, W is not read.
 hipError_t launch_fitness(const Net &net, const FitPlan &plan, const DevState &d,
                           const float *W, size_t ld, int rows, OutMap map, float *out,
-                          hipStream_t st, hipEvent_t mid = nullptr);
+                          hipStream_t st, hipEvent_t mid = nullptr,
+                          const SparkRegen *rg = nullptr);
+// The kernel arguments and finalisation of one fitness launch (what
+// launch_fitness passes), for a grouped launch's job descriptor.
+FitLaunch fit_launch_args(const Net &net, const FitPlan &plan, const DevState &d, const float *W,
+                          size_t ld, int rows, OutMap map, float *out,
+                          const SparkRegen *rg = nullptr);
+// Fitness launch `which` of every job of t, all on the same kernel instance
+// (gkernel, nw wavefronts, lds_bytes of dynamic LDS: the most any of them needs;
+// fit_group_prepare must have allowed it).
+hipError_t fit_group_prepare(const void *gkernel, int lds_bytes);
+hipError_t launch_fitness_group(const GroupTable &t, const void *gkernel, int nw, int lds_bytes,
+                                int which, hipStream_t st);
+hipError_t launch_finalize_group(const GroupTable &t, int which, hipStream_t st);
+dim3 fitness_grid(const FitLaunch &f);     // the job's own grid of the GEMM kernel
+dim3 finalize_grid(const FitLaunch &f);
 hipError_t launch_pack_problem(const Net &net, const float *x, const float *y,
                                const int32_t *labels, const DevState &d, hipStream_t st);
 // largest partial-sum count per row any plan may use

@@ -71,24 +71,28 @@ __device__ void population_best(const float *Y, int N, int *fb_out, float *yb_ou
     *yb_out = yb;
 }
 
-__global__ __launch_bounds__(TPB) void k_select(Shape s, float *__restrict__ Yc, float *__restrict__ Y,
-                                                float *__restrict__ Yprev, float *__restrict__ A,
-                                                float *__restrict__ Aexp,
-                                                int32_t *__restrict__ fresh,
-                                                int32_t *__restrict__ cstar,
-                                                int32_t *__restrict__ improved,
-                                                int32_t *__restrict__ reinit,
-                                                int32_t *__restrict__ src,
-                                                float *__restrict__ best_y,
-                                                int32_t *__restrict__ best_f,
-                                                int32_t *__restrict__ best_gen,
-                                                int32_t *__restrict__ best_upd,
-                                                const float *__restrict__ ystar,
-                                                int32_t *__restrict__ ctrl)
+__device__ __forceinline__ void select_body(const Shape &s, const DevState &d, bool checked,
+                                            Blk blk)
 {
+    float *__restrict__ Yc = d.Yc;
+    float *__restrict__ Y = d.Y;
+    float *__restrict__ Yprev = d.Yprev;
+    float *__restrict__ A = d.A;
+    float *__restrict__ Aexp = d.Aexp;
+    int32_t *__restrict__ fresh = d.fresh;
+    int32_t *__restrict__ cstar = d.cstar;
+    int32_t *__restrict__ improved = d.improved;
+    int32_t *__restrict__ reinit = d.reinit;
+    int32_t *__restrict__ src = d.src;
+    float *__restrict__ best_y = d.best_y;
+    int32_t *__restrict__ best_f = d.best_f;
+    int32_t *__restrict__ best_gen = d.best_gen;
+    int32_t *__restrict__ best_upd = d.best_upd;
+    const float *__restrict__ ystar = checked ? d.Ystar : nullptr;
+    int32_t *__restrict__ ctrl = d.ctrl;
     if (ctrl[CTRL_DONE]) return;
     const int t = ctrl[CTRL_GEN] + 1;
-    const int b = blockIdx.x, N = s.N;
+    const int b = blk.x, N = s.N;
     __shared__ int s_fb;
     __shared__ float s_yb;
     // one wavefront per firework: c* and its fitness (with ystar, both come from
@@ -155,6 +159,11 @@ __global__ __launch_bounds__(TPB) void k_select(Shape s, float *__restrict__ Yc,
     }
 }
 
+__global__ __launch_bounds__(TPB) void k_select(Shape s, DevState d, int checked)
+{
+    select_body(s, d, checked != 0, own_block());
+}
+
 // After the initial fitness: Yprev = Y, best-so-far = population best at generation 0.
 __global__ __launch_bounds__(TPB) void k_init_select(Shape s, const float *__restrict__ Y,
                                                      float *__restrict__ Yprev,
@@ -191,25 +200,26 @@ __global__ __launch_bounds__(TPB) void k_init_select(Shape s, const float *__res
 // row (still the generation's, read before it is overwritten), its explosion
 // amplitude and the population range, exactly as the explosion drew it.  With
 // wstar the winner is the row k_gather_best stored there.
-__global__ __launch_bounds__(TPB) void k_apply(Shape s, float *__restrict__ F,
-                                               const float *__restrict__ SE,
-                                               const float *__restrict__ SG,
-                                               const float *__restrict__ Aexp,
-                                               const float *__restrict__ lo,
-                                               const float *__restrict__ hi,
-                                               const int32_t *__restrict__ src,
-                                               const int32_t *__restrict__ reinit,
-                                               const int32_t *__restrict__ best_f,
-                                               const int32_t *__restrict__ best_upd,
-                                               float *__restrict__ best_x,
-                                               const float *__restrict__ wstar,
-                                               const int32_t *__restrict__ ctrl)
+__device__ __forceinline__ void apply_body(const Shape &s, const DevState &d, bool checked, Blk blk)
 {
+    float *__restrict__ F = d.F;
+    const float *__restrict__ SE = d.SE;
+    const float *__restrict__ SG = d.SG;
+    const float *__restrict__ Aexp = d.Aexp;
+    const float *__restrict__ lo = s.map_range ? d.lo : nullptr;
+    const float *__restrict__ hi = s.map_range ? d.hi : nullptr;
+    const int32_t *__restrict__ src = d.src;
+    const int32_t *__restrict__ reinit = d.reinit;
+    const int32_t *__restrict__ best_f = d.best_f;
+    const int32_t *__restrict__ best_upd = d.best_upd;
+    float *__restrict__ best_x = d.best_x;
+    const float *__restrict__ wstar = checked ? d.Wstar : nullptr;
+    const int32_t *__restrict__ ctrl = d.ctrl;
     if (ctrl[CTRL_DONE]) return;
     const uint32_t t = (uint32_t)ctrl[CTRL_GEN] + 1u;
-    const int chunk = blockIdx.x * TPB + threadIdx.x;
+    const int chunk = blk.x * TPB + threadIdx.x;
     if (chunk >= (s.Dp >> 2)) return;
-    for (int gf = blockIdx.y; gf < s.BN; gf += gridDim.y) {
+    for (int gf = blk.y; gf < s.BN; gf += blk.gy) {
         const int b = gf / s.N, f = gf % s.N;
         const int sr = src[gf], ri = reinit[gf];
         const bool copy_best = best_upd[b] && best_f[b] == f;
@@ -252,40 +262,41 @@ __global__ __launch_bounds__(TPB) void k_apply(Shape s, float *__restrict__ F,
     }
 }
 
-// c* of firework blockIdx.y (every block recomputes it: C values, one
+__global__ __launch_bounds__(TPB) void k_apply(Shape s, DevState d, int checked)
+{
+    apply_body(s, d, checked != 0, own_block());
+}
+
+// c* of firework blk.y (every block recomputes it: C values, one
 // wavefront) and coordinates 4*chunk.. of its row: an explosion spark
 // (regenerated from the firework's row and amplitude when s.regen, as the
 // explosion drew it) or a guiding spark.  Runs before k_select, so F and A
 // still hold the generation's values.
-__global__ __launch_bounds__(TPB) void k_gather_best(Shape s, const float *__restrict__ Yc,
-                                                     const float *__restrict__ F,
-                                                     const float *__restrict__ A,
-                                                     const float *__restrict__ SE,
-                                                     const float *__restrict__ SG,
-                                                     const float *__restrict__ lo,
-                                                     const float *__restrict__ hi,
-                                                     int32_t *__restrict__ cstar,
-                                                     float *__restrict__ wstar,
-                                                     const int32_t *__restrict__ ctrl)
+__device__ __forceinline__ void gather_best_body(const Shape &s, const DevState &d, Blk blk)
 {
-    if (ctrl[CTRL_DONE]) return;
-    const uint32_t t = (uint32_t)ctrl[CTRL_GEN] + 1u;
+    const float *__restrict__ Yc = d.Yc;
+    const float *__restrict__ F = d.F;
+    const float *__restrict__ A = d.A;
+    const float *__restrict__ lo = s.map_range ? d.lo : nullptr;
+    const float *__restrict__ hi = s.map_range ? d.hi : nullptr;
+    if (d.ctrl[CTRL_DONE]) return;
+    const uint32_t t = (uint32_t)d.ctrl[CTRL_GEN] + 1u;
     __shared__ int s_cs;
     const int nchunk = s.Dp >> 2;
-    for (int gf = blockIdx.y; gf < s.BN; gf += gridDim.y) {
+    for (int gf = blk.y; gf < s.BN; gf += blk.gy) {
         if (threadIdx.x < 64) {
             float ymin;
             int cs;
             best_candidate(Yc + (size_t)gf * s.C, s.C, threadIdx.x, &ymin, &cs);
             if (threadIdx.x == 0) {
                 s_cs = cs;
-                if (blockIdx.x == 0) cstar[gf] = cs;
+                if (blk.x == 0) d.cstar[gf] = cs;
             }
         }
         __syncthreads();
         const int cs = s_cs;
         __syncthreads();   // s_cs is rewritten for the next firework
-        const int chunk = blockIdx.x * TPB + threadIdx.x;
+        const int chunk = blk.x * TPB + threadIdx.x;
         if (chunk >= nchunk) continue;
         float4 v;
         if (cs < s.lam && s.regen) {
@@ -297,12 +308,17 @@ __global__ __launch_bounds__(TPB) void k_gather_best(Shape s, const float *__res
                             lo ? lo + pb : nullptr, hi ? hi + pb : nullptr, s.D, e4);
             v = make_float4(e4[0], e4[1], e4[2], e4[3]);
         } else {
-            const float *row = cs < s.lam ? SE + ((size_t)gf * s.lam + cs) * s.Dp
-                                          : SG + ((size_t)gf * s.G + (cs - s.lam)) * s.Dp;
+            const float *row = cs < s.lam ? d.SE + ((size_t)gf * s.lam + cs) * s.Dp
+                                          : d.SG + ((size_t)gf * s.G + (cs - s.lam)) * s.Dp;
             v = reinterpret_cast<const float4 *>(row)[chunk];
         }
-        reinterpret_cast<float4 *>(wstar + (size_t)gf * s.Dp)[chunk] = v;
+        reinterpret_cast<float4 *>(d.Wstar + (size_t)gf * s.Dp)[chunk] = v;
     }
+}
+
+__global__ __launch_bounds__(TPB) void k_gather_best(Shape s, DevState d)
+{
+    gather_best_body(s, d, own_block());
 }
 
 __global__ void k_clear_ctrl(int32_t *ctrl)
@@ -310,12 +326,46 @@ __global__ void k_clear_ctrl(int32_t *ctrl)
     if (threadIdx.x < CTRL_WORDS) ctrl[threadIdx.x] = 0;
 }
 
-__global__ void k_finish(int32_t *ctrl, int advance)
+__device__ __forceinline__ void finish_body(int32_t *ctrl, int advance)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (threadIdx.x != 0) return;
     if (ctrl[CTRL_DONE]) return;
     if (advance) ctrl[CTRL_GEN] = ctrl[CTRL_GEN] + 1;
     if (ctrl[CTRL_DONE_PENDING]) ctrl[CTRL_DONE] = 1;
+}
+
+__global__ void k_finish(int32_t *ctrl, int advance)
+{
+    if (blockIdx.x != 0) return;
+    finish_body(ctrl, advance);
+}
+
+// ---- grouped launches: the same bodies over many jobs (one grid) ----
+__global__ __launch_bounds__(TPB) void k_select_group(GroupTable t)
+{
+    const int j = group_job(t, blockIdx.x);
+    const JobDesc &J = *t.job[j];
+    select_body(J.s, J.d, J.s.recheck != 0, group_block(t, j, blockIdx.x));
+}
+
+__global__ __launch_bounds__(TPB) void k_apply_group(GroupTable t)
+{
+    const int j = group_job(t, blockIdx.x);
+    const JobDesc &J = *t.job[j];
+    apply_body(J.s, J.d, J.s.recheck != 0, group_block(t, j, blockIdx.x));
+}
+
+__global__ __launch_bounds__(TPB) void k_gather_best_group(GroupTable t)
+{
+    const int j = group_job(t, blockIdx.x);
+    const JobDesc &J = *t.job[j];
+    gather_best_body(J.s, J.d, group_block(t, j, blockIdx.x));
+}
+
+// one block per job (the solo launch has one block)
+__global__ void k_finish_group(GroupTable t)
+{
+    finish_body(t.job[group_job(t, blockIdx.x)]->d.ctrl, 1);
 }
 
 __global__ __launch_bounds__(TPB) void k_store_fitness(const float *__restrict__ in, int rows,
@@ -330,22 +380,48 @@ __global__ __launch_bounds__(TPB) void k_store_fitness(const float *__restrict__
 
 }  // namespace
 
+dim3 select_grid(const Shape &s) { return dim3(s.B); }
+
+// grid over (4-coordinate chunk, firework): apply and gather
+dim3 firework_row_grid(const Shape &s)
+{
+    const int nchunk = s.Dp >> 2;
+    return dim3((nchunk + TPB - 1) / TPB, s.BN < MAX_GRID_Y ? s.BN : MAX_GRID_Y);
+}
+
 hipError_t launch_select(const Shape &s, const DevState &d, hipStream_t st, bool checked)
 {
-    hipLaunchKernelGGL(k_select, dim3(s.B), dim3(TPB), 0, st, s, d.Yc, d.Y, d.Yprev, d.A, d.Aexp,
-                       d.fresh,
-                       d.cstar, d.improved, d.reinit, d.src, d.best_y, d.best_f, d.best_gen,
-                       d.best_upd, checked ? d.Ystar : nullptr, d.ctrl);
+    hipLaunchKernelGGL(k_select, select_grid(s), dim3(TPB), 0, st, s, d, checked ? 1 : 0);
     return hipGetLastError();
 }
 
 hipError_t launch_gather_best(const Shape &s, const DevState &d, hipStream_t st)
 {
-    const int nchunk = s.Dp >> 2;
-    dim3 grid((nchunk + TPB - 1) / TPB, s.BN < MAX_GRID_Y ? s.BN : MAX_GRID_Y);
-    hipLaunchKernelGGL(k_gather_best, grid, dim3(TPB), 0, st, s, d.Yc, d.F, d.A, d.SE, d.SG,
-                       s.map_range ? d.lo : nullptr, s.map_range ? d.hi : nullptr, d.cstar,
-                       d.Wstar, d.ctrl);
+    hipLaunchKernelGGL(k_gather_best, firework_row_grid(s), dim3(TPB), 0, st, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_group(const GroupTable &t, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_select_group, dim3(t.start[t.njobs]), dim3(TPB), 0, st, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_group(const GroupTable &t, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_apply_group, dim3(t.start[t.njobs]), dim3(TPB), 0, st, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_best_group(const GroupTable &t, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gather_best_group, dim3(t.start[t.njobs]), dim3(TPB), 0, st, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_group(const GroupTable &t, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_finish_group, dim3(t.start[t.njobs]), dim3(64), 0, st, t);
     return hipGetLastError();
 }
 
@@ -358,11 +434,7 @@ hipError_t launch_init_select(const Shape &s, const DevState &d, hipStream_t st)
 
 hipError_t launch_apply(const Shape &s, const DevState &d, hipStream_t st, bool checked)
 {
-    const int nchunk = s.Dp >> 2;
-    dim3 grid((nchunk + TPB - 1) / TPB, s.BN < MAX_GRID_Y ? s.BN : MAX_GRID_Y);
-    hipLaunchKernelGGL(k_apply, grid, dim3(TPB), 0, st, s, d.F, d.SE, d.SG, d.Aexp,
-                       s.map_range ? d.lo : nullptr, s.map_range ? d.hi : nullptr, d.src, d.reinit,
-                       d.best_f, d.best_upd, d.best_x, checked ? d.Wstar : nullptr, d.ctrl);
+    hipLaunchKernelGGL(k_apply, firework_row_grid(s), dim3(TPB), 0, st, s, d, checked ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -36,15 +36,14 @@ __global__ __launch_bounds__(TPB) void k_init_positions(float *__restrict__ F,
 
 // Per-dimension minimum and maximum over the N fireworks of every population
 // (the range the range-mapping variant draws into), fireworks in index order.
-__global__ __launch_bounds__(TPB) void k_pop_range(const float *__restrict__ F, int N, int B,
-                                                   int Dp, float *__restrict__ lo,
-                                                   float *__restrict__ hi,
-                                                   const int32_t *__restrict__ ctrl)
+__device__ __forceinline__ void pop_range_body(const float *__restrict__ F, int N, int B, int Dp,
+                                               float *__restrict__ lo, float *__restrict__ hi,
+                                               const int32_t *__restrict__ ctrl, Blk blk)
 {
     if (ctrl[CTRL_DONE]) return;
-    const int d = blockIdx.x * TPB + threadIdx.x;
+    const int d = blk.x * TPB + threadIdx.x;
     if (d >= Dp) return;
-    for (int b = blockIdx.y; b < B; b += gridDim.y) {
+    for (int b = blk.y; b < B; b += blk.gy) {
         const float *f0 = F + (size_t)b * N * Dp;
         float a = f0[d], c = f0[d];
         for (int f = 1; f < N; ++f) {
@@ -55,6 +54,22 @@ __global__ __launch_bounds__(TPB) void k_pop_range(const float *__restrict__ F, 
         lo[(size_t)b * Dp + d] = a;
         hi[(size_t)b * Dp + d] = c;
     }
+}
+
+__global__ __launch_bounds__(TPB) void k_pop_range(const float *__restrict__ F, int N, int B,
+                                                   int Dp, float *__restrict__ lo,
+                                                   float *__restrict__ hi,
+                                                   const int32_t *__restrict__ ctrl)
+{
+    pop_range_body(F, N, B, Dp, lo, hi, ctrl, own_block());
+}
+
+__global__ __launch_bounds__(TPB) void k_pop_range_group(GroupTable t)
+{
+    const int j = group_job(t, blockIdx.x);
+    const JobDesc &J = *t.job[j];
+    pop_range_body(J.d.F, J.s.N, J.s.B, J.s.Dp, J.d.lo, J.d.hi, J.d.ctrl,
+                   group_block(t, j, blockIdx.x));
 }
 
 // Explosion spark j of firework f (row = f*lambda + j) for generation t+1:
@@ -101,19 +116,19 @@ __device__ __forceinline__ void pack_four(const WidePack &wp, int row, int j0, i
 // SE null: the FP32 rows are not stored (the packed rows are the only copy the
 // fitness needs; later steps regenerate the sparks they read).
 template <int PACK>   // 0: no packing, 1: FP32 packed rows, 2: BF16
-__global__ __launch_bounds__(TPB) void k_explode(const float *__restrict__ F,
-                                                 const float *__restrict__ A,
-                                                 float *__restrict__ SE, int lam, int rows, int D,
-                                                 int Dp, uint2 key, Box box,
-                                                 const int32_t *__restrict__ ctrl, int N,
-                                                 const float *__restrict__ lo,
-                                                 const float *__restrict__ hi, WidePack wp)
+__device__ __forceinline__ void explode_body(const float *__restrict__ F, const float *__restrict__ A,
+                                             float *__restrict__ SE, int lam, int rows, int D,
+                                             int Dp, uint2 key, Box box,
+                                             const int32_t *__restrict__ ctrl, int N,
+                                             const float *__restrict__ lo,
+                                             const float *__restrict__ hi, const WidePack &wp,
+                                             Blk b)
 {
     if (ctrl[CTRL_DONE]) return;
     const uint32_t tn = (uint32_t)ctrl[CTRL_GEN] + 1u;
-    const int chunk = blockIdx.x * TPB + threadIdx.x;
+    const int chunk = b.x * TPB + threadIdx.x;
     if (chunk >= (Dp >> 2)) return;
-    for (int row = blockIdx.y; row < rows; row += gridDim.y) {
+    for (int row = b.y; row < rows; row += b.gy) {
         const int gf = row / lam;
         const float amp = A[gf];
         const float4 x4 = reinterpret_cast<const float4 *>(F + (size_t)gf * Dp)[chunk];
@@ -127,6 +142,30 @@ __global__ __launch_bounds__(TPB) void k_explode(const float *__restrict__ F,
         if constexpr (PACK != 0)
             if (4 * chunk < D) pack_four<PACK == 2>(wp, row, 4 * chunk, D, s);
     }
+}
+
+template <int PACK>
+__global__ __launch_bounds__(TPB) void k_explode(const float *__restrict__ F,
+                                                 const float *__restrict__ A,
+                                                 float *__restrict__ SE, int lam, int rows, int D,
+                                                 int Dp, uint2 key, Box box,
+                                                 const int32_t *__restrict__ ctrl, int N,
+                                                 const float *__restrict__ lo,
+                                                 const float *__restrict__ hi, WidePack wp)
+{
+    explode_body<PACK>(F, A, SE, lam, rows, D, Dp, key, box, ctrl, N, lo, hi, wp, own_block());
+}
+
+// The explosion of many jobs (stored FP32 sparks, no packed rows) in one launch.
+__global__ __launch_bounds__(TPB) void k_explode_group(GroupTable t)
+{
+    const int j = group_job(t, blockIdx.x);
+    const JobDesc &J = *t.job[j];
+    const Shape &s = J.s;
+    const DevState &d = J.d;
+    explode_body<0>(d.F, d.A, d.SE, s.lam, s.BN * s.lam, s.D, s.Dp, s.key, s.box, d.ctrl, s.N,
+                    s.map_range ? d.lo : nullptr, s.map_range ? d.hi : nullptr, WidePack{},
+                    group_block(t, j, blockIdx.x));
 }
 
 // Blocks over (chunk range, rows); a block takes rows_per_block rows (strided by
@@ -147,11 +186,36 @@ hipError_t launch_init_positions(const Shape &s, const DevState &d, hipStream_t 
     return hipGetLastError();
 }
 
+dim3 pop_range_grid(const Shape &s)
+{
+    return dim3((s.Dp + TPB - 1) / TPB, s.B < MAX_GRID_Y ? s.B : MAX_GRID_Y);
+}
+
+dim3 explode_grid(const Shape &s)
+{
+    const int rows = s.BN * s.lam;
+    // 32 or 8 rows per block while there are enough blocks to fill the device
+    const long blocks_x = ((s.Dp >> 2) + TPB - 1) / TPB;
+    const int rpb = blocks_x * (rows / 32) >= 2048 ? 32 : blocks_x * (rows / 8) >= 2048 ? 8 : 1;
+    return row_grid(s.Dp, rows, rpb);
+}
+
 hipError_t launch_pop_range(const Shape &s, const DevState &d, hipStream_t st)
 {
-    const dim3 grid((s.Dp + TPB - 1) / TPB, s.B < MAX_GRID_Y ? s.B : MAX_GRID_Y);
-    hipLaunchKernelGGL(k_pop_range, grid, dim3(TPB), 0, st, d.F, s.N,
+    hipLaunchKernelGGL(k_pop_range, pop_range_grid(s), dim3(TPB), 0, st, d.F, s.N,
                        s.B, s.Dp, d.lo, d.hi, d.ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_pop_range_group(const GroupTable &t, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pop_range_group, dim3(t.start[t.njobs]), dim3(TPB), 0, st, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_explode_group(const GroupTable &t, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_explode_group, dim3(t.start[t.njobs]), dim3(TPB), 0, st, t);
     return hipGetLastError();
 }
 
@@ -159,13 +223,10 @@ hipError_t launch_explode(const Shape &s, const DevState &d, hipStream_t st, con
                           bool write_se)
 {
     const int rows = s.BN * s.lam;
-    // 32 or 8 rows per block while there are enough blocks to fill the device
-    const long blocks_x = ((s.Dp >> 2) + TPB - 1) / TPB;
-    const int rpb = blocks_x * (rows / 32) >= 2048 ? 32 : blocks_x * (rows / 8) >= 2048 ? 8 : 1;
     const WidePack none{};
     const WidePack &w = wp ? *wp : none;
     auto *k = !wp ? &k_explode<0> : wp->bf16 ? &k_explode<2> : &k_explode<1>;
-    hipLaunchKernelGGL(k, row_grid(s.Dp, rows, rpb), dim3(TPB), 0, st, d.F, d.A,
+    hipLaunchKernelGGL(k, explode_grid(s), dim3(TPB), 0, st, d.F, d.A,
                        write_se || !wp ? d.SE : nullptr, s.lam, rows,
                        s.D, s.Dp, s.key, s.box, d.ctrl, s.N, s.map_range ? d.lo : nullptr,
                        s.map_range ? d.hi : nullptr, w);

@@ -43,7 +43,7 @@ class mgfwa_config(C.Structure):
                 ("lb", C.c_float), ("ub", C.c_float), ("max_generations", C.c_int),
                 ("loser_out", C.c_int), ("precision", C.c_int), ("external_fitness", C.c_int),
                 ("use_target", C.c_int), ("target_loss", C.c_float), ("seed", C.c_uint64),
-                ("lag_guiding", C.c_int), ("map_range", C.c_int), ("fit_path", C.c_int)]
+                ("lag_guiding", C.c_int), ("map_range", C.c_int), ("fit_path", C.c_int), ("regen_sparks", C.c_int)]
 
 
 _STATE_ARRAYS = ("F", "A", "Y", "Yprev", "fresh", "SE", "SG", "Yc", "top", "bottom", "tie",
@@ -143,7 +143,8 @@ def lib() -> C.CDLL:
     L.mgfwa_server_destroy.argtypes = [C.c_void_p]
     L.mgfwa_server_destroy.restype = None
     for name in ("mgfwa_init", "mgfwa_step", "mgfwa_best", "mgfwa_best_all", "mgfwa_ask",
-                 "mgfwa_tell", "mgfwa_evaluate", "mgfwa_state", "mgfwa_set_timing",
+                 "mgfwa_tell", "mgfwa_evaluate", "mgfwa_state",
+                 "mgfwa_set_timing",
                  "mgfwa_timing", "mgfwa_autotune", "mgfwa_fit_plan", "mgfwa_fit_candidates",
                  "mgfwa_set_fit_plan", "mgfwa_batch_create",
                  "mgfwa_batch_step", "mgfwa_server_create", "mgfwa_server_submit",
@@ -162,7 +163,8 @@ def _check(status: int) -> None:
 def make_config(n_fireworks=4, n_sparks=32, n_guiding=4, n_populations=1, sigma=0.2, boost=1.0,
                 amp_up=1.2, amp_down=0.9, amp_init=0.0, lb=-5.0, ub=5.0, max_generations=100,
                 loser_out=True, precision="fp32", external_fitness=False, target_loss=None,
-                seed=0, lag_guiding=False, map_range=False, fit_path=0) -> mgfwa_config:
+                seed=0, lag_guiding=False, map_range=False, fit_path=0,
+                regen_sparks=False) -> mgfwa_config:
     c = mgfwa_config()
     c.n_populations, c.n_fireworks, c.n_sparks, c.n_guiding = (
         n_populations, n_fireworks, n_sparks, n_guiding)
@@ -177,6 +179,7 @@ def make_config(n_fireworks=4, n_sparks=32, n_guiding=4, n_populations=1, sigma=
     c.lag_guiding = int(bool(lag_guiding))
     c.map_range = int(bool(map_range))
     c.fit_path = int(fit_path)
+    c.regen_sparks = int(bool(regen_sparks))
     return c
 
 

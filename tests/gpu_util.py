@@ -25,7 +25,7 @@ def require_gpu():
 def make_pair(wl, n_populations=1, n_fireworks=None, n_sparks=None, n_guiding=None, sigma=0.2,
               boost=1.0, amp_up=1.2, amp_down=0.9, T=None, seed=0, loser_out=True, target=None,
               external=False, precision="fp32", with_oracle=True, lag_guiding=False,
-              map_range=False, fit_path=0):
+              map_range=False, fit_path=0, regen_sparks=False):
     torch, M = require_gpu()
     N = n_fireworks or wl.n_fireworks
     lam = n_sparks or wl.n_sparks
@@ -46,7 +46,7 @@ def make_pair(wl, n_populations=1, n_fireworks=None, n_sparks=None, n_guiding=No
                 amp_up=amp_up, amp_down=amp_down, lb=wl.lb, ub=wl.ub, max_generations=T,
                 loser_out=loser_out, precision=precision, external_fitness=external,
                 target_loss=target, seed=seed, lag_guiding=lag_guiding, map_range=map_range,
-                fit_path=fit_path)
+                fit_path=fit_path, regen_sparks=regen_sparks)
     return o, g
 
 

@@ -97,6 +97,42 @@ def test_batched_jobs_match_oracle():
         g.close()
 
 
+def test_mixed_batch_grouped_and_branch_jobs_equal_alone():
+    """A batch whose register-chain jobs run as grouped launches (one grid per
+    kernel for all of them: stored and regenerated sparks, range mapping, two
+    populations, groups ranked in and outside the guiding kernel, BF16 with the
+    FP32 re-check) beside jobs kept as their own graph branches (the wide
+    kernel, the lag order): every job ends bit for bit as when stepped alone."""
+    torch, M = require_gpu()
+    gmm = inputs.gaussian_mixture(n_samples=300, widths=(32, 64, 10), n_fireworks=3, n_sparks=32)
+    teacher = inputs.teacher_regression(n_samples=128)
+    wide = inputs.random_mlp_problem((40, 64, 5), ("relu",), "ce", 300, seed=3)
+    specs = [
+        (gmm, dict(seed=1)),
+        (gmm, dict(seed=2, regen_sparks=True, map_range=True, n_populations=2)),
+        (teacher, dict(seed=3, precision="bf16")),
+        (teacher, dict(seed=4, n_fireworks=2, n_sparks=160, n_guiding=2)),   # 80 per group
+        (wide, dict(seed=5, n_fireworks=3, n_sparks=16, n_guiding=2, fit_path=2)),
+        (teacher, dict(seed=6, lag_guiding=True)),
+        (gmm, dict(seed=7, precision="bf16", regen_sparks=True)),
+    ]
+    jobs = [_ctx(M, wl, max_generations=30, **cfg) for wl, cfg in specs]
+    b = M.Batch(jobs)
+    b.step(2)
+    b.step(4)
+    torch.cuda.synchronize()
+    for i, (wl, cfg) in enumerate(specs):
+        alone = _ctx(M, wl, max_generations=30, **cfg)
+        alone.step(6)
+        sa, sb = alone.state_numpy(), jobs[i].state_numpy()
+        for k in STATE_KEYS:
+            assert_bits(sb[k], sa[k], f"job {i} {cfg} {k}")
+        alone.close()
+    b.close()
+    for g in jobs:
+        g.close()
+
+
 def test_batch_and_own_steps_interleave_in_order():
     torch, M = require_gpu()
     js, cfgs = _jobs(n=3)

@@ -9,6 +9,10 @@
   generations agree with the oracle's bit for bit (sparks, ranking sets,
   selection, amplitudes) until a decision compares two fitness values within
   the FP32 tolerance; every fitness value stays within that tolerance.
+* Sparks regenerated instead of stored (regen_sparks): the fitness kernel draws
+  each explosion spark from the counter-based generator while staging its
+  weights; the state equals the stored-sparks run bit for bit and follows the
+  oracle like every other run.
 """
 import numpy as np
 import pytest
@@ -96,3 +100,39 @@ def test_lag_plan_covers_both_spark_kinds():
         g.step(1)
         assert_fitness_close(g.state_numpy()["Yc"], o.view()["Yc64"], f"gen {gen} tuned lag")
     g.close()
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(regen_sparks=True),
+    dict(regen_sparks=True, map_range=True, n_populations=2, seed=3),
+])
+def test_free_running_regenerated_sparks_match_oracle(cfg):
+    torch, M = require_gpu()
+    wl = inputs.teacher_regression()
+    probe = M.MGFWA.from_workload(wl, regen_sparks=True)
+    assert probe.fit_plan(0)["lds_weights"] == 1 and not probe.sparks_materialised
+    probe.close()
+    at = _free_run(wl, 60, **cfg)
+    print(f"{cfg}: diverged_at={at}")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_regenerated_sparks_equal_stored_sparks(precision):
+    """The same job with its explosion sparks stored and regenerated inside the
+    fitness kernel: every array of the state is bit-identical each generation."""
+    torch, M = require_gpu()
+    wl = inputs.gaussian_mixture(n_samples=512)
+    kw = dict(n_fireworks=3, n_sparks=32, n_guiding=4, seed=7, precision=precision,
+              max_generations=40)
+    a = M.MGFWA.from_workload(wl, **kw)
+    b = M.MGFWA.from_workload(wl, regen_sparks=True, **kw)
+    assert a.sparks_materialised and not b.sparks_materialised
+    assert a.fit_plan(0) == b.fit_plan(0)
+    for gen in range(1, 9):
+        a.step(1)
+        b.step(1)
+        sa, sb = a.state_numpy(), b.state_numpy()
+        for name in ("F", "A", "Y", "Yc", "SG", "top", "bottom", "best_x", "best_y", "reinit"):
+            assert_bits(sb[name], sa[name], f"generation {gen} {name}")
+    a.close()
+    b.close()
