@@ -301,6 +301,36 @@ MGFWA_API mgfwa_status mgfwa_tell(mgfwa_ctx *ctx, const float *fitness_dev);
 MGFWA_API mgfwa_status mgfwa_evaluate(mgfwa_ctx *ctx, const float *w_dev, int rows, int ld,
                                       float *out_dev);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops or harnesses that forbid allocation): the fitness of `rows`
+ * sparks of a weights problem (kind = MGFWA_PROBLEM_WEIGHTS), with no context and
+ * no workspace.  It runs the kernels and launch shapes of mgfwa_evaluate (no
+ * autotuning) in the given precision, so its values equal those of mgfwa_evaluate
+ * on a context of the same problem and precision whenever both take the rows in
+ * one launch.
+ * problem   the MLP loss problem as for mgfwa_init; its x/y/labels buffers are
+ *           read in stream order by this call.
+ * precision mgfwa_precision of the fitness GEMMs.
+ * w_dev     float [rows][ld] device (16-byte aligned, ld >= D, ld % 4 == 0);
+ * out_dev   float [rows] device; both caller-owned, in stream order.
+ * hip_stream  a stream created by the caller (NULL -> EINVAL).
+ * Scratch: the packed samples, targets and per-row partial sums live in a
+ * library-held device array of MGFWA_NOALLOC_SCRATCH_BYTES (one per device, held
+ * until the process ends); rows are taken in chunks that fit it.  EINVAL when
+ * the packed problem plus one row does not fit.  The call allocates nothing
+ * (no hipMalloc/hipFree, no library allocation) and does not wait for the device.
+ * Every call on one device shares that device's array: calls that may overlap
+ * on one device (different streams, or different host threads) race; order
+ * them on one stream.  Errors: EINVAL (arguments, problem too large for the
+ * scratch), EUNSUPPORTED (input problems, shapes outside the compiled kernels),
+ * EHIP.
+ */
+#define MGFWA_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+MGFWA_API mgfwa_status mgfwa_evaluate_noalloc(const mgfwa_problem *problem, int precision,
+                                              const float *w_dev, int rows, int ld,
+                                              float *out_dev, void *hip_stream);
+
 /* Offsets and dimensions of the device state (no device work). */
 MGFWA_API mgfwa_status mgfwa_state(const mgfwa_ctx *ctx, mgfwa_state_info *info);
 

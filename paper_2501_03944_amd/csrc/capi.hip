@@ -1006,6 +1006,137 @@ void mgfwa_destroy(mgfwa_ctx *c)
 
 }  // extern "C"
 
+// ---- fitness without a workspace --------------------------------------------
+namespace {
+
+// Device scratch of mgfwa_evaluate_noalloc: a file-scope device array, so every
+// device the library runs on holds its own copy until the process ends.  In host
+// code its name is only a stand-in: kernels get the per-device address that
+// hipGetSymbolAddress returns.
+__device__ __align__(256) char scratch[MGFWA_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch[MAX_DEVICES] = {};
+
+// Address of the current device's scratch, looked up on its first use there.
+mgfwa_status scratch_address(int dev, char **out)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(MGFWA_EHIP, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(MGFWA_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch[dev] = static_cast<char *>(p);
+    }
+    *out = g_scratch[dev];
+    return MGFWA_OK;
+}
+
+}  // namespace
+
+extern "C" mgfwa_status mgfwa_evaluate_noalloc(const mgfwa_problem *problem, int precision,
+                                               const float *w, int rows, int ld, float *out,
+                                               void *hip_stream)
+{
+    if (!problem) return fail(MGFWA_EINVAL, "problem is NULL");
+    if (!hip_stream)
+        return fail(MGFWA_EINVAL, "hip_stream is NULL: pass a stream created by the caller");
+    if (problem->kind != MGFWA_PROBLEM_WEIGHTS)
+        return fail(MGFWA_EUNSUPPORTED, "mgfwa_evaluate_noalloc takes weights problems only");
+    // the network as a context of this problem would see it (one firework)
+    mgfwa_config cfg{};
+    cfg.n_populations = cfg.n_fireworks = cfg.n_guiding = 1;
+    cfg.n_sparks = 2;
+    cfg.sigma = 0.5f;
+    cfg.boost = cfg.amp_up = cfg.amp_down = 1.0f;
+    cfg.lb = -1.0f;
+    cfg.ub = 1.0f;
+    cfg.max_generations = 1;
+    cfg.precision = precision;
+    Derived dv;
+    mgfwa_status r = derive(&cfg, problem, &dv);
+    if (r != MGFWA_OK) return r;
+    const Net &n0 = dv.net;
+    if (rows < 0 || (rows > 0 && (!w || !out))) return fail(MGFWA_EINVAL, "bad rows/buffers");
+    if (ld < dv.s.D || ld % 4 != 0 || reinterpret_cast<uintptr_t>(w) % 16 != 0)
+        return fail(MGFWA_EINVAL, "ld must be >= D and a multiple of 4; w 16-byte aligned");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    int lds_max = 0, num_cu = 0;
+    HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    HIP_TRY(hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    Net net = n0;
+    net.lds_max = lds_max - 256;
+    net.num_cu = num_cu > 0 ? num_cu : 1;
+    // scratch layout: packed samples, targets or labels, then per chunk of rows
+    // the partial sums (and the wide kernel's packed rows)
+    const size_t es = net.bf16 ? 2 : 4;
+    const int outw = net.fo[net.nl - 1];
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, ALIGN);
+        return o;
+    };
+    const size_t oX = take(net.wide ? 0 : (size_t)net.S_pad * net.in_pad * es);
+    const size_t oXw = take(net.wide ? (size_t)net.S_pad * wide_kp(net) * es : 0);
+    const size_t oY = take(net.loss == MGFWA_LOSS_MSE ? (size_t)net.S_pad * outw * 4 : 0);
+    const size_t oL = take(net.loss == MGFWA_LOSS_CE ? (size_t)net.S_pad * 4 : 0);
+    const size_t fixed = off;
+    const size_t per_row = net.wide ? wide_row_bytes(net) + (size_t)(net.S_pad / 256) * 4
+                                    : (size_t)fit_max_bpr() * 4;
+    const size_t cap = MGFWA_NOALLOC_SCRATCH_BYTES;
+    if (fixed + per_row + 2 * ALIGN > cap)
+        return fail(MGFWA_EINVAL, "problem too large for the %zu-byte no-allocation scratch "
+                                  "(packed samples need %zu bytes, one row %zu)", cap, fixed, per_row);
+    // rows per launch: what fits, and no more than mgfwa_evaluate takes at once
+    const int chunk = (int)std::min<size_t>((cap - fixed - 2 * ALIGN) / per_row, 1024);
+    const size_t oP = take((size_t)chunk * (net.wide ? (size_t)(net.S_pad / 256) * 4
+                                                     : (size_t)fit_max_bpr() * 4));
+    const size_t oW = take(net.wide ? (size_t)chunk * wide_row_bytes(net) : 0);
+    if (off > cap) return fail(MGFWA_EINVAL, "internal: no-allocation scratch layout overflows");
+    if (rows == 0) return MGFWA_OK;
+    char *base = nullptr;
+    r = scratch_address(dev, &base);
+    if (r != MGFWA_OK) return r;
+    if (net.wide) {
+        if (wide_lds_bytes(net) > lds_max - 64)
+            return fail(MGFWA_EUNSUPPORTED, "device LDS too small for the wide fitness kernel");
+        HIP_TRY(wide_prepare(net));
+    }
+    DevState d{};
+    d.Xp = !net.wide && !net.bf16 ? at<float>(base, oX) : nullptr;
+    d.Xb = !net.wide && net.bf16 ? at<uint16_t>(base, oX) : nullptr;
+    d.Xw = net.wide ? at<char>(base, oXw) : nullptr;
+    d.Ypad = net.loss == MGFWA_LOSS_MSE ? at<float>(base, oY) : nullptr;
+    d.Lpad = net.loss == MGFWA_LOSS_CE ? at<int32_t>(base, oL) : nullptr;
+    d.partial = at<float>(base, oP);
+    d.Wpack = net.wide ? at<char>(base, oW) : nullptr;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    // the array keeps the previous call's contents: every byte a launch reads is
+    // rewritten here first (samples, targets, labels and their padding by the
+    // packing kernels; packed rows and partial sums by the fitness launch)
+    HIP_TRY(launch_pack_problem(net, problem->x_dev, problem->y_dev, problem->labels_dev, d, st));
+    if (net.wide) HIP_TRY(launch_pack_wide_x(net, problem->x_dev, d.Xw, st));
+    for (int r0 = 0; r0 < rows; r0 += chunk) {
+        const int nr = std::min(chunk, rows - r0);
+        const float *wr = w + (size_t)r0 * ld;
+        if (net.wide) {
+            HIP_TRY(launch_fitness_wide(net, d, wr, (size_t)ld, nr, kFlat, out + r0, st));
+        } else {
+            FitPlan plan{};
+            if (!fit_select(net, nr, &plan))
+                return fail(MGFWA_EUNSUPPORTED, "no compiled fitness kernel covers this MLP shape");
+            HIP_TRY(fit_prepare(plan));
+            HIP_TRY(launch_fitness(net, plan, d, wr, (size_t)ld, nr, kFlat, out + r0, st));
+        }
+    }
+    return MGFWA_OK;
+}
+
 // ---- autotuning ------------------------------------------------------------
 namespace {
 

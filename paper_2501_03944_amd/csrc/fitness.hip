@@ -55,8 +55,9 @@ __global__ __launch_bounds__(256) void k_fit_finalize_group(GroupTable t, int wh
                   group_block(t, j, blockIdx.x));
 }
 
-// Pack the problem data: X zero-padded to [S_pad][in_pad] (FP32 or bf16 RNE),
-// MSE targets to [S_pad][out], labels to [S_pad] (-1 on padding).
+// Pack the problem data: X zero-padded to [S_pad][in_pad] (FP32 or bf16 RNE;
+// skipped when both X destinations are null), MSE targets to [S_pad][out],
+// labels to [S_pad] (-1 on padding).
 __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ x, const float *__restrict__ y,
                                               const int32_t *__restrict__ lab, int S, int S_pad,
                                               int in, int in_pad, int out, int bf16,
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ x, const
 {
     const size_t tid = (size_t)blockIdx.x * 256 + threadIdx.x;
     const size_t nx = (size_t)S_pad * in_pad;
-    if (tid < nx) {
+    if (tid < nx && (Xb || Xp)) {   // (the wide kernel packs its samples itself)
         const int s = (int)(tid / in_pad), k = (int)(tid % in_pad);
         const float v = (s < S && k < in) ? x[(size_t)s * in + k] : 0.0f;
         if (bf16) Xb[tid] = __builtin_bit_cast(uint16_t, (__bf16)v);

@@ -117,6 +117,8 @@ def lib() -> C.CDLL:
     L.mgfwa_ask.argtypes = [C.c_void_p, P(C.c_void_p), P(C.c_int), P(C.c_int)]
     L.mgfwa_tell.argtypes = [C.c_void_p, C.c_void_p]
     L.mgfwa_evaluate.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+    L.mgfwa_evaluate_noalloc.argtypes = [P(mgfwa_problem), C.c_int, C.c_void_p, C.c_int, C.c_int,
+                                         C.c_void_p, C.c_void_p]
     L.mgfwa_state.argtypes = [C.c_void_p, P(mgfwa_state_info)]
     L.mgfwa_set_timing.argtypes = [C.c_void_p, C.c_int]
     L.mgfwa_timing.argtypes = [C.c_void_p, P(mgfwa_timing_info)]
@@ -143,7 +145,7 @@ def lib() -> C.CDLL:
     L.mgfwa_server_destroy.argtypes = [C.c_void_p]
     L.mgfwa_server_destroy.restype = None
     for name in ("mgfwa_init", "mgfwa_step", "mgfwa_best", "mgfwa_best_all", "mgfwa_ask",
-                 "mgfwa_tell", "mgfwa_evaluate", "mgfwa_state",
+                 "mgfwa_tell", "mgfwa_evaluate", "mgfwa_evaluate_noalloc", "mgfwa_state",
                  "mgfwa_set_timing",
                  "mgfwa_timing", "mgfwa_autotune", "mgfwa_fit_plan", "mgfwa_fit_candidates",
                  "mgfwa_set_fit_plan", "mgfwa_batch_create",
@@ -248,6 +250,12 @@ def mgfwa_tell(ctx, fitness_ptr: int) -> None:
 
 def mgfwa_evaluate(ctx, w_ptr: int, rows: int, ld: int, out_ptr: int) -> None:
     _check(lib().mgfwa_evaluate(ctx, C.c_void_p(w_ptr), int(rows), int(ld), C.c_void_p(out_ptr)))
+
+
+def mgfwa_evaluate_noalloc(problem: mgfwa_problem, precision: int, w_ptr: int, rows: int,
+                           ld: int, out_ptr: int, stream: int) -> None:
+    _check(lib().mgfwa_evaluate_noalloc(C.byref(problem), int(precision), w_ptr, rows, ld,
+                                        out_ptr, stream))
 
 
 def mgfwa_state(ctx) -> mgfwa_state_info:
