@@ -21,10 +21,11 @@ LIB = os.path.join(HERE, "libmgfwa.so")
 ARCH = os.environ.get("MGFWA_OFFLOAD_ARCH", "gfx950")
 
 # the wide fitness instances take the longest: start them first
-SOURCES = ["fit_l4_wide_f32.hip", "fit_l4_wide_bf16.hip", "fit_l2_wide.hip", "fit_l3_wide_f32.hip",
-           "fit_l3_wide_bf16.hip", "fit_l4_f32.hip", "fit_l4_bf16.hip", "fit_l3.hip", "fit_std.hip",
-           "fit_l2.hip", "fit_l1.hip", "fit_wide.hip", "fitness.hip", "capi.hip", "spark.hip",
-           "guide.hip", "select.hip", "server.hip", "net_input.hip"]
+SOURCES = ["fit_l4_wide_f32.hip", "fit_l4_wide_bf16.hip", "fit_lds_bf16.hip", "fit_lds_f32.hip",
+           "fit_l2_wide.hip", "fit_l3_wide_f32.hip", "fit_l3_wide_bf16.hip", "fit_l4_f32.hip",
+           "fit_l4_bf16.hip", "fit_l3.hip", "fit_std.hip", "fit_l2.hip", "fit_l1.hip",
+           "fit_wide.hip", "fitness.hip", "capi.hip", "spark.hip", "guide.hip", "select.hip",
+           "server.hip", "net_input.hip"]
 HEADERS = ["device_common.h", "internal.h", "fit_kernel.h", "fit_wide.h"]
 
 FLAGS = [

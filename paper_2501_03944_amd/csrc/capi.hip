@@ -1274,6 +1274,7 @@ struct mgfwa_batch {
     hipGraphExec_t gexec = nullptr;
     std::vector<int> grouped, solo;          // jobs run by grouped launches / as branches
     std::vector<JobDesc> desc;               // host copies of the grouped jobs' descriptors
+    std::vector<hipStream_t> fit_branch;     // capture branches of the grouped fitness launches
 };
 
 void mgfwa::group_table(const JobDesc *const *jobs, const dim3 *grid, int n, GroupTable *t)
@@ -1285,7 +1286,7 @@ void mgfwa::group_table(const JobDesc *const *jobs, const dim3 *grid, int n, Gro
         t->gx[i] = (int)grid[i].x;
         t->gy[i] = (int)grid[i].y;
         t->job[i] = jobs[i];
-        acc += (int)(grid[i].x * grid[i].y);
+        acc += (int)((grid[i].x * grid[i].y + GROUP_ALIGN - 1) / GROUP_ALIGN * GROUP_ALIGN);
     }
     t->start[n] = acc;
 }
@@ -1293,6 +1294,7 @@ void mgfwa::group_table(const JobDesc *const *jobs, const dim3 *grid, int n, Gro
 namespace {
 
 constexpr int MAX_BRANCHES = 16;
+constexpr int MAX_FIT_BRANCHES = 8;   // parallel grouped fitness launches (kernel instances)
 
 // Jobs whose whole generation runs as grouped launches: weights problems on the
 // register-chain kernels in the default order.  (The wide kernel is persistent
@@ -1357,8 +1359,11 @@ mgfwa_status group_run(mgfwa_batch *b, Take take, Grid grid, Launch launch)
     return MGFWA_OK;
 }
 
+hipEvent_t batch_event(mgfwa_batch *b);
+
 // Fitness launch `which` of the grouped jobs: one grouped launch per kernel
-// instance, then one grouped finalisation.
+// instance, the instances on parallel branches of the graph (they touch
+// different jobs), then one grouped finalisation.
 mgfwa_status group_fitness(mgfwa_batch *b, int which, bool (*take)(const mgfwa_ctx *),
                            hipStream_t st)
 {
@@ -1369,7 +1374,17 @@ mgfwa_status group_fitness(mgfwa_batch *b, int which, bool (*take)(const mgfwa_c
         const void *k = job_plan(c, which).gkernel;
         if (std::find(kernels.begin(), kernels.end(), k) == kernels.end()) kernels.push_back(k);
     }
-    for (const void *k : kernels) {
+    const int nbr = std::min((int)kernels.size(), (int)b->fit_branch.size());
+    hipEvent_t fork = nullptr;
+    if (nbr > 1) {
+        fork = batch_event(b);
+        if (!fork) return fail(MGFWA_EHIP, "hipEventCreate failed");
+        HIP_TRY(hipEventRecord(fork, st));
+        for (int i = 0; i < nbr; ++i) HIP_TRY(hipStreamWaitEvent(b->fit_branch[i], fork, 0));
+    }
+    for (size_t ik = 0; ik < kernels.size(); ++ik) {
+        const void *k = kernels[ik];
+        hipStream_t ks = nbr > 1 ? b->fit_branch[ik % nbr] : st;
         int lds = 0, nw = 0;
         for (int i : b->grouped) {
             const mgfwa_ctx *c = b->jobs[i];
@@ -1382,8 +1397,14 @@ mgfwa_status group_fitness(mgfwa_batch *b, int which, bool (*take)(const mgfwa_c
             [&](const mgfwa_ctx *c) {
                 return dim3((unsigned)(job_fit_rows(c, which) * job_plan(c, which).bpr));
             },
-            [&](const GroupTable &t) { return launch_fitness_group(t, k, nw, lds, which, st); });
+            [&](const GroupTable &t) { return launch_fitness_group(t, k, nw, lds, which, ks); });
         if (r) return r;
+    }
+    for (int i = 0; i < nbr && nbr > 1; ++i) {
+        hipEvent_t join = batch_event(b);
+        if (!join) return fail(MGFWA_EHIP, "hipEventCreate failed");
+        HIP_TRY(hipEventRecord(join, b->fit_branch[i]));
+        HIP_TRY(hipStreamWaitEvent(st, join, 0));
     }
     return group_run(
         b, take, [&](const mgfwa_ctx *c) { return dim3((unsigned)((job_fit_rows(c, which) + 255) / 256)); },
@@ -1446,6 +1467,11 @@ mgfwa_status group_setup(mgfwa_batch *b)
 {
     for (int i = 0; i < (int)b->jobs.size(); ++i)
         (groupable(b->jobs[i]) ? b->grouped : b->solo).push_back(i);
+    for (int i = 0; i < MAX_FIT_BRANCHES && !b->grouped.empty(); ++i) {
+        hipStream_t st = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        b->fit_branch.push_back(st);
+    }
     b->desc.resize(b->grouped.size());
     for (size_t k = 0; k < b->grouped.size(); ++k) {
         mgfwa_ctx *c = b->jobs[b->grouped[k]];
@@ -1654,6 +1680,7 @@ void mgfwa_batch_destroy(mgfwa_batch *b)
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     for (hipStream_t st : b->branch) (void)hipStreamDestroy(st);
+    for (hipStream_t st : b->fit_branch) (void)hipStreamDestroy(st);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : b->job_ev) (void)hipEventDestroy(e);

@@ -118,12 +118,15 @@ typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
 // ReLU of eight BF16 values as packed 16-bit integer maxima against zero: a
 // non-negative BF16 is a non-negative integer, a negative one (or -0) a negative
 // integer.  Rounding to BF16 keeps the sign, so this equals ReLU before rounding.
+// Written with the compiler's element-wise maximum, not as inline assembly: the
+// result feeds a matrix-core operand, and the compiler inserts the wait states
+// between a vector write and a matrix-core read only for instructions it
+// generates itself.
+typedef short shortx8 __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ bf16x8 relu_bf16x8(bf16x8 v)
 {
-    uintx4 u = __builtin_bit_cast(uintx4, v);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) asm("v_pk_max_i16 %0, %1, 0" : "=v"(u[e]) : "v"(u[e]));
-    return __builtin_bit_cast(bf16x8, u);
+    const shortx8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+    return __builtin_bit_cast(bf16x8, __builtin_elementwise_max(__builtin_bit_cast(shortx8, v), zero));
 }
 
 __device__ __forceinline__ bf16x8 to_bf16x8(floatx4 lo, floatx4 hi)
@@ -713,15 +716,19 @@ __global__ __launch_bounds__(NW * 64) void k_fit(FitArgs a)
     fit_body<BF, WL, NW, P, ACT, R1, R2, R3, R4, SCHED>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
-// The same kernel over the fitness launch `which` of many jobs that share it:
-// grouped block ids are spread over the XCDs as in a single launch, then each
-// block runs the block it would have been in its job's own launch.
+// The same kernel over the fitness launch `which` of many jobs that share it.
+// A job's range of grouped blocks starts on XCD 0, so its blocks take the XCD
+// remap of its own launch and each runs the block it would have run there.
 template <bool BF, bool WL, int NW, int P, int ACT, int R1, int R2, int R3, int R4, int SCHED = 1>
 __global__ __launch_bounds__(NW * 64) void k_fit_group(GroupTable t, int which)
 {
-    const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int j = group_job(t, bid);
-    fit_body<BF, WL, NW, P, ACT, R1, R2, R3, R4, SCHED>(t.job[j]->fit[which].a, bid - t.start[j]);
+    const int j = group_job(t, blockIdx.x);
+    const int local = blockIdx.x - t.start[j], n = t.gx[j] * t.gy[j];
+    if (local >= n) return;   // padding
+    // a private copy: read through a pointer into global memory, the arguments
+    // would be reloaded after every store the body makes
+    const FitArgs a = t.job[j]->fit[which].a;
+    fit_body<BF, WL, NW, P, ACT, R1, R2, R3, R4, SCHED>(a, xcd_remap(local, n));
 }
 
 // One compiled fitness kernel: precision, weight source, wavefronts per block,

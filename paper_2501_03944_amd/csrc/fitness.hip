@@ -20,6 +20,8 @@ const KernelEntry *table_l4_f32(int *n);
 const KernelEntry *table_l4_bf16(int *n);
 const KernelEntry *table_l4_wide_f32(int *n);
 const KernelEntry *table_l4_wide_bf16(int *n);
+const KernelEntry *table_lds_bf16(int *n);
+const KernelEntry *table_lds_f32(int *n);
 }  // namespace fit
 
 namespace {
@@ -50,9 +52,11 @@ __global__ __launch_bounds__(256) void k_fit_finalize(const float *__restrict__ 
 __global__ __launch_bounds__(256) void k_fit_finalize_group(GroupTable t, int which)
 {
     const int j = group_job(t, blockIdx.x);
-    const FitLaunch &f = t.job[j]->fit[which];
+    Blk gb;
+    if (!group_block(t, j, blockIdx.x, &gb)) return;   // padding
+    const FitLaunch f = t.job[j]->fit[which];
     finalize_body(f.a.partial, f.a.rows, f.a.bpr, f.inv_norm, f.map, f.out,
-                  group_block(t, j, blockIdx.x));
+                  gb);
 }
 
 // Pack the problem data: X zero-padded to [S_pad][in_pad] (FP32 or bf16 RNE;
@@ -82,7 +86,7 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ x, const
 const KernelEntry *(*const kTables[])(int *) = {
     table_std,         table_l1,          table_l2,       table_l2_wide,     table_l3,
     table_l3_wide_f32, table_l3_wide_bf16, table_l4_f32,  table_l4_bf16,     table_l4_wide_f32,
-    table_l4_wide_bf16,
+    table_l4_wide_bf16, table_lds_bf16, table_lds_f32,
 };
 
 }  // namespace

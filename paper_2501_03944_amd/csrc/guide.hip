@@ -92,10 +92,15 @@ __global__ __launch_bounds__(TPB) void k_rank_group(GroupTable t)
 {
     extern __shared__ uint32_t sh[];
     const int j = group_job(t, blockIdx.x);
-    const JobDesc &J = *t.job[j];
-    const Shape &s = J.s;
-    rank_body(J.d.Yc, s.C, s.lam, s.G, s.m, s.k, J.d.top, J.d.bottom, J.d.tie, J.d.ctrl, s.lag, sh,
-              group_block(t, j, blockIdx.x));
+    Blk gb;
+    if (!group_block(t, j, blockIdx.x, &gb)) return;   // padding
+    // private copies: read through a pointer into global memory, the
+    // arguments would be reloaded after every store the body makes
+    const Shape js = t.job[j]->s;
+    const DevState jd = t.job[j]->d;
+    const Shape &s = js;
+    rank_body(jd.Yc, s.C, s.lam, s.G, s.m, s.k, jd.top, jd.bottom, jd.tie, jd.ctrl, s.lag, sh,
+              gb);
 }
 
 // Groups of m <= 64 members: the calling wavefront ranks group gi (g = gi % G
@@ -279,14 +284,19 @@ __global__ __launch_bounds__(TPB) void k_guide(Shape s, DevState d)
 __global__ __launch_bounds__(TPB) void k_guide_group(GroupTable t)
 {
     const int j = group_job(t, blockIdx.x);
-    const JobDesc &J = *t.job[j];
-    const Blk b = group_block(t, j, blockIdx.x);
-    if (J.s.m <= 64) {
-        if (J.s.regen) guide_job<true, true>(J.s, J.d, b);
-        else guide_job<true, false>(J.s, J.d, b);
+    Blk gb;
+    if (!group_block(t, j, blockIdx.x, &gb)) return;   // padding
+    // private copies: read through a pointer into global memory, the
+    // arguments would be reloaded after every store the body makes
+    const Shape js = t.job[j]->s;
+    const DevState jd = t.job[j]->d;
+    const Blk b = gb;
+    if (js.m <= 64) {
+        if (js.regen) guide_job<true, true>(js, jd, b);
+        else guide_job<true, false>(js, jd, b);
     } else {
-        if (J.s.regen) guide_job<false, true>(J.s, J.d, b);
-        else guide_job<false, false>(J.s, J.d, b);
+        if (js.regen) guide_job<false, true>(js, jd, b);
+        else guide_job<false, false>(js, jd, b);
     }
 }
 

@@ -231,6 +231,11 @@ struct JobDesc {
 
 constexpr int GROUP_MAX = 64;   // jobs per grouped launch
 
+// Every job's range of grouped blocks starts at a multiple of 8 (padding blocks
+// exit at once), so block l of a job sits on XCD l % 8 as in its own launch: a
+// job's blocks are spread over the XCDs and its XCD-aware tile order holds.
+constexpr int GROUP_ALIGN = 8;
+
 struct GroupTable {
     int njobs;
     int start[GROUP_MAX + 1];          // first grouped block of job j; start[njobs] = total
@@ -250,10 +255,13 @@ __device__ __forceinline__ int group_job(const GroupTable &t, int bid)
     return lo;
 }
 
-__device__ __forceinline__ Blk group_block(const GroupTable &t, int j, int bid)
+// The job's own block for grouped block bid; false for a padding block.
+__device__ __forceinline__ bool group_block(const GroupTable &t, int j, int bid, Blk *b)
 {
     const int l = bid - t.start[j];
-    return Blk{l % t.gx[j], l / t.gx[j], t.gx[j], t.gy[j]};
+    if (l >= t.gx[j] * t.gy[j]) return false;
+    *b = Blk{l % t.gx[j], l / t.gx[j], t.gx[j], t.gy[j]};
+    return true;
 }
 
 // Host side: a grouped launch over jobs[0..n) whose own grids are grid[i].

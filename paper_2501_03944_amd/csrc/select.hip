@@ -344,28 +344,46 @@ __global__ void k_finish(int32_t *ctrl, int advance)
 __global__ __launch_bounds__(TPB) void k_select_group(GroupTable t)
 {
     const int j = group_job(t, blockIdx.x);
-    const JobDesc &J = *t.job[j];
-    select_body(J.s, J.d, J.s.recheck != 0, group_block(t, j, blockIdx.x));
+    Blk gb;
+    if (!group_block(t, j, blockIdx.x, &gb)) return;   // padding
+    // private copies: read through a pointer into global memory, the
+    // arguments would be reloaded after every store the body makes
+    const Shape js = t.job[j]->s;
+    const DevState jd = t.job[j]->d;
+    select_body(js, jd, js.recheck != 0, gb);
 }
 
 __global__ __launch_bounds__(TPB) void k_apply_group(GroupTable t)
 {
     const int j = group_job(t, blockIdx.x);
-    const JobDesc &J = *t.job[j];
-    apply_body(J.s, J.d, J.s.recheck != 0, group_block(t, j, blockIdx.x));
+    Blk gb;
+    if (!group_block(t, j, blockIdx.x, &gb)) return;   // padding
+    // private copies: read through a pointer into global memory, the
+    // arguments would be reloaded after every store the body makes
+    const Shape js = t.job[j]->s;
+    const DevState jd = t.job[j]->d;
+    apply_body(js, jd, js.recheck != 0, gb);
 }
 
 __global__ __launch_bounds__(TPB) void k_gather_best_group(GroupTable t)
 {
     const int j = group_job(t, blockIdx.x);
-    const JobDesc &J = *t.job[j];
-    gather_best_body(J.s, J.d, group_block(t, j, blockIdx.x));
+    Blk gb;
+    if (!group_block(t, j, blockIdx.x, &gb)) return;   // padding
+    // private copies: read through a pointer into global memory, the
+    // arguments would be reloaded after every store the body makes
+    const Shape js = t.job[j]->s;
+    const DevState jd = t.job[j]->d;
+    gather_best_body(js, jd, gb);
 }
 
 // one block per job (the solo launch has one block)
 __global__ void k_finish_group(GroupTable t)
 {
-    finish_body(t.job[group_job(t, blockIdx.x)]->d.ctrl, 1);
+    const int j = group_job(t, blockIdx.x);
+    Blk gb;
+    if (!group_block(t, j, blockIdx.x, &gb)) return;   // padding
+    finish_body(t.job[j]->d.ctrl, 1);
 }
 
 __global__ __launch_bounds__(TPB) void k_store_fitness(const float *__restrict__ in, int rows,

@@ -67,9 +67,14 @@ __global__ __launch_bounds__(TPB) void k_pop_range(const float *__restrict__ F, 
 __global__ __launch_bounds__(TPB) void k_pop_range_group(GroupTable t)
 {
     const int j = group_job(t, blockIdx.x);
-    const JobDesc &J = *t.job[j];
-    pop_range_body(J.d.F, J.s.N, J.s.B, J.s.Dp, J.d.lo, J.d.hi, J.d.ctrl,
-                   group_block(t, j, blockIdx.x));
+    Blk gb;
+    if (!group_block(t, j, blockIdx.x, &gb)) return;   // padding
+    // private copies: read through a pointer into global memory, the
+    // arguments would be reloaded after every store the body makes
+    const Shape js = t.job[j]->s;
+    const DevState jd = t.job[j]->d;
+    pop_range_body(jd.F, js.N, js.B, js.Dp, jd.lo, jd.hi, jd.ctrl,
+                   gb);
 }
 
 // Explosion spark j of firework f (row = f*lambda + j) for generation t+1:
@@ -160,12 +165,123 @@ __global__ __launch_bounds__(TPB) void k_explode(const float *__restrict__ F,
 __global__ __launch_bounds__(TPB) void k_explode_group(GroupTable t)
 {
     const int j = group_job(t, blockIdx.x);
-    const JobDesc &J = *t.job[j];
-    const Shape &s = J.s;
-    const DevState &d = J.d;
+    Blk gb;
+    if (!group_block(t, j, blockIdx.x, &gb)) return;   // padding
+    // private copies: read through a pointer into global memory, the
+    // arguments would be reloaded after every store the body makes
+    const Shape js = t.job[j]->s;
+    const DevState jd = t.job[j]->d;
+    const Shape &s = js;
+    const DevState &d = jd;
     explode_body<0>(d.F, d.A, d.SE, s.lam, s.BN * s.lam, s.D, s.Dp, s.key, s.box, d.ctrl, s.N,
                     s.map_range ? d.lo : nullptr, s.map_range ? d.hi : nullptr, WidePack{},
-                    group_block(t, j, blockIdx.x));
+                    gb);
+}
+
+// Explosion sparks written only as the wide fitness kernel's packed rows, in the
+// rows' own K-blocked order (the FP32 rows are not stored).  x-blocks below
+// `units`: a wavefront produces 16 rows x 32 columns of one K block of W1aug (b1
+// is column `in`), 8 consecutive columns per lane, and writes them as one
+// contiguous 1 KiB (BF16) or 2 KiB (FP32) segment; rows past the hidden width
+// and the zero columns past `in` are left to the initial zeroing except inside a
+// written segment.  The x-blocks from `units` on take the W2 and b2
+// coordinates, four per thread, placed one by one.  Values are those of
+// explosion_chunk, as in k_explode.
+constexpr int XP_ROWS = 64;   // W1aug rows per block (16 per wavefront)
+
+template <bool BF>
+__global__ __launch_bounds__(TPB) void k_explode_packed(const float *__restrict__ F,
+                                                        const float *__restrict__ A, int lam,
+                                                        int rows, int D, int Dp, uint2 key, Box box,
+                                                        const int32_t *__restrict__ ctrl, int N,
+                                                        const float *__restrict__ lo,
+                                                        const float *__restrict__ hi, WidePack wp,
+                                                        int units)
+{
+    if (ctrl[CTRL_DONE]) return;
+    const uint32_t tn = (uint32_t)ctrl[CTRL_GEN] + 1u;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nob = (wp.hid + XP_ROWS - 1) / XP_ROWS;       // 64-row blocks of hidden units
+    // W1 columns k..k+7 of a row start on a 4-coordinate chunk of the spark
+    const bool aligned = (wp.in & 3) == 0 && (wp.woff1 & 3) == 0;
+    const int woff2 = wp.boff1 + wp.hid;                      // W2, then b2, up to D
+    for (int row = blockIdx.y; row < rows; row += gridDim.y) {
+        const int gf = row / lam;
+        const float amp = A[gf];
+        const float4 *xrow = reinterpret_cast<const float4 *>(F + (size_t)gf * Dp);
+        const size_t pb = (size_t)(gf / N) * Dp;
+        const float *plo = lo ? lo + pb : nullptr, *phi = hi ? hi + pb : nullptr;
+        char *dst = wp.Wp + (size_t)row * wp.pr;
+        if ((int)blockIdx.x < units) {
+            const int kb = blockIdx.x / nob, ob = blockIdx.x - kb * nob;
+            const int o = ob * XP_ROWS + wave * 16 + (lane >> 2);
+            const int k0 = kb * 32 + 8 * (lane & 3);
+            if (o >= wp.hid) continue;
+            float v[8];
+            if (aligned && k0 + 8 <= wp.in) {
+                const int c0 = (wp.woff1 + o * wp.in + k0) >> 2;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const float4 x4 = xrow[c0 + h];
+                    const float x[4] = {x4.x, x4.y, x4.z, x4.w};
+                    float s4[4];
+                    explosion_chunk(x, amp, key, c0 + h, (uint32_t)row, tn, box, plo, phi, D, s4);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[4 * h + e] = s4[e];
+                }
+            } else {
+                // the K block holding b1, or unaligned rows: coordinate by coordinate
+                int cached = -1;
+                float s4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int k = k0 + e;
+                    const int j = k < wp.in ? wp.woff1 + o * wp.in + k : k == wp.in ? wp.boff1 + o : -1;
+                    if (j < 0) {
+                        v[e] = 0.0f;
+                        continue;
+                    }
+                    if ((j >> 2) != cached) {
+                        cached = j >> 2;
+                        const float4 x4 = xrow[cached];
+                        const float x[4] = {x4.x, x4.y, x4.z, x4.w};
+                        explosion_chunk(x, amp, key, cached, (uint32_t)row, tn, box, plo, phi, D, s4);
+                    }
+                    v[e] = s4[j & 3];
+                }
+            }
+            char *p = dst + wide_w1_offset(o, k0, BF ? 2 : 4);
+            if constexpr (BF) {
+                uint32_t h[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    h[e] = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[2 * e]) |
+                           ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[2 * e + 1]) << 16);
+                *reinterpret_cast<uint4 *>(p) = make_uint4(h[0], h[1], h[2], h[3]);
+            } else {
+                reinterpret_cast<float4 *>(p)[0] = make_float4(v[0], v[1], v[2], v[3]);
+                reinterpret_cast<float4 *>(p)[1] = make_float4(v[4], v[5], v[6], v[7]);
+            }
+        } else {
+            // W2 and b2: chunk c covers coordinates 4c..4c+3; those below woff2 (b1)
+            // belong to the W1aug blocks
+            const int c = (woff2 >> 2) + ((int)blockIdx.x - units) * TPB + threadIdx.x;
+            if (4 * c >= D) continue;
+            const float4 x4 = xrow[c];
+            const float x[4] = {x4.x, x4.y, x4.z, x4.w};
+            float s4[4];
+            explosion_chunk(x, amp, key, c, (uint32_t)row, tn, box, plo, phi, D, s4);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int j = 4 * c + e;
+                if (j < woff2 || j >= D) continue;
+                bool f32;
+                const size_t off = wide_pack_offset(wp, j, &f32);
+                if (BF && !f32) *reinterpret_cast<uint16_t *>(dst + off) = __builtin_bit_cast(uint16_t, (__bf16)s4[e]);
+                else *reinterpret_cast<float *>(dst + off) = s4[e];
+            }
+        }
+    }
 }
 
 // Blocks over (chunk range, rows); a block takes rows_per_block rows (strided by
@@ -223,6 +339,24 @@ hipError_t launch_explode(const Shape &s, const DevState &d, hipStream_t st, con
                           bool write_se)
 {
     const int rows = s.BN * s.lam;
+    if (wp && !write_se) {
+        // packed rows only, written in their own order
+        const int units = (wp->Kp / 32) * ((wp->hid + XP_ROWS - 1) / XP_ROWS);
+        const int woff2 = wp->boff1 + wp->hid;
+        const int tail = ((s.D - (woff2 & ~3)) / 4 + 1 + TPB - 1) / TPB;
+        const int bx = units + tail;
+        const int rpb = (long)bx * (rows / 8) >= 4096 ? 8 : 1;
+        const int ry = (rows + rpb - 1) / rpb;
+        const dim3 grid((unsigned)bx, ry < MAX_GRID_Y ? ry : MAX_GRID_Y);
+        const float *lo = s.map_range ? d.lo : nullptr, *hi = s.map_range ? d.hi : nullptr;
+        if (wp->bf16)
+            hipLaunchKernelGGL(k_explode_packed<true>, grid, dim3(TPB), 0, st, d.F, d.A, s.lam, rows,
+                               s.D, s.Dp, s.key, s.box, d.ctrl, s.N, lo, hi, *wp, units);
+        else
+            hipLaunchKernelGGL(k_explode_packed<false>, grid, dim3(TPB), 0, st, d.F, d.A, s.lam, rows,
+                               s.D, s.Dp, s.key, s.box, d.ctrl, s.N, lo, hi, *wp, units);
+        return hipGetLastError();
+    }
     const WidePack none{};
     const WidePack &w = wp ? *wp : none;
     auto *k = !wp ? &k_explode<0> : wp->bf16 ? &k_explode<2> : &k_explode<1>;

@@ -368,3 +368,36 @@ def test_wide_bf16_generation_fitness_from_explosion_packing(widths, loss, lag):
         print(f"gen {gen + 1} {widths} lag={lag}: max abs err {err.max():.3e}")
         assert np.all(err <= bound), f"generation {gen + 1}"
     g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("widths,map_range", [((40, 64, 5), False), ((95, 200, 10), False),
+                                              ((33, 48, 3), True)])
+def test_wide_explosion_packing_equals_packing_stored_sparks(widths, map_range, precision):
+    """The explosion writes the wide kernel's packed rows itself, in their own
+    order (unaligned input widths coordinate by coordinate).  Its generation's
+    explosion fitness equals bit for bit the fitness mgfwa_evaluate computes for
+    the same sparks (regenerated by the oracle, packed by the library's packing
+    kernel, same launch shape): the packed rows agree."""
+    torch, M = require_gpu()
+    wl = inputs.random_mlp_problem(widths, ("relu",), "ce", 300, seed=11)
+    N, lam = 3, 16
+    g = M.MGFWA(wl.widths, wl.acts, wl.loss, wl.x, wl.y, wl.labels, n_fireworks=N, n_sparks=lam,
+                n_guiding=2, seed=5, precision=precision, fit_path=WIDE, map_range=map_range)
+    assert not g.sparks_materialised
+    D, Dp = g.D, g.Dp
+    cfg = O.make_config(N=N, lam=lam, G=2, seed=5, T=100)
+    for gen in range(1, 3):
+        before = g.state_numpy()
+        g.step(1)
+        st = g.state_numpy()
+        lo = hi = None
+        if map_range:
+            lo, hi = O.population_range(before["F"][:, :D])
+        W = np.zeros((N * lam, Dp), np.float32)
+        for r in range(N * lam):
+            W[r, :D] = O.explosion_row(cfg, before["F"][r // lam, :D], before["A"][r // lam], r, gen,
+                                       lo, hi)
+        y = g.evaluate(torch.from_numpy(W).cuda()).cpu().numpy()
+        assert_bits(st["Yc"][:, :lam].ravel(), y, f"generation {gen} explosion fitness")
+    g.close()
