@@ -1407,7 +1407,8 @@ mgfwa_status group_fitness(mgfwa_batch *b, int which, bool (*take)(const mgfwa_c
         HIP_TRY(hipStreamWaitEvent(st, join, 0));
     }
     return group_run(
-        b, take, [&](const mgfwa_ctx *c) { return dim3((unsigned)((job_fit_rows(c, which) + 255) / 256)); },
+        b, take,
+        [&](const mgfwa_ctx *c) { return dim3((unsigned)((job_fit_rows(c, which) + 255) / 256)); },
         [&](const GroupTable &t) { return launch_finalize_group(t, which, st); });
 }
 

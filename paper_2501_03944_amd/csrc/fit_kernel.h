@@ -115,18 +115,32 @@ __device__ __forceinline__ floatx4 ldw4(const float *p, bool row_ok, int kbase, 
 
 typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
 
-// ReLU of eight BF16 values as packed 16-bit integer maxima against zero: a
-// non-negative BF16 is a non-negative integer, a negative one (or -0) a negative
-// integer.  Rounding to BF16 keeps the sign, so this equals ReLU before rounding.
-// Written with the compiler's element-wise maximum, not as inline assembly: the
-// result feeds a matrix-core operand, and the compiler inserts the wait states
-// between a vector write and a matrix-core read only for instructions it
-// generates itself.
-typedef short shortx8 __attribute__((ext_vector_type(8)));
-__device__ __forceinline__ bf16x8 relu_bf16x8(bf16x8 v)
+// ReLU of eight values as they are converted to BF16: each pair converted with
+// round to nearest even (which keeps the sign), then the packed 16-bit integer
+// maximum against zero (a non-negative BF16 is a non-negative integer, a
+// negative one or -0 a negative integer), so this is ReLU before or after
+// rounding alike.  Written with the compiler's vector conversion and
+// element-wise maximum: the result feeds a matrix-core operand, and the
+// compiler inserts the wait states between a vector write and a matrix-core read
+// only for instructions it generates itself (an inline-assembly maximum here
+// once let the multiply read stale operands).
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short shortx2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t relu_pk_bf16(float a, float b)
 {
-    const shortx8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
-    return __builtin_bit_cast(bf16x8, __builtin_elementwise_max(__builtin_bit_cast(shortx8, v), zero));
+    const floatx2 f = {a, b};
+    const shortx2 h = __builtin_bit_cast(shortx2, __builtin_convertvector(f, bf16x2));
+    const shortx2 zero = {0, 0};
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(h, zero));
+}
+
+__device__ __forceinline__ bf16x8 relu_to_bf16x8(floatx4 lo, floatx4 hi)
+{
+    const uintx4 u = {relu_pk_bf16(lo[0], lo[1]), relu_pk_bf16(lo[2], lo[3]),
+                      relu_pk_bf16(hi[0], hi[1]), relu_pk_bf16(hi[2], hi[3])};
+    return __builtin_bit_cast(bf16x8, u);
 }
 
 __device__ __forceinline__ bf16x8 to_bf16x8(floatx4 lo, floatx4 hi)
@@ -451,8 +465,8 @@ __device__ __forceinline__ void layer_h(const WView<BF, WL> &wv, const floatx4 (
             for (int p = 0; p < P; ++p) {
                 floatx4 hi = zero4();
                 if (2 * kb + 1 < RI) hi = in[p][(2 * kb + 1) < RI ? 2 * kb + 1 : 0];
-                bx[p] = to_bf16x8(in[p][2 * kb], hi);
-                if constexpr (FOLD) bx[p] = relu_bf16x8(bx[p]);
+                if constexpr (FOLD) bx[p] = relu_to_bf16x8(in[p][2 * kb], hi);
+                else bx[p] = to_bf16x8(in[p][2 * kb], hi);
             }
 #pragma unroll
             for (int rb = 0; rb < RO; ++rb) {

@@ -556,7 +556,7 @@ __device__ void wide_epilogue(const WideArgs &a, char *smem, int r, int col, int
             const bf16x8 afr = __builtin_bit_cast(bf16x8, w2.f[kb]);
 #pragma unroll
             for (int cb = 0; cb < 8; ++cb) {
-                const bf16x8 bfr = ACT == 1 ? relu_bf16x8(to_bf16x8(acc[2 * kb][cb], acc[2 * kb + 1][cb]))
+                const bf16x8 bfr = ACT == 1 ? relu_to_bf16x8(acc[2 * kb][cb], acc[2 * kb + 1][cb])
                                             : to_bf16x8(act4<ACT>(acc[2 * kb][cb]),
                                                         act4<ACT>(acc[2 * kb + 1][cb]));
                 z[cb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr, z[cb][0], 0, 0, 0);

@@ -217,8 +217,9 @@ __global__ __launch_bounds__(TPB) void k_explode_packed(const float *__restrict_
             const int o = ob * XP_ROWS + wave * 16 + (lane >> 2);
             const int k0 = kb * 32 + 8 * (lane & 3);
             if (o >= wp.hid) continue;
-            float v[8];
+            char *p = dst + wide_w1_offset(o, k0, BF ? 2 : 4);
             if (aligned && k0 + 8 <= wp.in) {
+                float v[8];
                 const int c0 = (wp.woff1 + o * wp.in + k0) >> 2;
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
@@ -229,38 +230,42 @@ __global__ __launch_bounds__(TPB) void k_explode_packed(const float *__restrict_
 #pragma unroll
                     for (int e = 0; e < 4; ++e) v[4 * h + e] = s4[e];
                 }
+                if constexpr (BF) {
+                    uint32_t h[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        h[e] = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[2 * e]) |
+                               ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[2 * e + 1]) << 16);
+                    *reinterpret_cast<uint4 *>(p) = make_uint4(h[0], h[1], h[2], h[3]);
+                } else {
+                    reinterpret_cast<float4 *>(p)[0] = make_float4(v[0], v[1], v[2], v[3]);
+                    reinterpret_cast<float4 *>(p)[1] = make_float4(v[4], v[5], v[6], v[7]);
+                }
             } else {
-                // the K block holding b1, or unaligned rows: coordinate by coordinate
+                // the K block holding b1, or unaligned rows: coordinate by
+                // coordinate (a rolled loop: rare, and it keeps registers low)
                 int cached = -1;
                 float s4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
+#pragma unroll 1
                 for (int e = 0; e < 8; ++e) {
                     const int k = k0 + e;
                     const int j = k < wp.in ? wp.woff1 + o * wp.in + k : k == wp.in ? wp.boff1 + o : -1;
-                    if (j < 0) {
-                        v[e] = 0.0f;
-                        continue;
+                    float val = 0.0f;
+                    if (j >= 0) {
+                        if ((j >> 2) != cached) {
+                            cached = j >> 2;
+                            const float4 x4 = xrow[cached];
+                            const float x[4] = {x4.x, x4.y, x4.z, x4.w};
+                            explosion_chunk(x, amp, key, cached, (uint32_t)row, tn, box, plo, phi, D, s4);
+                        }
+                        const int q = j & 3;
+                        val = q == 0 ? s4[0] : q == 1 ? s4[1] : q == 2 ? s4[2] : s4[3];
                     }
-                    if ((j >> 2) != cached) {
-                        cached = j >> 2;
-                        const float4 x4 = xrow[cached];
-                        const float x[4] = {x4.x, x4.y, x4.z, x4.w};
-                        explosion_chunk(x, amp, key, cached, (uint32_t)row, tn, box, plo, phi, D, s4);
-                    }
-                    v[e] = s4[j & 3];
+                    if constexpr (BF)
+                        reinterpret_cast<uint16_t *>(p)[e] = __builtin_bit_cast(uint16_t, (__bf16)val);
+                    else
+                        reinterpret_cast<float *>(p)[e] = val;
                 }
-            }
-            char *p = dst + wide_w1_offset(o, k0, BF ? 2 : 4);
-            if constexpr (BF) {
-                uint32_t h[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    h[e] = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[2 * e]) |
-                           ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[2 * e + 1]) << 16);
-                *reinterpret_cast<uint4 *>(p) = make_uint4(h[0], h[1], h[2], h[3]);
-            } else {
-                reinterpret_cast<float4 *>(p)[0] = make_float4(v[0], v[1], v[2], v[3]);
-                reinterpret_cast<float4 *>(p)[1] = make_float4(v[4], v[5], v[6], v[7]);
             }
         } else {
             // W2 and b2: chunk c covers coordinates 4c..4c+3; those below woff2 (b1)
@@ -271,14 +276,15 @@ __global__ __launch_bounds__(TPB) void k_explode_packed(const float *__restrict_
             const float x[4] = {x4.x, x4.y, x4.z, x4.w};
             float s4[4];
             explosion_chunk(x, amp, key, c, (uint32_t)row, tn, box, plo, phi, D, s4);
-#pragma unroll
+#pragma unroll 1
             for (int e = 0; e < 4; ++e) {
                 const int j = 4 * c + e;
                 if (j < woff2 || j >= D) continue;
                 bool f32;
                 const size_t off = wide_pack_offset(wp, j, &f32);
-                if (BF && !f32) *reinterpret_cast<uint16_t *>(dst + off) = __builtin_bit_cast(uint16_t, (__bf16)s4[e]);
-                else *reinterpret_cast<float *>(dst + off) = s4[e];
+                const float val = e == 0 ? s4[0] : e == 1 ? s4[1] : e == 2 ? s4[2] : s4[3];
+                if (BF && !f32) *reinterpret_cast<uint16_t *>(dst + off) = __builtin_bit_cast(uint16_t, (__bf16)val);
+                else *reinterpret_cast<float *>(dst + off) = val;
             }
         }
     }
