@@ -293,7 +293,7 @@ def kernel_roofline(wl, precision, fit_ms, workload_name):
     else:         # every spark's weights once (the wide kernel reads them packed in its
         # own precision), the samples once
         alg_bytes = rows * wl.dim * (es if wide else 4) + wl.n_samples * wl.widths[0] * es
-        kernel = ("k_fit_wide_pipe" if precision == "bf16" else "k_fit_wide") if wide else "k_fit"
+        kernel = ("k_fit_wide_pipe" if precision == "bf16" else "k_fit_wide32") if wide else "k_fit"
         kernel += " (explosion-spark fitness)"
     return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": traffic, "traffic_source": traffic_src,

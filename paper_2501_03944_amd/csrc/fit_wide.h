@@ -18,9 +18,12 @@
 //             multiplies, so loads, LDS reads and matrix work overlap; a step
 //             needs few other instructions (its look-ahead sources come from
 //             tile bases set once per tile), since with one wavefront per SIMD
-//             they take issue slots from the multiplies.  FP32 (k_fit_wide): a
-//             2-stage ring, loads issued one step ahead.  Past the end a step
-//             re-loads the last tile, so wait counts are constants;
+//             they take issue slots from the multiplies.  FP32 (k_fit_wide32):
+//             a 2-stage ring of 64 KiB steps and one barrier per step; the
+//             next step's loads are issued in the first quarter of a step's
+//             multiplies and each row block's fragment is read one row block
+//             ahead.  Past the last tile the look-ahead re-loads the last
+//             step (BF16: so its wait counts are constants);
 //  * swizzle: a 16-byte chunk c of tile row r lives at chunk c ^ s(r), with
 //             s(r) = (r >> 1) & 3 for 64-byte rows (BF16) and r & 7 for 128-byte
 //             rows (FP32).  A 16-byte LDS read serves eight lanes at a time,
@@ -84,12 +87,13 @@ struct WideCfg {
     static constexpr int RPL = 64 / NCH;                   // rows per wave load (1 KiB)
     static constexpr int TILEB = WT_M * ROWB;              // bytes of one operand tile
     static constexpr int STAGEB = 2 * TILEB;               // W tile + X tile
-    static constexpr int STAGES = BF ? 3 : 2;
+    static constexpr int STAGES = 2;                       // FP32 ring (BF16: PipeCfg)
     static constexpr int LOADS = STAGEB / 1024 / WT_NW;    // wave loads per wave per step
     static constexpr int ZX = STAGES * STAGEB;             // logits exchange area
     static constexpr int ZXB = WT_N * ZP * 4;              // logits of the tile's samples
     static constexpr int LDS = ZX + ZXB;
-    static constexpr int KMULT = BF ? WT_K : STAGES * WT_K;       // padded K is a multiple
+    // padded K is a multiple (FP32: an even step count, so every tile starts on stage 0)
+    static constexpr int KMULT = BF ? WT_K : STAGES * WT_K;
 };
 
 // BF16 software pipeline: a 4-stage ring; fragments of the next step are read
@@ -143,33 +147,6 @@ struct TileIter {
     }
 };
 
-// Issue this wave's loads of one K step (W and X tiles) into an LDS stage.
-template <bool BF>
-__device__ __forceinline__ void wide_issue(const WideArgs &a, char *stage, int r, int col, int kt,
-                                           int wave, int lane)
-{
-    using C = WideCfg<BF>;
-    // K-blocked operands: step kt of a tile is one contiguous 256-row block
-    const char *wrow = a.Wp + (size_t)r * a.pr + (size_t)kt * C::TILEB;
-    const char *xrow = a.Xw + ((size_t)col * a.nk + kt) * C::TILEB;
-    const uint32_t gpitch = C::ROWB;
-    const int lr = lane / C::NCH, pc = lane % C::NCH;
-#pragma unroll
-    for (int t = 0; t < C::LOADS; ++t) {
-        // wave loads alternate between the W tile and the X tile; the base is
-        // uniform and the lane offset 32-bit (a tile spans < 4 GiB), so the
-        // load takes a scalar base plus a vector offset
-        const int half = t & 1;
-        const int r0 = (wave * (C::LOADS / 2) + (t >> 1)) * C::RPL;
-        const int row = r0 + lr;
-        const int q = pc ^ wide_swz(row, C::NCH);
-        const uint32_t off = (uint32_t)row * gpitch + (uint32_t)q * 16u;
-        const char *src = (half ? xrow : wrow) + off;
-        char *dst = stage + half * C::TILEB + r0 * C::ROWB;
-        __builtin_amdgcn_global_load_lds(src, (lds_void_t *)dst, 16, 0, 0);
-    }
-}
-
 // Compiler-only fence: no memory access moves across it.
 __device__ __forceinline__ void cfence() { asm volatile("" ::: "memory"); }
 
@@ -179,19 +156,6 @@ __device__ __forceinline__ void lds_barrier()
 {
     cfence();
     __builtin_amdgcn_s_waitcnt(0xF | (3 << 14) | (7 << 4));   // lgkmcnt(0), others unconstrained
-    __builtin_amdgcn_s_barrier();
-    cfence();
-}
-
-// Wait until the current step's stage has landed: the loads of the STAGES-1
-// younger steps may still be in flight.
-template <bool BF>
-__device__ __forceinline__ void wait_stage()
-{
-    constexpr int n = (WideCfg<BF>::STAGES - 1) * WideCfg<BF>::LOADS;
-    static_assert(n < 64, "vmcnt holds at most 63");
-    cfence();
-    __builtin_amdgcn_s_waitcnt((n & 0xF) | ((n >> 4) << 14) | (7 << 4) | (15 << 8));
     __builtin_amdgcn_s_barrier();
     cfence();
 }
@@ -239,10 +203,11 @@ struct Look {
     int nmask;        // -1 while a next tile exists, else 0
 };
 
+template <bool BF = true>
 __device__ __forceinline__ void look_set(const WideArgs &a, const TileIter &it, int i, int ntiles,
                                          Look &lk)
 {
-    using C = WideCfg<true>;
+    using C = WideCfg<BF>;
     int r, col;
     it.tile(i, &r, &col);
     lk.wcur = a.Wp + (size_t)r * a.pr;
@@ -389,63 +354,6 @@ __device__ __forceinline__ void pipe_tile(const WideArgs &a, char *smem, const L
         pipe_step<P0>(a, smem, lk, kt + 1, qbase + kt + 1, L, acc, fa, fb);
     }
     if (kt < a.nk) pipe_step<1 - P0>(a, smem, lk, kt, qbase + kt, L, acc, fa, fb);
-}
-
-// MFMAs of one K step on the stage: acc[rb][cb] over this wave's quarter.
-template <bool BF>
-__device__ __forceinline__ void wide_mma(const char *stage, int nh, int sh, int n, int g,
-                                         floatx4 (&acc)[8][8])
-{
-    using C = WideCfg<BF>;
-    const char *wt = stage;
-    const char *xt = stage + C::TILEB;
-    if constexpr (BF) {
-        // all 16 fragment reads are issued before the first multiply, so the
-        // LDS latency is paid once per step (later reads land while earlier
-        // multiplies run); the scheduling barrier keeps the compiler from
-        // re-serialising them into one register set
-        bf16x8 bfr[8], afr[8];
-#pragma unroll
-        for (int cb = 0; cb < 8; ++cb) {
-            const int row = 128 * sh + 16 * cb + n;
-            bfr[cb] = *reinterpret_cast<const bf16x8 *>(xt + row * C::ROWB +
-                                                        ((g ^ wide_swz(row, 4)) << 4));
-        }
-#pragma unroll
-        for (int rb = 0; rb < 8; ++rb) {
-            const int row = 128 * nh + 16 * rb + n;
-            afr[rb] = *reinterpret_cast<const bf16x8 *>(wt + row * C::ROWB +
-                                                        ((g ^ wide_swz(row, 4)) << 4));
-        }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int rb = 0; rb < 8; ++rb)
-#pragma unroll
-            for (int cb = 0; cb < 8; ++cb) mfma_acc(acc[rb][cb], afr[rb], bfr[cb]);
-    } else {
-        // lane group g holds k = 16kk + 4g + v of the two 16-column halves kk
-#pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
-            floatx4 bfr[8];
-#pragma unroll
-            for (int cb = 0; cb < 8; ++cb) {
-                const int row = 128 * sh + 16 * cb + n;
-                bfr[cb] = *reinterpret_cast<const floatx4 *>(
-                    xt + row * C::ROWB + (((4 * kk + g) ^ wide_swz(row, 8)) << 4));
-            }
-#pragma unroll
-            for (int rb = 0; rb < 8; ++rb) {
-                const int row = 128 * nh + 16 * rb + n;
-                const floatx4 afr = *reinterpret_cast<const floatx4 *>(
-                    wt + row * C::ROWB + (((4 * kk + g) ^ wide_swz(row, 8)) << 4));
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-#pragma unroll
-                    for (int cb = 0; cb < 8; ++cb)
-                        mfma_acc(acc[rb][cb], afr[v], bfr[cb][v]);
-            }
-        }
-    }
 }
 
 // Layer-2 A fragments of this wave's hidden half, read from the packed row.
@@ -627,42 +535,162 @@ __device__ void wide_epilogue(const WideArgs &a, char *smem, int r, int col, int
     if (threadIdx.x == 0) a.partial[(size_t)r * a.ntn + col] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// One K step: issue the loads STAGES-1 steps ahead, wait for this step's
-// stage, multiply, release the stage.
-template <bool BF, int S>
-__device__ __forceinline__ void wide_step(const WideArgs &a, char *smem, const TileIter &it, int q,
-                                          int Q, int wave, int lane, int nh, int sh, int n, int g,
-                                          floatx4 (&acc)[8][8])
+// FP32 pipeline: a 2-stage ring of 32-column K steps (64 KiB each), one barrier
+// per step.  After it a step reads the first fragments of its stage, then runs
+// its 512 multiplies (halves kk = 0, 1 of the step's columns, each 8 row
+// blocks x 4 columns x 8 column blocks) while it reads every row block's A
+// fragment one row block ahead, the second half's B fragments during the first
+// half, and issues the next step's 16 loads into the other stage within the
+// first four row blocks, so they have most of a step (~6 us) to land.  Same
+// tiles, layout, multiply order and results as the two-barrier form it
+// replaces; the step's sources come from the tile bases (no divisions).
+struct Lane32 {
+    uint32_t goff;       // lane's byte offset inside a 1 KiB block of 8 rows (global side)
+    uint32_t aoff[2];    // LDS offset of the lane's A fragment of row block 0, half kk
+    uint32_t boff[2];    // same for the B fragments (X half of the stage)
+    int woff;            // byte offset of this wave's first 8-row block of a tile (uniform)
+};
+
+__device__ __forceinline__ Lane32 lane32(int wave, int lane, int nh, int sh)
 {
-    using C = WideCfg<BF>;
-    {
-        int qq = q + C::STAGES - 1;
-        qq = qq < Q ? qq : Q - 1;                 // past the end: re-load into the free stage
-        int r, col;
-        it.tile(qq / a.nk, &r, &col);
-        wide_issue<BF>(a, smem + ((S + C::STAGES - 1) % C::STAGES) * C::STAGEB, r, col, qq % a.nk,
-                       wave, lane);
+    using C = WideCfg<false>;
+    static_assert(C::NCH == 8 && C::RPL == 8, "128-byte rows, 8 rows per wave load");
+    const int n = lane & 15, g = lane >> 4;
+    const int lr = lane / C::NCH, pc = lane % C::NCH;
+    Lane32 L;
+    // a wave load covers rows r0..r0+7 with r0 a multiple of 8, so the swizzle
+    // term of a lane's row is lr; a fragment row 16 cb + n has term n & 7
+    L.goff = (uint32_t)(lr * C::ROWB + ((pc ^ lr) << 4));
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+        const uint32_t ch = (uint32_t)(((4 * kk + g) ^ (n & 7)) << 4);
+        L.aoff[kk] = (uint32_t)((128 * nh + n) * C::ROWB) + ch;
+        L.boff[kk] = (uint32_t)(C::TILEB + (128 * sh + n) * C::ROWB) + ch;
     }
-    wait_stage<BF>();
-    wide_mma<BF>(smem + S * C::STAGEB, nh, sh, n, g, acc);
-    lds_barrier();
+    L.woff = wave * (C::LOADS / 2) * C::RPL * C::ROWB;
+    return L;
 }
 
-// One round of STAGES consecutive K steps starting at step q0 (q0 % STAGES == 0).
-template <bool BF, int S = 0>
-__device__ __forceinline__ void wide_round(const WideArgs &a, char *smem, const TileIter &it,
-                                           int q0, int Q, int wave, int lane, int nh, int sh,
-                                           int n, int g, floatx4 (&acc)[8][8])
+// Wave load T (of 16) of a K step: loads 0-7 take this wave's eight 1 KiB
+// blocks of the W tile, 8-15 those of the X tile.  Blocks 0-3 and 4-7 of an
+// operand each share one address and one LDS base, the block being the
+// instruction's immediate offset (which must stay below 4 KiB).
+template <int T>
+__device__ __forceinline__ void issue32(const char *wsrc, const char *xsrc, char *stage, const Lane32 &L)
 {
-    wide_step<BF, S>(a, smem, it, q0 + S, Q, wave, lane, nh, sh, n, g, acc);
-    if constexpr (S + 1 < WideCfg<BF>::STAGES)
-        wide_round<BF, S + 1>(a, smem, it, q0, Q, wave, lane, nh, sh, n, g, acc);
+    using C = WideCfg<false>;
+    constexpr int half = T >> 3, blk = T & 7;
+    constexpr int hi = (blk >> 2) * 4096, lo = (blk & 3) * 1024;
+    const char *src = (half ? xsrc : wsrc) + L.woff + hi + L.goff;
+    char *dst = stage + half * C::TILEB + L.woff + hi;
+    __builtin_amdgcn_global_load_lds(src, (lds_void_t *)dst, 16, lo, 0);
 }
 
-template <bool BF, int ACT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_fit_wide(WideArgs a)
+template <int OFF>
+__device__ __forceinline__ floatx4 lds_read4_at(uint32_t addr)
 {
-    using C = WideCfg<BF>;
+    floatx4 v;
+    asm volatile("ds_read_b128 %0, %1 offset:%2" : "=v"(v) : "v"(addr), "i"(OFF));
+    return v;
+}
+
+// This wave's LDS reads have completed; the fragments passed through are tied
+// to the wait so that nothing uses them earlier.
+__device__ __forceinline__ void lgkm_wait1(floatx4 &a) { asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(a)); }
+
+__device__ __forceinline__ void lgkm_wait9(floatx4 &a, floatx4 (&b)[8])
+{
+    asm volatile("s_waitcnt lgkmcnt(0)"
+                 : "+v"(a), "+v"(b[0]), "+v"(b[1]), "+v"(b[2]), "+v"(b[3]), "+v"(b[4]), "+v"(b[5]),
+                   "+v"(b[6]), "+v"(b[7]));
+}
+
+template <int CB>
+__device__ __forceinline__ void read_b32(uint32_t addr, floatx4 (&b)[8])
+{
+    b[CB] = lds_read4_at<CB * 16 * WideCfg<false>::ROWB>(addr);
+    if constexpr (CB + 1 < 8) read_b32<CB + 1>(addr, b);
+}
+
+template <bool FIRST>
+__device__ __forceinline__ void mfma32(floatx4 &c, float a, float b)
+{
+    if constexpr (FIRST) asm("v_mfma_f32_16x16x4_f32 %0, %1, %2, 0" : "=a"(c) : "v"(a), "v"(b));
+    else mfma_acc(c, a, b);
+}
+
+// Row block RB of half KK of a step: read the next A fragment (row block RB+1,
+// or row block 0 of the second half), in the first half also two of the second
+// half's B fragments (row blocks 4-7) or four of the next step's loads (row
+// blocks 0-3), then the row block's 32 multiplies.  (A read may target the
+// registers of the A fragment that the multiplies just issued read: the matrix
+// core reads its A and B operands at issue; only its accumulator input has a
+// write-after-read hazard, and accumulators live in AGPRs nothing else writes.)
+template <int KK, int RB, bool FIRST>
+__device__ __forceinline__ void rb32(uint32_t st, const char *wsrc, const char *xsrc, char *fill,
+                                     const Lane32 &L, floatx4 (&acc)[8][8], floatx4 (&fa)[2],
+                                     const floatx4 (&bk)[8], floatx4 (&b1)[8])
+{
+    using C = WideCfg<false>;
+    constexpr int RB1 = RB + 1 < 8 ? RB + 1 : 0;
+    constexpr bool more = RB + 1 < 8 || KK == 0;
+    constexpr int J = 8 * KK + RB;              // A fragment J of the step lives in fa[J % 2]
+    if constexpr (more)
+        fa[(J + 1) % 2] = lds_read4_at<RB1 * 16 * C::ROWB>(st + L.aoff[RB + 1 < 8 ? KK : 1]);
+    if constexpr (KK == 0 && RB >= 4) {
+        constexpr int c0 = 2 * (RB - 4);
+        b1[c0] = lds_read4_at<c0 * 16 * C::ROWB>(st + L.boff[1]);
+        b1[c0 + 1] = lds_read4_at<(c0 + 1) * 16 * C::ROWB>(st + L.boff[1]);
+    }
+    if constexpr (KK == 0 && RB < 4) {
+        issue32<4 * RB>(wsrc, xsrc, fill, L);
+        issue32<4 * RB + 1>(wsrc, xsrc, fill, L);
+        issue32<4 * RB + 2>(wsrc, xsrc, fill, L);
+        issue32<4 * RB + 3>(wsrc, xsrc, fill, L);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const floatx4 a = fa[J % 2];
+#pragma unroll
+    for (int cb = 0; cb < 8; ++cb) mfma32<FIRST && KK == 0>(acc[RB][cb], a[0], bk[cb][0]);
+#pragma unroll
+    for (int v = 1; v < 4; ++v)
+#pragma unroll
+        for (int cb = 0; cb < 8; ++cb) mfma32<false>(acc[RB][cb], a[v], bk[cb][v]);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (KK == 0 && RB == 7) lgkm_wait9(fa[(J + 1) % 2], b1);
+    else if constexpr (more) lgkm_wait1(fa[(J + 1) % 2]);
+    if constexpr (RB + 1 < 8) rb32<KK, RB + 1, FIRST>(st, wsrc, xsrc, fill, L, acc, fa, bk, b1);
+}
+
+// K step kt of a tile (stage kt & 1; the step count per tile is even).
+template <bool FIRST>
+__device__ __forceinline__ void step32(const WideArgs &a, char *smem, const Look &lk, int kt,
+                                       const Lane32 &L, floatx4 (&acc)[8][8])
+{
+    using C = WideCfg<false>;
+    // this wave's loads of the stage have landed and its reads of the other
+    // stage are done; after the barrier, so are every wavefront's
+    cfence();
+    __builtin_amdgcn_s_waitcnt(7 << 4);                        // vmcnt(0) lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    cfence();
+    const bool wrap = kt + 1 >= a.nk;
+    const char *wsrc = wrap ? lk.wnext : lk.wcur + (size_t)(kt + 1) * C::TILEB;
+    const char *xsrc = wrap ? lk.xnext : lk.xcur + (size_t)(kt + 1) * C::TILEB;
+    char *fill = smem + ((kt + 1) & 1) * C::STAGEB;
+    const uint32_t st = (uint32_t)(uintptr_t)(lds_void_t *)(smem + (kt & 1) * C::STAGEB);
+    floatx4 fa[2], b0[8], b1[8];
+    read_b32<0>(st + L.boff[0], b0);
+    fa[0] = lds_read4_at<0>(st + L.aoff[0]);
+    lgkm_wait9(fa[0], b0);
+    rb32<0, 0, FIRST>(st, wsrc, xsrc, fill, L, acc, fa, b0, b1);
+    rb32<1, 0, FIRST>(st, wsrc, xsrc, fill, L, acc, fa, b1, b1);
+}
+
+template <int ACT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_fit_wide32(WideArgs a)
+{
+    using C = WideCfg<false>;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ float red[4];
     const int lane = threadIdx.x & 63;
@@ -678,42 +706,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     it.setup();
     const int ntiles = it.count();
     if (ntiles == 0) return;
-    const int Q = ntiles * a.nk;          // K steps of this block; nk is a multiple of STAGES
-    // prologue: the first STAGES-1 steps
-#pragma unroll
-    for (int s = 0; s < C::STAGES - 1; ++s) {
-        const int qq = s < Q ? s : Q - 1;
-        int r, col;
-        it.tile(qq / a.nk, &r, &col);
-        wide_issue<BF>(a, smem + s * C::STAGEB, r, col, qq % a.nk, wave, lane);
-    }
+    const Lane32 L = lane32(wave, lane, nh, sh);
+    Look lk;
+    look_set<false>(a, it, 0, ntiles, lk);
+    // prologue: step 0 of tile 0 into stage 0
+    issue32<0>(lk.wcur, lk.xcur, smem, L);
+    issue32<1>(lk.wcur, lk.xcur, smem, L);
+    issue32<2>(lk.wcur, lk.xcur, smem, L);
+    issue32<3>(lk.wcur, lk.xcur, smem, L);
+    issue32<4>(lk.wcur, lk.xcur, smem, L);
+    issue32<5>(lk.wcur, lk.xcur, smem, L);
+    issue32<6>(lk.wcur, lk.xcur, smem, L);
+    issue32<7>(lk.wcur, lk.xcur, smem, L);
+    issue32<8>(lk.wcur, lk.xcur, smem, L);
+    issue32<9>(lk.wcur, lk.xcur, smem, L);
+    issue32<10>(lk.wcur, lk.xcur, smem, L);
+    issue32<11>(lk.wcur, lk.xcur, smem, L);
+    issue32<12>(lk.wcur, lk.xcur, smem, L);
+    issue32<13>(lk.wcur, lk.xcur, smem, L);
+    issue32<14>(lk.wcur, lk.xcur, smem, L);
+    issue32<15>(lk.wcur, lk.xcur, smem, L);
     for (int i = 0; i < ntiles; ++i) {
         int r, col;
         it.tile(i, &r, &col);
+        if (i > 0) look_set<false>(a, it, i, ntiles, lk);
         floatx4 acc[8][8];
-#pragma unroll
-        for (int rb = 0; rb < 8; ++rb)
-#pragma unroll
-            for (int cb = 0; cb < 8; ++cb) acc[rb][cb] = zero4();
+        step32<true>(a, smem, lk, 0, L, acc);
+        // the epilogue's global inputs, fetched while the tile's K loop runs
+        // (after its first step: the next step's wait covers them)
+        W2Frag<false> w2;
+        w2_load<false>(a, r, nh, n, g, w2);
+        const int label = tile_label(a, col, wave, lane);
+        for (int kt = 1; kt < a.nk; ++kt) step32<false>(a, smem, lk, kt, L, acc);
         mfma_acc_sync(acc);
-        const int qbase = i * a.nk;
-        for (int kt0 = 0; kt0 + C::STAGES < a.nk; kt0 += C::STAGES)
-            wide_round<BF>(a, smem, it, qbase + kt0, Q, wave, lane, nh, sh, n, g, acc);
-        // last round of the tile; BF16 fetches the layer-2 weights while it runs
-        // (its tiles are short), FP32 after it (fewer live registers)
-        W2Frag<BF> w2;
-        if constexpr (BF) w2_load<BF>(a, r, nh, n, g, w2);
-        wide_round<BF>(a, smem, it, qbase + a.nk - C::STAGES, Q, wave, lane, nh, sh, n, g, acc);
-        if constexpr (!BF) w2_load<BF>(a, r, nh, n, g, w2);
-        mfma_acc_sync(acc);
-        wide_epilogue<BF, ACT>(a, smem, r, col, wave, lane, acc, w2, red,
-                               tile_label(a, col, wave, lane));
+        wide_epilogue<false, ACT>(a, smem, r, col, wave, lane, acc, w2, red, label);
     }
     __builtin_amdgcn_s_waitcnt(0);
 }
 
-// BF16 variant of k_fit_wide with the software pipeline above (same tiles,
-// layout, epilogue and results).
+// BF16 wide kernel with the software pipeline above (same tiles, layout and
+// epilogue as the FP32 kernel).
 template <int ACT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_fit_wide_pipe(WideArgs a)
 {

@@ -154,8 +154,8 @@ __global__ __launch_bounds__(256) void k_wide_finalize(const float *__restrict__
 // One instance per (precision, hidden activation): a run-time activation
 // switch over the 256 accumulators would push them out of registers.
 const void *const kWide[2][4] = {
-    {reinterpret_cast<const void *>(&k_fit_wide<false, 0>), reinterpret_cast<const void *>(&k_fit_wide<false, 1>),
-     reinterpret_cast<const void *>(&k_fit_wide<false, 2>), reinterpret_cast<const void *>(&k_fit_wide<false, 3>)},
+    {reinterpret_cast<const void *>(&k_fit_wide32<0>), reinterpret_cast<const void *>(&k_fit_wide32<1>),
+     reinterpret_cast<const void *>(&k_fit_wide32<2>), reinterpret_cast<const void *>(&k_fit_wide32<3>)},
     {reinterpret_cast<const void *>(&k_fit_wide_pipe<0>), reinterpret_cast<const void *>(&k_fit_wide_pipe<1>),
      reinterpret_cast<const void *>(&k_fit_wide_pipe<2>), reinterpret_cast<const void *>(&k_fit_wide_pipe<3>)},
 };
