@@ -536,14 +536,15 @@ __device__ void wide_epilogue(const WideArgs &a, char *smem, int r, int col, int
 }
 
 // FP32 pipeline: a 2-stage ring of 32-column K steps (64 KiB each), one barrier
-// per step.  After it a step reads the first fragments of its stage, then runs
-// its 512 multiplies (halves kk = 0, 1 of the step's columns, each 8 row
-// blocks x 4 columns x 8 column blocks) while it reads every row block's A
-// fragment one row block ahead, the second half's B fragments during the first
-// half, and issues the next step's 16 loads into the other stage within the
-// first four row blocks, so they have most of a step (~6 us) to land.  Same
-// tiles, layout, multiply order and results as the two-barrier form it
-// replaces; the step's sources come from the tile bases (no divisions).
+// per step.  A step runs its 512 multiplies (halves kk = 0, 1 of the step's
+// columns, each 8 row blocks x 4 columns x 8 column blocks) while it reads every
+// row block's A fragment one row block ahead and the second half's B fragments
+// during the first half, issues the next step's 16 loads into the other stage
+// within the first four row blocks (they have ~10 row blocks, ~4 us, to land),
+// and passes the barrier before its last row block, which reads the next step's
+// first fragments.  Same tiles, layout, multiply order and results as the
+// two-barrier form it replaces; the step's sources come from the tile bases
+// (no divisions).
 struct Lane32 {
     uint32_t goff;       // lane's byte offset inside a 1 KiB block of 8 rows (global side)
     uint32_t aoff[2];    // LDS offset of the lane's A fragment of row block 0, half kk
@@ -619,23 +620,37 @@ __device__ __forceinline__ void mfma32(floatx4 &c, float a, float b)
     else mfma_acc(c, a, b);
 }
 
+// Stage complete for every wavefront: this wave's loads have landed and its
+// LDS reads are done; after the barrier, so are every wavefront's.
+__device__ __forceinline__ void stage_barrier()
+{
+    cfence();
+    __builtin_amdgcn_s_waitcnt(7 << 4);                        // vmcnt(0) lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    cfence();
+}
+
 // Row block RB of half KK of a step: read the next A fragment (row block RB+1,
 // or row block 0 of the second half), in the first half also two of the second
 // half's B fragments (row blocks 4-7) or four of the next step's loads (row
-// blocks 0-3), then the row block's 32 multiplies.  (A read may target the
-// registers of the A fragment that the multiplies just issued read: the matrix
-// core reads its A and B operands at issue; only its accumulator input has a
-// write-after-read hazard, and accumulators live in AGPRs nothing else writes.)
+// blocks 0-3), then the row block's 32 multiplies.  After row block 6 of the
+// second half the step's last A fragment is in registers: the stage barrier
+// there publishes the next step's stage (its loads were issued in row blocks
+// 0-3), and row block 7 reads the next step's first fragments (B of its first
+// half, A of its row block 0) while it multiplies, so a step starts multiplying
+// at once.  (A read may target the registers of the A fragment that the
+// multiplies just issued read: the matrix core reads its A and B operands at
+// issue; only its accumulator input has a write-after-read hazard, and
+// accumulators live in AGPRs nothing else writes.)
 template <int KK, int RB, bool FIRST>
-__device__ __forceinline__ void rb32(uint32_t st, const char *wsrc, const char *xsrc, char *fill,
-                                     const Lane32 &L, floatx4 (&acc)[8][8], floatx4 (&fa)[2],
-                                     const floatx4 (&bk)[8], floatx4 (&b1)[8])
+__device__ __forceinline__ void rb32(uint32_t st, uint32_t stn, const char *wsrc, const char *xsrc,
+                                     char *fill, const Lane32 &L, floatx4 (&acc)[8][8],
+                                     floatx4 (&fa)[2], floatx4 (&b0)[8], floatx4 (&b1)[8])
 {
     using C = WideCfg<false>;
     constexpr int RB1 = RB + 1 < 8 ? RB + 1 : 0;
-    constexpr bool more = RB + 1 < 8 || KK == 0;
     constexpr int J = 8 * KK + RB;              // A fragment J of the step lives in fa[J % 2]
-    if constexpr (more)
+    if constexpr (J < 15)
         fa[(J + 1) % 2] = lds_read4_at<RB1 * 16 * C::ROWB>(st + L.aoff[RB + 1 < 8 ? KK : 1]);
     if constexpr (KK == 0 && RB >= 4) {
         constexpr int c0 = 2 * (RB - 4);
@@ -648,8 +663,13 @@ __device__ __forceinline__ void rb32(uint32_t st, const char *wsrc, const char *
         issue32<4 * RB + 2>(wsrc, xsrc, fill, L);
         issue32<4 * RB + 3>(wsrc, xsrc, fill, L);
     }
+    if constexpr (J == 15) {
+        read_b32<0>(stn + L.boff[0], b0);
+        fa[0] = lds_read4_at<0>(stn + L.aoff[0]);
+    }
     __builtin_amdgcn_sched_barrier(0);
     const floatx4 a = fa[J % 2];
+    floatx4 (&bk)[8] = KK == 0 ? b0 : b1;
 #pragma unroll
     for (int cb = 0; cb < 8; ++cb) mfma32<FIRST && KK == 0>(acc[RB][cb], a[0], bk[cb][0]);
 #pragma unroll
@@ -657,34 +677,37 @@ __device__ __forceinline__ void rb32(uint32_t st, const char *wsrc, const char *
 #pragma unroll
         for (int cb = 0; cb < 8; ++cb) mfma32<false>(acc[RB][cb], a[v], bk[cb][v]);
     __builtin_amdgcn_sched_barrier(0);
-    if constexpr (KK == 0 && RB == 7) lgkm_wait9(fa[(J + 1) % 2], b1);
-    else if constexpr (more) lgkm_wait1(fa[(J + 1) % 2]);
-    if constexpr (RB + 1 < 8) rb32<KK, RB + 1, FIRST>(st, wsrc, xsrc, fill, L, acc, fa, bk, b1);
+    if constexpr (J == 7) {
+        lgkm_wait9(fa[0], b1);
+    } else if constexpr (J == 14) {
+        lgkm_wait1(fa[1]);
+        stage_barrier();
+    } else if constexpr (J == 15) {
+        lgkm_wait9(fa[0], b0);
+    } else {
+        lgkm_wait1(fa[(J + 1) % 2]);
+    }
+    if constexpr (RB + 1 < 8) rb32<KK, RB + 1, FIRST>(st, stn, wsrc, xsrc, fill, L, acc, fa, b0, b1);
 }
 
-// K step kt of a tile (stage kt & 1; the step count per tile is even).
+// K step kt of a tile (stage kt & 1; the step count per tile is even).  On
+// entry the step's stage is complete for every wavefront and its first
+// fragments are in b0 and fa[0]; on exit the same holds for the next step
+// (the next tile's first step after a tile's last).
 template <bool FIRST>
 __device__ __forceinline__ void step32(const WideArgs &a, char *smem, const Look &lk, int kt,
-                                       const Lane32 &L, floatx4 (&acc)[8][8])
+                                       const Lane32 &L, floatx4 (&acc)[8][8], floatx4 (&fa)[2],
+                                       floatx4 (&b0)[8], floatx4 (&b1)[8])
 {
     using C = WideCfg<false>;
-    // this wave's loads of the stage have landed and its reads of the other
-    // stage are done; after the barrier, so are every wavefront's
-    cfence();
-    __builtin_amdgcn_s_waitcnt(7 << 4);                        // vmcnt(0) lgkmcnt(0)
-    __builtin_amdgcn_s_barrier();
-    cfence();
     const bool wrap = kt + 1 >= a.nk;
     const char *wsrc = wrap ? lk.wnext : lk.wcur + (size_t)(kt + 1) * C::TILEB;
     const char *xsrc = wrap ? lk.xnext : lk.xcur + (size_t)(kt + 1) * C::TILEB;
     char *fill = smem + ((kt + 1) & 1) * C::STAGEB;
     const uint32_t st = (uint32_t)(uintptr_t)(lds_void_t *)(smem + (kt & 1) * C::STAGEB);
-    floatx4 fa[2], b0[8], b1[8];
-    read_b32<0>(st + L.boff[0], b0);
-    fa[0] = lds_read4_at<0>(st + L.aoff[0]);
-    lgkm_wait9(fa[0], b0);
-    rb32<0, 0, FIRST>(st, wsrc, xsrc, fill, L, acc, fa, b0, b1);
-    rb32<1, 0, FIRST>(st, wsrc, xsrc, fill, L, acc, fa, b1, b1);
+    const uint32_t stn = (uint32_t)(uintptr_t)(lds_void_t *)fill;
+    rb32<0, 0, FIRST>(st, stn, wsrc, xsrc, fill, L, acc, fa, b0, b1);
+    rb32<1, 0, FIRST>(st, stn, wsrc, xsrc, fill, L, acc, fa, b0, b1);
 }
 
 template <int ACT>
@@ -726,18 +749,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     issue32<13>(lk.wcur, lk.xcur, smem, L);
     issue32<14>(lk.wcur, lk.xcur, smem, L);
     issue32<15>(lk.wcur, lk.xcur, smem, L);
+    stage_barrier();
+    floatx4 fa[2], b0[8], b1[8];
+    {
+        const uint32_t st0 = (uint32_t)(uintptr_t)(lds_void_t *)smem;
+        read_b32<0>(st0 + L.boff[0], b0);
+        fa[0] = lds_read4_at<0>(st0 + L.aoff[0]);
+        lgkm_wait9(fa[0], b0);
+    }
     for (int i = 0; i < ntiles; ++i) {
         int r, col;
         it.tile(i, &r, &col);
         if (i > 0) look_set<false>(a, it, i, ntiles, lk);
         floatx4 acc[8][8];
-        step32<true>(a, smem, lk, 0, L, acc);
+        step32<true>(a, smem, lk, 0, L, acc, fa, b0, b1);
         // the epilogue's global inputs, fetched while the tile's K loop runs
         // (after its first step: the next step's wait covers them)
         W2Frag<false> w2;
         w2_load<false>(a, r, nh, n, g, w2);
         const int label = tile_label(a, col, wave, lane);
-        for (int kt = 1; kt < a.nk; ++kt) step32<false>(a, smem, lk, kt, L, acc);
+        for (int kt = 1; kt < a.nk; ++kt) step32<false>(a, smem, lk, kt, L, acc, fa, b0, b1);
         mfma_acc_sync(acc);
         wide_epilogue<false, ACT>(a, smem, r, col, wave, lane, acc, w2, red, label);
     }
