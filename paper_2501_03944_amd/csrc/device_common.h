@@ -20,7 +20,9 @@ struct Box {
 // Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11).  Each round
 // takes the 64-bit products of counter words 0 and 2 with the two round
 // multipliers; the new counter is (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0) and
-// the key advances by the two Weyl increments between rounds.
+// the key advances by the two Weyl increments between rounds.  Each
+// three-way XOR is one gfx950 three-input bit operation (truth table 0x96),
+// so a round is two 32x32 -> 64-bit multiplies and two logic instructions.
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k)
 {
 #pragma unroll
@@ -33,7 +35,8 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k)
         const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
         const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
         const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
-        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+        c = make_uint4(__builtin_amdgcn_bitop3_b32(hi1, c.y, k.x, 0x96), lo1,
+                       __builtin_amdgcn_bitop3_b32(hi0, c.w, k.y, 0x96), lo0);
     }
     return c;
 }
