@@ -444,6 +444,30 @@ __device__ __forceinline__ int tile_label(const WideArgs &a, int col, int wave, 
     return (a.loss == 1 && s < a.S) ? a.lab[s] : 0;
 }
 
+// Sum of a float over the wavefront, exact in lane 0 (other lanes hold partial
+// sums), added in the order of an xor butterfly as lane 0 sees it: pairs and
+// quads by quad permutations, 8 and 16 lanes by rotations within each row of
+// 16 (lane j takes lane j+4, then j+8), then (row 0 + row 1) + (row 2 + row 3)
+// from the rows' first lanes.  All register-to-register: no LDS round trips.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL,
+                                                                 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float wave_sum_lane0(float v)
+{
+    v = v + dpp_mov<0xB1>(v);     // quad_perm [1,0,3,2]: lane j ^ 1
+    v = v + dpp_mov<0x4E>(v);     // quad_perm [2,3,0,1]: lane j ^ 2
+    v = v + dpp_mov<0x12C>(v);    // row_ror 12: lane (j + 4) mod 16
+    v = v + dpp_mov<0x128>(v);    // row_ror 8: lane (j + 8) mod 16
+    const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
+    const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
+    const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
+    return (v + r1) + (r2 + r3);
+}
+
 template <bool BF, int ACT>
 __device__ void wide_epilogue(const WideArgs &a, char *smem, int r, int col, int wave, int lane,
                               floatx4 (&acc)[8][8], const W2Frag<BF> &w2, float *red, int label,
@@ -527,9 +551,8 @@ __device__ void wide_epilogue(const WideArgs &a, char *smem, int r, int col, int
         }
         ls = sample_loss<BF>(a, s, label, zz);
     }
-    // fixed-order reduction: wavefront butterfly, then the four wavefronts in order
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) ls += __shfl_xor(ls, off);
+    // fixed-order reduction: the wavefront's sum, then the four wavefronts in order
+    ls = wave_sum_lane0(ls);
     if (lane == 0) red[wave] = ls;
     lds_barrier();
     if (threadIdx.x == 0) a.partial[(size_t)r * a.ntn + col] = (red[0] + red[1]) + (red[2] + red[3]);
