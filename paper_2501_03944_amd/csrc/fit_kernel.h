@@ -485,10 +485,17 @@ __device__ __forceinline__ void layer_h(const WView<BF, WL> &wv, const floatx4 (
 }
 
 // ---- bias, activation, loss ---------------------------------------------------
+// ReLU as a signed integer maximum against zero: a positive float is a positive
+// integer, a negative one and -0 negative integers, so this is z > 0 ? z : +0
+// for every non-NaN z in one instruction (the float maximum takes two: the
+// compiler quiets a possible signalling NaN first).
 template <int ACT>
 __device__ __forceinline__ float act_c(float z)
 {
-    if constexpr (ACT == 1) return z > 0.0f ? z : 0.0f;
+    if constexpr (ACT == 1) {
+        const int i = __builtin_bit_cast(int, z);
+        return __builtin_bit_cast(float, i > 0 ? i : 0);
+    }
     else if constexpr (ACT == 2) return tanhf(z);
     else if constexpr (ACT == 3) return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
     else return z;
