@@ -1542,11 +1542,19 @@ mgfwa_status batch_capture(mgfwa_batch *b)
     hipError_t e = hipEventRecord(fork, b->cap);
     for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamWaitEvent(b->branch[i], fork, 0);
     if (e != hipSuccess) r = fail(MGFWA_EHIP, "batch capture: %s", hipGetErrorString(e));
-    // jobs that cannot be grouped go round-robin over the branches (a branch
-    // runs its jobs in order); the grouped jobs' generation is one sequence of
-    // grouped launches on the capture stream, beside them
-    for (int i = 0; i < n && r == MGFWA_OK; ++i)
-        r = enqueue_generation(b->jobs[b->solo[i]], b->branch[i % nb], nullptr);
+    // branch jobs, largest first, each to the branch with the least work so far
+    // (a branch runs its jobs in order); the grouped jobs' generation is one
+    // sequence of grouped launches on the capture stream, beside them
+    std::vector<int> order(b->solo);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return job_flops(b->jobs[x]) > job_flops(b->jobs[y]);
+    });
+    std::vector<double> load(nb, 0.0);
+    for (size_t k = 0; k < order.size() && r == MGFWA_OK; ++k) {
+        const int br = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[br] += job_flops(b->jobs[order[k]]);
+        r = enqueue_generation(b->jobs[order[k]], b->branch[br], nullptr);
+    }
     if (r == MGFWA_OK && !b->grouped.empty()) r = enqueue_grouped(b, b->cap);
     for (int i = 0; i < nb && r == MGFWA_OK; ++i) {
         e = hipEventRecord(join[i], b->branch[i]);
