@@ -19,11 +19,13 @@
 //             needs few other instructions (its look-ahead sources come from
 //             tile bases set once per tile), since with one wavefront per SIMD
 //             they take issue slots from the multiplies.  FP32 (k_fit_wide32):
-//             a 2-stage ring of 64 KiB steps and one barrier per step; the
-//             next step's loads are issued in the first quarter of a step's
-//             multiplies and each row block's fragment is read one row block
-//             ahead.  Past the last tile the look-ahead re-loads the last
-//             step (BF16: so its wait counts are constants);
+//             a 2-stage ring of 64 KiB steps and one barrier per step, placed
+//             before the step's last row block; the next step's loads are
+//             issued in the first quarter of a step's multiplies, each row
+//             block's fragment is read one row block ahead and the last row
+//             block reads the next step's first fragments.  Past the last tile
+//             the look-ahead re-loads the last step (BF16: so its wait counts
+//             are constants);
 //  * swizzle: a 16-byte chunk c of tile row r lives at chunk c ^ s(r), with
 //             s(r) = (r >> 1) & 3 for 64-byte rows (BF16) and r & 7 for 128-byte
 //             rows (FP32).  A 16-byte LDS read serves eight lanes at a time,
@@ -37,8 +39,12 @@
 //             computes one sample's loss on its own; one partial per (spark,
 //             sample tile), reduced later in a fixed order;
 //  * schedule: blocks are persistent (one per CU); tile groups of GS sparks go
-//             to one XCD, whose blocks split the group's sample tiles, so a
-//             spark's weights are fetched from HBM into that XCD's L2 once.
+//             to one XCD, whose blocks split the group's sample tiles round by
+//             round (GS sparks x bx/GS sample tiles at a time), so a spark's rows
+//             are read by one XCD only, by its blocks at about the same time.
+//             A round's operand tiles (4.8 MB at 784-256-10) exceed the XCD's
+//             4 MB L2, so every round fetches them once past the L2 (mostly the
+//             sample tiles, from the Infinity Cache).
 //
 // Packed spark layout (written by k_pack_wide_rows, or by the explosion kernel
 // for explosion sparks; row pitch PR bytes):
