@@ -98,8 +98,7 @@ struct WideCfg {
     static constexpr int ZX = STAGES * STAGEB;             // logits exchange area
     static constexpr int ZXB = WT_N * ZP * 4;              // logits of the tile's samples
     static constexpr int LDS = ZX + ZXB;
-    // padded K is a multiple (FP32: an even step count, so every tile starts on stage 0)
-    static constexpr int KMULT = BF ? WT_K : STAGES * WT_K;
+    static constexpr int KMULT = WT_K;                     // padded K is a multiple
 };
 
 // BF16 software pipeline: a 4-stage ring; fragments of the next step are read
@@ -719,12 +718,13 @@ __device__ __forceinline__ void rb32(uint32_t st, uint32_t stn, const char *wsrc
     if constexpr (RB + 1 < 8) rb32<KK, RB + 1, FIRST>(st, stn, wsrc, xsrc, fill, L, acc, fa, b0, b1);
 }
 
-// K step kt of a tile (stage kt & 1; the step count per tile is even).  On
-// entry the step's stage is complete for every wavefront and its first
-// fragments are in b0 and fa[0]; on exit the same holds for the next step
-// (the next tile's first step after a tile's last).
+// K step kt of a tile, global step q of the block (stage q & 1: a tile with an
+// odd step count hands the other stage to the next).  On entry the step's
+// stage is complete for every wavefront and its first fragments are in b0 and
+// fa[0]; on exit the same holds for the next step (the next tile's first step
+// after a tile's last).
 template <bool FIRST>
-__device__ __forceinline__ void step32(const WideArgs &a, char *smem, const Look &lk, int kt,
+__device__ __forceinline__ void step32(const WideArgs &a, char *smem, const Look &lk, int kt, int q,
                                        const Lane32 &L, floatx4 (&acc)[8][8], floatx4 (&fa)[2],
                                        floatx4 (&b0)[8], floatx4 (&b1)[8])
 {
@@ -732,8 +732,8 @@ __device__ __forceinline__ void step32(const WideArgs &a, char *smem, const Look
     const bool wrap = kt + 1 >= a.nk;
     const char *wsrc = wrap ? lk.wnext : lk.wcur + (size_t)(kt + 1) * C::TILEB;
     const char *xsrc = wrap ? lk.xnext : lk.xcur + (size_t)(kt + 1) * C::TILEB;
-    char *fill = smem + ((kt + 1) & 1) * C::STAGEB;
-    const uint32_t st = (uint32_t)(uintptr_t)(lds_void_t *)(smem + (kt & 1) * C::STAGEB);
+    char *fill = smem + ((q + 1) & 1) * C::STAGEB;
+    const uint32_t st = (uint32_t)(uintptr_t)(lds_void_t *)(smem + (q & 1) * C::STAGEB);
     const uint32_t stn = (uint32_t)(uintptr_t)(lds_void_t *)fill;
     rb32<0, 0, FIRST>(st, stn, wsrc, xsrc, fill, L, acc, fa, b0, b1);
     rb32<1, 0, FIRST>(st, stn, wsrc, xsrc, fill, L, acc, fa, b0, b1);
@@ -791,13 +791,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         it.tile(i, &r, &col);
         if (i > 0) look_set<false>(a, it, i, ntiles, lk);
         floatx4 acc[8][8];
-        step32<true>(a, smem, lk, 0, L, acc, fa, b0, b1);
+        const int qbase = i * a.nk;
+        step32<true>(a, smem, lk, 0, qbase, L, acc, fa, b0, b1);
         // the epilogue's global inputs, fetched while the tile's K loop runs
         // (after its first step: the next step's wait covers them)
         W2Frag<false> w2;
         w2_load<false>(a, r, nh, n, g, w2);
         const int label = tile_label(a, col, wave, lane);
-        for (int kt = 1; kt < a.nk; ++kt) step32<false>(a, smem, lk, kt, L, acc, fa, b0, b1);
+        for (int kt = 1; kt < a.nk; ++kt) step32<false>(a, smem, lk, kt, qbase + kt, L, acc, fa, b0, b1);
         mfma_acc_sync(acc);
         wide_epilogue<false, ACT>(a, smem, r, col, wave, lane, acc, w2, red, label);
     }
