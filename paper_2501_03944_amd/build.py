@@ -39,6 +39,17 @@ FLAGS = [
 ]
 
 
+# Instance files whose kernels read the weights from global memory: their layer
+# loops (every (K block, row block) pair of a layer, fully unrolled so that the
+# activation tiles stay in registers) exceed the compiler's default size limit
+# for a requested full unroll; left partly rolled, the activation arrays are
+# indexed at run time and live in scratch memory.
+UNROLL_FLAGS = ["-mllvm", "-pragma-unroll-threshold=1000000"]
+GLOBAL_WEIGHT_SOURCES = {"fit_l1.hip", "fit_l2.hip", "fit_l2_wide.hip", "fit_l3.hip",
+                         "fit_l3_wide_bf16.hip", "fit_l3_wide_f32.hip", "fit_l4_bf16.hip",
+                         "fit_l4_f32.hip", "fit_l4_wide_bf16.hip", "fit_l4_wide_f32.hip"}
+
+
 def hipcc() -> str:
     p = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(p):
@@ -62,7 +73,8 @@ def _fresh(src: str) -> bool:
 
 def _compile(src: str, verbose: bool) -> str:
     obj = _obj(src)
-    cmd = [hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    extra = UNROLL_FLAGS if src in GLOBAL_WEIGHT_SOURCES else []
+    cmd = [hipcc(), *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

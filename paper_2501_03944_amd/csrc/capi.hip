@@ -1203,9 +1203,15 @@ void fill_plan_info(const mgfwa_ctx *c, const FitPlan &p, int rows, mgfwa_plan_i
 
 // Time every candidate plan for `rows` sparks of W on the context's stream and
 // keep the fastest; a shape seen before reuses its choice without timing.
-mgfwa_status tune_plan(mgfwa_ctx *c, int rows, const float *W, OutMap map, int reps, FitPlan *out)
+// check: the launch is the FP32 re-check of a BF16 run's winners (the FP32
+// network and sample buffers, results into the re-check's output).
+mgfwa_status tune_plan(mgfwa_ctx *c, int rows, const float *W, OutMap map, int reps, FitPlan *out,
+                       bool check = false)
 {
-    const std::string key = c->input ? tune_key_input(c->in, rows) : tune_key(c->net, rows);
+    const Net &net = check ? c->net32 : c->net;
+    const DevState &dv = check ? c->d32 : c->d;
+    float *res = check ? c->d.Ystar : c->d.Yc;
+    const std::string key = c->input ? tune_key_input(c->in, rows) : tune_key(net, rows);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
@@ -1216,7 +1222,8 @@ mgfwa_status tune_plan(mgfwa_ctx *c, int rows, const float *W, OutMap map, int r
         }
     }
     FitPlan cand[MAX_CANDIDATES];
-    const int n = tune_candidates(c, rows, cand, MAX_CANDIDATES);
+    const int n = check ? fit_candidates(net, rows, cand, MAX_CANDIDATES)
+                        : tune_candidates(c, rows, cand, MAX_CANDIDATES);
     if (n == 0) return fail(MGFWA_EUNSUPPORTED, "no compiled fitness kernel covers this MLP shape");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
@@ -1231,8 +1238,7 @@ mgfwa_status tune_plan(mgfwa_ctx *c, int rows, const float *W, OutMap map, int r
             if (e == hipSuccess)
                 e = c->input ? launch_net_input(c->in, cand[i].net_shape, c->d.Pnet, W, c->s.Dp, rows,
                                                 map, c->d.Yc, c->d.H0, c->d.H1, c->d.zero, c->stream)
-                             : launch_fitness(c->net, cand[i], c->d, W, c->s.Dp, rows, map, c->d.Yc,
-                                              c->stream);
+                             : launch_fitness(net, cand[i], dv, W, c->s.Dp, rows, map, res, c->stream);
         }
         if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -1590,7 +1596,11 @@ mgfwa_status mgfwa_autotune(mgfwa_ctx *c, int reps)
     mgfwa_status r = tune_plan(c, s.BN * expl_rows(s), c->d.SE, expl_map(s), reps, &c->plan_expl);
     if (r) return r;
     c->s.regen = sparks_regenerated(c) ? 1 : 0;   // the plan decides whether it can regenerate
-    return tune_plan(c, s.BN * s.G, c->d.SG, OutMap{s.G, s.C, s.lam}, reps, &c->plan_guide);
+    r = tune_plan(c, s.BN * s.G, c->d.SG, OutMap{s.G, s.C, s.lam}, reps, &c->plan_guide);
+    if (r || !s.recheck || c->net32.wide) return r;
+    // the FP32 re-check of the B*N winners (timed on the firework rows, whose
+    // FP32 fitness the initialisation computed with the same launch)
+    return tune_plan(c, s.BN, c->d.F, kFlat, reps, &c->plan_check, true);
 }
 
 mgfwa_status mgfwa_fit_plan(const mgfwa_ctx *c, int which, mgfwa_plan_info *info)

@@ -429,7 +429,30 @@ __device__ __forceinline__ void layer_h(const WView<BF, WL> &wv, const floatx4 (
 #pragma unroll
             for (int rb = 0; rb < RO; ++rb) out[p][rb] = zero4();
     }
-    if constexpr (!BF) {
+    if constexpr (!BF && !WL) {
+        // fragments from the spark row in global memory (L2): a ring of GD loads
+        // in flight in (kb, rb) order, so the multiplies of one fragment overlap
+        // the latency of the next GD - 1 (one load ahead left the kernel waiting
+        // on every fragment).  A fragment past the layer's columns is zero and
+        // issues no load.
+        constexpr int T = RI * RO, GD = T < 8 ? T : 8;
+        const int nkb = (wv.fi + 15) >> 4 < RI ? (wv.fi + 15) >> 4 : RI;
+        floatx4 ring[GD];
+#pragma unroll
+        for (int t = 0; t < GD; ++t) ring[t] = wv.f32(t % RO, t / RO);
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const int kb = t / RO, rb = t % RO;
+            const floatx4 aw = ring[t % GD];
+            if (t + GD < T) ring[t % GD] = wv.f32((t + GD) % RO, (t + GD) / RO);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+                    out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                        aw[v], in[p][kb][v], ZA && kb == 0 && v == 0 ? zero4() : out[p][rb], 0, 0, 0);
+        }
+    } else if constexpr (!BF) {
         // fragments of (kb, rb) in order; the next one is fetched before the
         // current one's MFMAs so the LDS latency overlaps matrix work
         // staged weights are zero-padded to RI blocks: no early exit needed

@@ -1,4 +1,5 @@
-// Fitness kernel instances: three layers, hidden width up to 256, FP32.
+// Fitness kernel instances: three layers, hidden width up to 256, FP32, weights
+// read from global memory.
 #include "fit_kernel.h"
 
 namespace mgfwa {
@@ -8,6 +9,12 @@ namespace {
 const KernelEntry kEntries[] = {
     FIT_ENTRY(false, false, 4, 2, 16, 16, 1, 0),
     FIT_ENTRY(false, false, 4, 2, 16, 16, 4, 0),
+    // one slab per wavefront: narrower layers leave the registers for the
+    // activation tiles of both layers (192- and 224-wide hidden layers; the
+    // 256-wide instances above keep two slabs and spill a few tiles, which
+    // measured faster than one slab there)
+    FIT_ENTRY(false, false, 4, 1, 12, 12, 1, 0),
+    FIT_ENTRY(false, false, 4, 1, 14, 14, 1, 0),
 };
 }  // namespace
 

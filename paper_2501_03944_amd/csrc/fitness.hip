@@ -167,13 +167,16 @@ static bool entry_fits(const Net &net, const KernelEntry &e, double *cost)
 }
 
 // Blocks per spark row by default: enough blocks to fill the chip (about 4 per
-// CU) while keeping at least two slab groups per wavefront.
+// CU) while keeping at least two slab groups per wavefront.  A launch too small
+// to fill the chip even then (a few rows: the re-check of the winners, the
+// guiding sparks of a small job) takes one slab group per wavefront, since its
+// duration is the chain of passes a block runs one after another.
 static int default_bpr(const Net &net, const KernelEntry &e, int rows)
 {
     const int group = e.nw * 16 * e.P;                    // samples per block pass
     const int max_bpr = (net.S_pad + group - 1) / group;
     int bpr = (1024 + rows - 1) / (rows > 0 ? rows : 1);
-    const int lim = max_bpr / 2 > 0 ? max_bpr / 2 : 1;
+    const int lim = (long)rows * max_bpr <= 1024 ? max_bpr : max_bpr / 2 > 0 ? max_bpr / 2 : 1;
     if (bpr > lim) bpr = lim;
     if (bpr > MAX_BPR) bpr = MAX_BPR;
     return bpr < 1 ? 1 : bpr;

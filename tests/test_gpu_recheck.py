@@ -22,11 +22,16 @@ pytestmark = pytest.mark.gpu
 REGISTER, WIDE = 1, 2   # fit_path: register-chain kernels, K-streamed wide-first-layer kernel
 
 CASES = [
-    # (problem, fit_path, fireworks, sparks, guiding)
-    ("teacher", REGISTER, 4, 16, 2),
-    ("mlp-ce", REGISTER, 3, 16, 2),
-    ("wide-ce", WIDE, 3, 16, 2),
-    ("wide-mse", WIDE, 2, 24, 3),
+    # (problem, fit_path, fireworks, sparks, guiding, autotuned)
+    ("teacher", REGISTER, 4, 16, 2, False),
+    ("mlp-ce", REGISTER, 3, 16, 2, False),
+    ("mlp-ce", REGISTER, 3, 16, 2, True),
+    # FP32 hidden layers too wide for the LDS: the re-check reads the weights
+    # from global memory (the tuner picks among those kernels)
+    ("deep-ce", REGISTER, 3, 16, 2, False),
+    ("deep-ce", REGISTER, 3, 16, 2, True),
+    ("wide-ce", WIDE, 3, 16, 2, False),
+    ("wide-mse", WIDE, 2, 24, 3, False),
 ]
 
 
@@ -35,6 +40,9 @@ def _problem(name):
         return inputs.teacher_regression(n_samples=192)
     if name == "mlp-ce":
         return inputs.random_mlp_problem((24, 48, 10), ("relu",), "ce", 400, seed=21)
+    if name == "deep-ce":
+        return inputs.random_mlp_problem((16, 176, 176, 10), ("relu", "relu"), "ce", 300, seed=17,
+                                         x_scale=0.5)
     if name == "wide-ce":
         return inputs.random_mlp_problem((40, 64, 5), ("relu",), "ce", 300, seed=11)
     return inputs.random_mlp_problem((33, 48, 3), ("tanh",), "mse", 260, seed=13)
@@ -47,8 +55,8 @@ def _near(a, b, rel=2e-5):
     return abs(a - b) <= rel * max(abs(a), abs(b))
 
 
-@pytest.mark.parametrize("name,path,N,lam,G", CASES)
-def test_bf16_selection_rechecked_in_fp32(name, path, N, lam, G):
+@pytest.mark.parametrize("name,path,N,lam,G,tune", CASES)
+def test_bf16_selection_rechecked_in_fp32(name, path, N, lam, G, tune):
     torch, M = require_gpu()
     wl = _problem(name)
     p = O.Problem.from_workload(wl)
@@ -56,6 +64,8 @@ def test_bf16_selection_rechecked_in_fp32(name, path, N, lam, G):
     g = M.MGFWA(wl.widths, wl.acts, wl.loss, wl.x, wl.y, wl.labels, n_fireworks=N,
                 n_sparks=lam, n_guiding=G, seed=3, precision="bf16", max_generations=T,
                 fit_path=path)
+    if tune:
+        g.autotune(2)
     cfg = O.make_config(N=N, lam=lam, G=G, seed=3, T=T)
     D = g.D
     st = g.state_numpy()
