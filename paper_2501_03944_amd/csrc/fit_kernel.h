@@ -434,7 +434,8 @@ __device__ __forceinline__ void layer_h(const WView<BF, WL> &wv, const floatx4 (
         // in flight in (kb, rb) order, so the multiplies of one fragment overlap
         // the latency of the next GD - 1 (one load ahead left the kernel waiting
         // on every fragment).  A fragment past the layer's columns is zero and
-        // issues no load.
+        // issues no load; K blocks past them are skipped (a predicate, not an
+        // early exit, so that the loop stays fully unrolled).
         constexpr int T = RI * RO, GD = T < 8 ? T : 8;
         const int nkb = (wv.fi + 15) >> 4 < RI ? (wv.fi + 15) >> 4 : RI;
         floatx4 ring[GD];
@@ -445,12 +446,15 @@ __device__ __forceinline__ void layer_h(const WView<BF, WL> &wv, const floatx4 (
             const int kb = t / RO, rb = t % RO;
             const floatx4 aw = ring[t % GD];
             if (t + GD < T) ring[t % GD] = wv.f32((t + GD) % RO, (t + GD) / RO);
+            if (kb < nkb) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
+                for (int v = 0; v < 4; ++v)
 #pragma unroll
-                for (int p = 0; p < P; ++p)
-                    out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                        aw[v], in[p][kb][v], ZA && kb == 0 && v == 0 ? zero4() : out[p][rb], 0, 0, 0);
+                    for (int p = 0; p < P; ++p)
+                        out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            aw[v], in[p][kb][v], ZA && kb == 0 && v == 0 ? zero4() : out[p][rb], 0,
+                            0, 0);
+            }
         }
     } else if constexpr (!BF) {
         // fragments of (kb, rb) in order; the next one is fetched before the
