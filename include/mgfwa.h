@@ -358,7 +358,9 @@ MGFWA_API const char *mgfwa_version(void);
 
 /* The fitness launch shape of a context (the fitness step of Alg. 1 as a grouped
  * GEMM): which = 0 explosion sparks (with lag_guiding: the explosion and the
- * guiding sparks, one launch), 1 guiding sparks (unused with lag_guiding). */
+ * guiding sparks, one launch), 1 guiding sparks (unused with lag_guiding), 2 the
+ * FP32 re-check of each firework's best candidate in a run with BF16 built-in
+ * fitness (B*N rows; ESTATE for other contexts).  EINVAL for other values. */
 typedef struct {
     int wide;               /* 1: the K-streamed wide-first-layer kernel (fixed tiles) */
     int rows;               /* sparks per launch */
@@ -378,7 +380,8 @@ typedef struct {
 MGFWA_API mgfwa_status mgfwa_fit_plan(const mgfwa_ctx *ctx, int which, mgfwa_plan_info *info);
 
 /*
- * Autotune the fitness launches of a context: every compiled kernel variant that
+ * Autotune the fitness launches of a context (which = 0, 1 and, with BF16
+ * fitness, 2 of mgfwa_plan_info): every compiled kernel variant that
  * covers the MLP shape, with a few sample splits, is timed on the device (reps
  * launches each, on the context's stream, over its own spark buffers) and the
  * fastest is kept.  The choice is cached for the process per (shape, precision,

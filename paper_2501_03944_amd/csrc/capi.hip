@@ -1178,19 +1178,42 @@ int tune_candidates(const mgfwa_ctx *c, int rows, FitPlan *cand, int max_out)
     return n;
 }
 
-// Sparks per launch of fitness launch `which` (0 explosion, 1 guiding sparks).
+// Sparks per launch of fitness launch `which` (0 explosion, 1 guiding sparks,
+// 2 the FP32 re-check of a BF16 run's winners).
 int launch_rows(const mgfwa_ctx *c, int which)
 {
-    return which == 0 ? c->s.BN * expl_rows(c->s) : c->s.BN * c->s.G;
+    return which == 0 ? c->s.BN * expl_rows(c->s) : which == 1 ? c->s.BN * c->s.G : c->s.BN;
 }
 
-void fill_plan_info(const mgfwa_ctx *c, const FitPlan &p, int rows, mgfwa_plan_info *info)
+// The network (precision) and the plan of fitness launch `which`.
+const Net &launch_net(const mgfwa_ctx *c, int which) { return which == 2 ? c->net32 : c->net; }
+FitPlan &launch_plan(mgfwa_ctx *c, int which)
 {
+    return which == 0 ? c->plan_expl : which == 1 ? c->plan_guide : c->plan_check;
+}
+const FitPlan &launch_plan(const mgfwa_ctx *c, int which)
+{
+    return launch_plan(const_cast<mgfwa_ctx *>(c), which);
+}
+
+// `which` names a fitness launch the context has (EINVAL / ESTATE otherwise).
+mgfwa_status check_which(const mgfwa_ctx *c, int which)
+{
+    if (which < 0 || which > 2) return fail(MGFWA_EINVAL, "which must be 0, 1 or 2");
+    if (which == 2 && !c->s.recheck)
+        return fail(MGFWA_ESTATE, "no re-check launch: the context has no BF16 built-in fitness");
+    return MGFWA_OK;
+}
+
+void fill_plan_info(const mgfwa_ctx *c, const FitPlan &p, int rows, mgfwa_plan_info *info,
+                    int which = 0)
+{
+    const Net &net = launch_net(c, which);
     std::memset(info, 0, sizeof *info);
-    info->wide = c->net.wide ? 1 : 0;
+    info->wide = net.wide ? 1 : 0;
     info->rows = rows;
     info->net_kernel = c->input ? p.net_shape : -1;
-    if (!c->net.wide && !c->input) {
+    if (!net.wide && !c->input) {
         info->wavefronts = p.nw;
         info->slabs = p.P;
         info->lds_weights = p.wl;
@@ -1346,10 +1369,7 @@ JobDesc job_desc(const mgfwa_ctx *c)
     return j;
 }
 
-const FitPlan &job_plan(const mgfwa_ctx *c, int which)
-{
-    return which == 0 ? c->plan_expl : which == 1 ? c->plan_guide : c->plan_check;
-}
+const FitPlan &job_plan(const mgfwa_ctx *c, int which) { return launch_plan(c, which); }
 
 // Sparks of fitness launch `which` of a grouped job (as in job_desc).
 int job_fit_rows(const mgfwa_ctx *c, int which)
@@ -1606,8 +1626,10 @@ mgfwa_status mgfwa_autotune(mgfwa_ctx *c, int reps)
 mgfwa_status mgfwa_fit_plan(const mgfwa_ctx *c, int which, mgfwa_plan_info *info)
 {
     if (!c || !info) return fail(MGFWA_EINVAL, "NULL argument");
-    if (which < 0 || which > 1) return fail(MGFWA_EINVAL, "which must be 0 or 1");
-    fill_plan_info(c, which == 0 ? c->plan_expl : c->plan_guide, launch_rows(c, which), info);
+    mgfwa_status r = check_which(c, which);
+    if (r) return r;
+    fill_plan_info(c, launch_plan(c, which), launch_rows(c, which), info,
+                   which);
     return MGFWA_OK;
 }
 
@@ -1615,14 +1637,18 @@ mgfwa_status mgfwa_fit_candidates(const mgfwa_ctx *c, int which, mgfwa_plan_info
                                   int *n)
 {
     if (!c || !n) return fail(MGFWA_EINVAL, "NULL argument");
-    if (which < 0 || which > 1) return fail(MGFWA_EINVAL, "which must be 0 or 1");
     if (max_out < 0 || (max_out > 0 && !out)) return fail(MGFWA_EINVAL, "bad output buffer");
     if (!c->has_data) return fail(MGFWA_ESTATE, "no built-in fitness: no fitness launches");
+    mgfwa_status r = check_which(c, which);
+    if (r) return r;
     const int rows = launch_rows(c, which);
+    const Net &net = launch_net(c, which);
     FitPlan cand[MAX_CANDIDATES];
-    const int nc = c->net.wide ? 1 : tune_candidates(c, rows, cand, MAX_CANDIDATES);
-    if (c->net.wide) cand[0] = which == 0 ? c->plan_expl : c->plan_guide;
-    for (int i = 0; i < nc && i < max_out; ++i) fill_plan_info(c, cand[i], rows, &out[i]);
+    const int nc = net.wide ? 1
+                   : which == 2 ? fit_candidates(net, rows, cand, MAX_CANDIDATES)
+                                : tune_candidates(c, rows, cand, MAX_CANDIDATES);
+    if (net.wide) cand[0] = launch_plan(c, which);
+    for (int i = 0; i < nc && i < max_out; ++i) fill_plan_info(c, cand[i], rows, &out[i], which);
     *n = nc;
     return MGFWA_OK;
 }
@@ -1630,19 +1656,23 @@ mgfwa_status mgfwa_fit_candidates(const mgfwa_ctx *c, int which, mgfwa_plan_info
 mgfwa_status mgfwa_set_fit_plan(mgfwa_ctx *c, int which, int index)
 {
     if (!c) return fail(MGFWA_EINVAL, "ctx is NULL");
-    if (which < 0 || which > 1) return fail(MGFWA_EINVAL, "which must be 0 or 1");
     if (c->cfg.external_fitness || !c->has_data)
         return fail(MGFWA_ESTATE, "forcing a plan needs the built-in fitness");
+    mgfwa_status r = check_which(c, which);
+    if (r) return r;
     if (c->phase != PH_READY || c->gen_host != 0 || c->gexec)
         return fail(MGFWA_ESTATE, "set the fitness plan before the first generation");
     const int rows = launch_rows(c, which);
+    const Net &net = launch_net(c, which);
     FitPlan cand[MAX_CANDIDATES];
-    const int nc = c->net.wide ? 1 : tune_candidates(c, rows, cand, MAX_CANDIDATES);
+    const int nc = net.wide ? 1
+                   : which == 2 ? fit_candidates(net, rows, cand, MAX_CANDIDATES)
+                                : tune_candidates(c, rows, cand, MAX_CANDIDATES);
     if (index < 0 || index >= nc)
         return fail(MGFWA_EINVAL, "plan index %d outside [0, %d)", index, nc);
-    if (c->net.wide) return MGFWA_OK;   // one fixed tile shape
+    if (net.wide) return MGFWA_OK;   // one fixed tile shape
     HIP_TRY(fit_prepare(cand[index]));
-    (which == 0 ? c->plan_expl : c->plan_guide) = cand[index];
+    launch_plan(c, which) = cand[index];
     c->s.regen = sparks_regenerated(c) ? 1 : 0;
     return MGFWA_OK;
 }

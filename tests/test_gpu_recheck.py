@@ -128,3 +128,55 @@ def test_recheck_time_reported_for_bf16_only():
             assert 0.0 < t["check_fit_ms"] <= t["phase_ms"]["selection"]
         else:
             assert t["check_fit_ms"] == 0.0
+
+
+def test_every_recheck_plan_matches_oracle():
+    """Each candidate plan of the FP32 re-check launch (plan index 2), forced
+    through mgfwa_set_fit_plan on a net whose re-check reads its weights from
+    global memory: over a few generations every firework fitness and best_y is
+    within the FP32 tolerance of the oracle's loss of its row, and some firework
+    moved (so re-checked values were used)."""
+    torch, M = require_gpu()
+    wl = _problem("deep-ce")
+    p = O.Problem.from_workload(wl)
+
+    def ctx(precision="bf16"):
+        return M.MGFWA(wl.widths, wl.acts, wl.loss, wl.x, wl.y, wl.labels, n_fireworks=3,
+                       n_sparks=16, n_guiding=2, seed=4, precision=precision, max_generations=20,
+                       fit_path=REGISTER)
+
+    g0 = ctx()
+    cands = g0.fit_candidates(2)
+    assert len(cands) >= 2 and all(c["rows"] == 3 for c in cands)
+    with pytest.raises(M.MgfwaError) as e:
+        g0.set_fit_plan(2, len(cands))
+    assert e.value.status == M.EINVAL
+    with pytest.raises(M.MgfwaError) as e:
+        g0.fit_plan(3)
+    assert e.value.status == M.EINVAL
+    g0.close()
+    g32 = ctx("fp32")
+    with pytest.raises(M.MgfwaError) as e:   # FP32 runs have no re-check launch
+        g32.fit_plan(2)
+    assert e.value.status == M.ESTATE
+    g32.close()
+    for i, plan in enumerate(cands):
+        g = ctx()
+        g.set_fit_plan(2, i)
+        assert g.fit_plan(2) == plan
+        moved = 0
+        for gen in range(6):
+            g.step(1)
+            st = g.state_numpy()
+            D = g.D
+            moved += int(st["improved"].sum())
+            keep = np.flatnonzero(st["reinit"] == 0)   # loser-out rows wait for their fitness
+            assert_fitness_close(st["Y"][keep],
+                                 p.loss_rows(st["F"][keep, :D].astype(np.float64)),
+                                 f"plan {i} generation {gen + 1} Y")
+            assert_fitness_close(st["best_y"],
+                                 p.loss_rows(st["best_x"][:, :D].astype(np.float64)),
+                                 f"plan {i} generation {gen + 1} best_y")
+        assert moved > 0, f"plan {i}: no firework moved"
+        g.close()
+    print(f"{len(cands)} re-check plans checked")
