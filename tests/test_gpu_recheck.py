@@ -146,6 +146,10 @@ def test_every_recheck_plan_matches_oracle():
                        fit_path=REGISTER)
 
     g0 = ctx()
+    # before tuning, a launch of 3 rows (far too few to fill the chip) takes one
+    # slab group per wavefront: as many blocks per row as the samples allow
+    info = g0.fit_plan(2)
+    assert info["samples_per_block"] == info["wavefronts"] * 16 * info["slabs"], info
     cands = g0.fit_candidates(2)
     assert len(cands) >= 2 and all(c["rows"] == 3 for c in cands)
     with pytest.raises(M.MgfwaError) as e:
