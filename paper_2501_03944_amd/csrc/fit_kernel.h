@@ -205,11 +205,20 @@ struct WView {
             const uint2 hi = *reinterpret_cast<const uint2 *>(p + 32);
             return __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
         } else {
-            const bool ok = 16 * rb + n < fo;
-            const float *p = gp + (size_t)(ok ? 16 * rb : 0) * fi + 32 * kb;
-            return to_bf16x8(ldw4(p, ok, 32 * kb + 4 * gq, fi, vec),
-                             ldw4(p + 16, ok, 32 * kb + 16 + 4 * gq, fi, vec));
+            floatx4 lo, hi;
+            b16_raw(rb, kb, lo, hi);
+            return to_bf16x8(lo, hi);
         }
+    }
+
+    // The FP32 weights of a BF16 fragment from global memory (WL = false),
+    // converted where they are used: lo = k 32kb + 4g.., hi = k 32kb + 16 + 4g..
+    __device__ __forceinline__ void b16_raw(int rb, int kb, floatx4 &lo, floatx4 &hi) const
+    {
+        const bool ok = 16 * rb + n < fo;
+        const float *p = gp + (size_t)(ok ? 16 * rb : 0) * fi + 32 * kb;
+        lo = ldw4(p, ok, 32 * kb + 4 * gq, fi, vec);
+        hi = ldw4(p + 16, ok, 32 * kb + 16 + 4 * gq, fi, vec);
     }
 };
 
@@ -478,6 +487,40 @@ __device__ __forceinline__ void layer_h(const WView<BF, WL> &wv, const floatx4 (
                         out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
                             aw[v], in[p][kb][v], ZA && kb == 0 && v == 0 ? zero4() : out[p][rb], 0, 0, 0);
                 aw = an;
+            }
+        }
+    } else if constexpr (!WL && RI <= 8) {
+        // BF16 with fragments from global memory, input layer up to 128 wide: a
+        // ring of GD fragment loads in flight (their FP32 weights, converted at
+        // use), as in the FP32 case.  (With 256-wide input layers the ring's
+        // registers add spills and it measured slower: 0.85 -> 1.39 ms at
+        // 32-240-240-10, against 0.41 -> 0.34 ms at 32-128-128-128-10.)
+        constexpr int NKB = (RI + 1) / 2, T = NKB * RO, GD = T < 4 ? T : 4;
+        const int nkb = (wv.fi + 31) >> 5 < NKB ? (wv.fi + 31) >> 5 : NKB;
+        floatx4 rlo[GD], rhi[GD];
+#pragma unroll
+        for (int t = 0; t < GD; ++t) wv.b16_raw(t % RO, t / RO, rlo[t], rhi[t]);
+        bf16x8 bx[P];
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const int kb = t / RO, rb = t % RO;
+            if (rb == 0 && kb < nkb) {
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    floatx4 hi = zero4();
+                    if (2 * kb + 1 < RI) hi = in[p][(2 * kb + 1) < RI ? 2 * kb + 1 : 0];
+                    if constexpr (FOLD) bx[p] = relu_to_bf16x8(in[p][2 * kb], hi);
+                    else bx[p] = to_bf16x8(in[p][2 * kb], hi);
+                }
+            }
+            const bf16x8 aw = to_bf16x8(rlo[t % GD], rhi[t % GD]);
+            if (t + GD < T) wv.b16_raw((t + GD) % RO, (t + GD) / RO, rlo[t % GD], rhi[t % GD]);
+            if (kb < nkb) {
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+                    out[p][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        aw, bx[p], ZA && kb == 0 ? (FOLD ? c0[rb] : zero4()) : out[p][rb], 0, 0,
+                        0);
             }
         }
     } else {
