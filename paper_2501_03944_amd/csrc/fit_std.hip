@@ -12,10 +12,14 @@ const KernelEntry kEntries[] = {
     FIT_ENTRY_ACT(false, true, 2, 2, 2, 1, 1, 0, 0),
     FIT_ENTRY_ACT(false, true, 4, 4, 2, 1, 1, 0, 0),
     FIT_ENTRY_ACT(true, true, 4, 4, 2, 2, 1, 0, 0),
-    // 64-128-128-10 ReLU: weights in LDS.  Measured best: FP32 with 8
-    // wavefronts x 2 slabs and fragments fetched right before use; BF16 with
-    // 4 wavefronts x 4 slabs (more A-fragment reuse per LDS read); both with
-    // zero-addend first K blocks (SCHED bit 1)
+    // 64-128-128-10 ReLU: weights in LDS.  Measured best: FP32 with 16
+    // wavefronts x 1 slab (four per SIMD: one wavefront's waits are covered by
+    // the others' multiplies), each fragment fetched one row block ahead
+    // (SCHED 1): 0.794 -> 0.824 of the FP32 peak against the next entry, 8 x 2
+    // with fragments fetched right before use and zero-addend first K blocks
+    // (SCHED 2), which the tuner still tries.  BF16: 4 wavefronts x 4 slabs
+    // (more A-fragment reuse per LDS read) with both options (SCHED 3).
+    FIT_ENTRY_SCHED(false, true, 16, 1, 1, 1, 8, 8, 1, 0),
     FIT_ENTRY_SCHED(false, true, 8, 2, 1, 2, 8, 8, 1, 0),
     FIT_ENTRY_SCHED(true, true, 4, 4, 1, 3, 8, 8, 1, 0),
     // 784-256-10 ReLU: the first layer does not fit in LDS
