@@ -17,11 +17,11 @@ const KernelEntry kEntries[] = {
     // the others' multiplies), each fragment fetched one row block ahead
     // (SCHED 1): 0.794 -> 0.824 of the FP32 peak against the next entry, 8 x 2
     // with fragments fetched right before use and zero-addend first K blocks
-    // (SCHED 2), which the tuner still tries.  BF16: 4 wavefronts x 4 slabs
-    // (more A-fragment reuse per LDS read) with both options (SCHED 3).
+    // (SCHED 2), which the tuner still tries.  (BF16 takes the LDS-staged
+    // 4 x 2 instance of the batched-job table: 0.60 ms per explosion-fitness
+    // launch, against 0.84 ms for 4 x 4 and 0.87 ms for 16 x 1.)
     FIT_ENTRY_SCHED(false, true, 16, 1, 1, 1, 8, 8, 1, 0),
     FIT_ENTRY_SCHED(false, true, 8, 2, 1, 2, 8, 8, 1, 0),
-    FIT_ENTRY_SCHED(true, true, 4, 4, 1, 3, 8, 8, 1, 0),
     // 784-256-10 ReLU: the first layer does not fit in LDS
     FIT_ENTRY_ACT(false, false, 4, 2, 1, 16, 1, 0, 0),
     FIT_ENTRY_ACT(true, false, 4, 2, 1, 16, 1, 0, 0),
